@@ -1,0 +1,75 @@
+"""Input generators and the CSR builder (host only)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+
+def test_c1_shape():
+    g = gg.workload_c1()
+    s = g.stats()
+    assert s["N"] == 10000 and s["E"] == 80000 and s["dangling"] >= 500
+    src, dst = g.edges()
+    assert not np.any(src == dst)
+    assert len(set(zip(src.tolist(), dst.tolist()))) == 80000
+
+
+def test_deterministic_and_thread_independent(monkeypatch):
+    a = gg.rmat(14, seed=3)
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    b = gg.rmat(14, seed=3)
+    assert np.array_equal(a.off, b.off) and np.array_equal(a.idx, b.idx)
+    c = gg.rmat(14, seed=4)
+    assert not np.array_equal(a.idx[:1000], c.idx[:1000])
+
+
+def test_csr_invariants():
+    g = gg.rmat(13, seed=2)
+    assert g.off[0] == 0 and np.all(np.diff(g.off) >= 0) and g.off[-1] == g.E
+    for v in range(0, g.N, 97):
+        row = g.idx[g.off[v]:g.off[v + 1]]
+        assert np.all(np.diff(row) > 0)  # sorted, no duplicates
+        assert not np.any(row == v)
+    assert np.array_equal(np.bincount(g.idx, minlength=g.N), g.outdeg)
+
+
+def test_rmat_skew_and_dangling():
+    g = gg.rmat(16, seed=1)
+    s = g.stats()
+    assert 0.88 < s["E"] / (16 * 65536) < 0.95
+    assert 0.3 < s["dangling"] / s["N"] < 0.5
+    assert s["max_indeg"] > 2000
+
+
+def test_non_power_of_two_rmat():
+    g = gg.rmat(N=3000, edge_factor=8, seed=7)
+    assert g.N == 3000 and g.idx.max() < 3000
+
+
+def test_multigraph_kept_when_asked():
+    g = gg.from_edges(3, [0, 0, 1, 2, 2], [1, 1, 1, 0, 0], dedupe=False, drop_self_loops=False)
+    assert list(g.off) == [0, 2, 5, 5] and list(g.outdeg) == [2, 1, 2]
+
+
+def test_relabel_roundtrip():
+    g = gg.rmat(10, seed=1)
+    p = gg.permutation(g.N, 5)
+    h = gg.relabel(g, p)
+    assert h.E == g.E and np.array_equal(np.sort(h.outdeg), np.sort(g.outdeg))
+    assert np.array_equal(h.outdeg[p], g.outdeg)
+
+
+def test_bad_ids_rejected():
+    with pytest.raises(ValueError):
+        gg.from_edges(3, [0, 5], [1, 1])
+
+
+def test_specs_cover_the_ranges():
+    specs = gg.many_graph_specs()
+    assert len(specs) == 64
+    Ns = [s["N"] for s in specs]
+    assert min(Ns) >= 1000 and max(Ns) <= 1000000
+    assert {s["alpha"] for s in specs} == {0.75, 0.85, 0.95}
+    assert {s["norm"] for s in specs} == {1, 2, 3}
+    assert gg.ALPHA_SWEEP[0] == 0.5 and gg.ALPHA_SWEEP[7] == 0.85 and gg.ALPHA_SWEEP[-1] == 1.0
+    assert len(gg.tau_sweep_21()) == 21
