@@ -1,0 +1,141 @@
+/*
+ * prpull.h -- C ABI of the MI355X (gfx950) pull-PageRank library, libprpull.so.
+ *
+ * The library computes the standard power-iteration (pull) PageRank of Sahu, Kothapalli and
+ * Banerjee, "Adjusting PageRank parameters and Comparing results" (arXiv 2108.02997):
+ *
+ *   section 2, rank update:  r'_v = c0 + alpha * sum over v's in-edges (u -> v) of r_u / d_u,
+ *                             every term taken from the previous iterate;
+ *   section 2, teleport:      c0 = (1 - alpha)/N + alpha * (sum of r over dangling vertices)/N,
+ *                             a dangling vertex being one with no out-edges;
+ *   section 3, convergence:   stop once the L1, L2 or L-infinity norm of r' - r falls strictly
+ *                             below the tolerance tau;
+ *   section 2, iteration cap: at most max_iter updates (the paper uses 500), after which the
+ *                             last iterate is returned as not converged.
+ * The start vector is uniform 1/N unless the caller passes one (the paper does not state it).
+ *
+ * Conventions for every entry point
+ *   - All array arguments are device pointers (memory on the context's GPU) unless marked
+ *     "host".  The caller owns every buffer, including the workspace; the library allocates no
+ *     device memory in pr_pull, pr_pull_batch or the warm-start calls.  A context owns only
+ *     host-side caches (captured HIP graphs, pinned status words) and frees them in pr_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     stream-ordered; calls that fill a host result synchronise the stream before returning.
+ *   - Graph layout ("in-edge CSR"): in_offsets[N+1] int32, non-decreasing, in_offsets[0] = 0,
+ *     in_offsets[N] = E; in_indices[E] int32, entry j of row v is the source u of an edge
+ *     u -> v; outdeg[N] int32 = number of CSR entries naming u.  Repeated entries and
+ *     self-loops are allowed and counted as edges.  0 <= E < 2^31.  Structure is checked only
+ *     by pr_validate_graph.
+ *   - Rank and trace arrays are float64.  A norm trace holds max_iter rows of (L1, L2, Linf),
+ *     one row per update performed; rows past the last update are left untouched.
+ *   - Return value: PR_OK (0) or PR_NOT_CONVERGED (1) when outputs are valid, a negative
+ *     status when they are undefined; pr_last_error() then describes the failure (text owned
+ *     by the library, valid until the next call on the same host thread).
+ *   - One context per host thread; calls that overlap on one context are not supported.
+ */
+#ifndef PRPULL_H
+#define PRPULL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pr_ctx pr_ctx;
+
+/* Error functions of section 3. */
+enum { PR_L1 = 1, PR_L2 = 2, PR_LINF = 3 };
+
+/* Arithmetic of the solve.
+ * PR_FP64:  contributions, gather, ranks, reductions all in float64.
+ * PR_MIXED: a float32 phase (float32 contributions and gather with float32 accumulation;
+ *           dangling sum, teleport term and norms in float64) runs until it meets tau or its L1
+ *           change stops decreasing; then float64 iterations continue from the float32 iterate
+ *           until a float64 update meets tau.  The convergence decision is always taken on a
+ *           float64 update. */
+enum { PR_FP64 = 0, PR_MIXED = 1 };
+
+enum {
+  PR_OK = 0,
+  PR_NOT_CONVERGED = 1, /* max_iter updates done without meeting tau; ranks hold the last iterate */
+  PR_EINVAL = -1,       /* bad scalar argument, NULL where a buffer is required, size mismatch */
+  PR_ENOMEM = -2,       /* workspace or prep buffer smaller than required */
+  PR_EDEVICE = -3,      /* a HIP call failed */
+  PR_EGRAPH = -4        /* pr_validate_graph found a malformed CSR */
+};
+
+typedef struct {
+  int32_t iterations; /* updates performed, including the one that met tau (1..max_iter) */
+  int32_t converged;  /* 1 if an update met tau (always a float64 update) */
+  int32_t fp32_iters; /* updates of the float32 phase (PR_MIXED), else 0 */
+  int32_t fp64_iters; /* float64 updates */
+  double final_err[3]; /* L1, L2, Linf of r' - r at the last update */
+} pr_result;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device`.  Returns PR_OK or PR_EDEVICE. */
+int pr_create(pr_ctx **out, int device);
+/* Destroy a context (NULL allowed).  Waits for nothing; the caller synchronises its streams. */
+void pr_destroy(pr_ctx *ctx);
+/* Description of the last negative status on this host thread ("" if none). */
+const char *pr_last_error(void);
+/* Library version string. */
+const char *pr_version(void);
+
+/* Tunables of a context (read by later solves):
+ *   "grid"  : maximum number of workgroups of an update launch, 1..4096 (default 2048)
+ *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 8)
+ *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
+ * Returns PR_OK or PR_EINVAL for an unknown key or a value out of range. */
+int pr_set_option(pr_ctx *ctx, const char *key, int64_t value);
+
+/* --------------------------------------------------------------- graph prep (once per graph) */
+
+/* Bytes of the prep buffer for a graph with N vertices and E CSR entries (an upper bound). */
+size_t pr_prep_bytes(int64_t N, int64_t E);
+
+/* Partition the rows of the in-edge CSR into work tiles by in-degree: runs of consecutive
+ * low/mid in-degree rows holding about one LDS tile of entries, and high in-degree rows split
+ * into fixed-size segments.  Reads only in_offsets.  Writes `prep` (device, caller-owned,
+ * prep_bytes >= pr_prep_bytes(N, E)); synchronises `stream` once to read the tile count.
+ * The result depends only on in_offsets and may be reused by every later solve on the graph. */
+int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, int64_t E, void *prep,
+               size_t prep_bytes);
+
+/* Structural check of a CSR (debugging/tests; O(N + E)): offsets monotone with off[0] = 0 and
+ * off[N] = E, every index in [0, N), and outdeg[u] equal to u's number of CSR entries.
+ * Needs a device workspace of at least 4*N + 256 bytes.  Returns PR_OK or PR_EGRAPH. */
+int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                      const int32_t *outdeg, int64_t N, int64_t E, void *workspace, size_t workspace_bytes);
+
+/* ------------------------------------------------------------------ single solve */
+
+/* Device workspace bytes needed by pr_pull (prep == NULL adds room to prepare inside it). */
+size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep);
+
+/* One PageRank solve (sections 2 and 3).
+ *   in_offsets/in_indices/outdeg : the graph, device, N+1 / E / N entries
+ *   prep      : pr_prepare output for this graph, or NULL to prepare inside the workspace
+ *   alpha     : damping factor in [0, 1] (alpha = 1 is allowed: c0 = dangling sum / N)
+ *   tau       : tolerance >= 0 (tau = 0 never converges; the solve then runs max_iter updates)
+ *   norm      : PR_L1, PR_L2 or PR_LINF
+ *   max_iter  : >= 1
+ *   precision : PR_FP64 or PR_MIXED
+ *   init      : device, N values, the start vector (any non-negative vector), or NULL for 1/N
+ *   ranks     : device, N values, out: the newest iterate (may alias init)
+ *   norm_trace: device, max_iter x 3 values, or NULL
+ *   workspace : device, workspace_bytes >= pr_workspace_bytes(N, E, precision, prep == NULL)
+ *   out       : host, filled after the stream is synchronised
+ * Returns PR_OK, PR_NOT_CONVERGED, or a negative status. */
+int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+            const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double alpha, double tau,
+            int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
+            double *norm_trace, void *workspace, size_t workspace_bytes, pr_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRPULL_H */

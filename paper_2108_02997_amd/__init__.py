@@ -1,0 +1,139 @@
+"""MI355X (gfx950) pull PageRank: Python front end of libprpull.so.
+
+The solver computes the standard power-iteration pull PageRank of Sahu, Kothapalli and
+Banerjee (arXiv 2108.02997, section 2 update and teleport term, section 3 error functions)
+in hand-written HIP kernels behind a C ABI (include/prpull.h).  This module only moves
+arguments: graphs and vectors are torch tensors on the GPU, the stream is torch's current
+stream, and every step of a solve runs in the library.  There is no CPU path: without a GPU
+or without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import (PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK, PrError,  # noqa: F401
+                   pr_result)
+
+__all__ = ["Context", "DeviceGraph", "pull", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2108_02997_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+
+
+class Context:
+    """A pr_ctx bound to one device (host-side caches only)."""
+
+    def __init__(self, device: int = 0):
+        _require_gpu()
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            _lib.check("pr_create", self.lib.pr_create(ctypes.byref(h), device))
+        self.handle = h
+
+    def set_option(self, key: str, value: int):
+        _lib.check("pr_set_option", self.lib.pr_set_option(self.handle, key.encode(), int(value)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self) -> int:
+        return _lib.stream_handle(self.device)
+
+
+@dataclass
+class DeviceGraph:
+    """In-edge CSR on the device (int32 off[N+1], idx[E], outdeg[N]) plus its tile partition."""
+
+    N: int
+    E: int
+    off: torch.Tensor
+    idx: torch.Tensor
+    outdeg: torch.Tensor
+    prep: torch.Tensor | None = None
+    _ws: dict = field(default_factory=dict)
+
+    @classmethod
+    def from_host(cls, g, device: int = 0):
+        dev = torch.device("cuda", device)
+        off = torch.from_numpy(g.off).to(dev)
+        idx = torch.from_numpy(g.idx if g.E > 0 else g.idx[:0]).to(dev)
+        outdeg = torch.from_numpy(g.outdeg).to(dev)
+        return cls(g.N, g.E, off, idx, outdeg)
+
+    def prepare(self, ctx: Context):
+        """pr_prepare: tile partition of this graph (kept on the object)."""
+        nbytes = ctx.lib.pr_prep_bytes(self.N, self.E)
+        self.prep = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)
+        _lib.check("pr_prepare", ctx.lib.pr_prepare(ctx.handle, ctx.stream, self.off.data_ptr(), self.N, self.E,
+                                                    self.prep.data_ptr(), nbytes))
+        return self
+
+    def workspace(self, ctx: Context, precision: int, with_prep: bool) -> torch.Tensor:
+        key = (precision, with_prep)
+        ws = self._ws.get(key)
+        if ws is None:
+            nbytes = ctx.lib.pr_workspace_bytes(self.N, self.E, precision, int(with_prep))
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)
+            self._ws[key] = ws
+        return ws
+
+    def validate(self, ctx: Context) -> None:
+        nbytes = 4 * self.N + 512
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)
+        _lib.check("pr_validate_graph", ctx.lib.pr_validate_graph(
+            ctx.handle, ctx.stream, self.off.data_ptr(), _lib.ptr(self.idx) if self.E else None,
+            self.outdeg.data_ptr(), self.N, self.E, ws.data_ptr(), nbytes))
+
+
+def pr_pull(ctx: Context, g: DeviceGraph, alpha: float, tau: float, norm: int, max_iter: int, precision: int,
+            init: torch.Tensor | None, ranks: torch.Tensor, norm_trace: torch.Tensor | None,
+            workspace: torch.Tensor, use_prep: bool = True) -> tuple[int, dict]:
+    """The C entry point pr_pull with tensors for device buffers; returns (status, result)."""
+    for t, n in ((ranks, g.N), (init, g.N)):
+        if t is not None and (t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous() or
+                              t.device != g.off.device):
+            raise ValueError("rank vectors must be contiguous float64 tensors of N elements on the graph's device")
+    if norm_trace is not None and (norm_trace.dtype != torch.float64 or norm_trace.numel() < 3 * max_iter):
+        raise ValueError("norm_trace must be float64 with max_iter*3 elements")
+    res = pr_result()
+    prep = g.prep if use_prep else None
+    st = ctx.lib.pr_pull(ctx.handle, ctx.stream, g.off.data_ptr(), _lib.ptr(g.idx) if g.E else None,
+                         g.outdeg.data_ptr(), g.N, g.E, _lib.ptr(prep), float(alpha), float(tau), int(norm),
+                         int(max_iter), int(precision), _lib.ptr(init), ranks.data_ptr(), _lib.ptr(norm_trace),
+                         workspace.data_ptr(), workspace.numel(), ctypes.byref(res))
+    _lib.check("pr_pull", st)
+    return st, res.as_dict()
+
+
+def pull(ctx: Context, g: DeviceGraph, alpha: float = 0.85, tau: float = 1e-6, norm: int = PR_L1,
+         max_iter: int = 500, precision: int = PR_FP64, init: torch.Tensor | None = None, trace: bool = False,
+         ranks: torch.Tensor | None = None) -> dict:
+    """Solve one PageRank problem; returns dict(ranks, iterations, converged, fp32_iters, fp64_iters, err, trace)."""
+    if g.prep is None:
+        g.prepare(ctx)
+    if ranks is None:
+        ranks = torch.empty(g.N, dtype=torch.float64, device=g.off.device)
+    tr = torch.full((max_iter, 3), float("nan"), dtype=torch.float64, device=g.off.device) if trace else None
+    ws = g.workspace(ctx, precision, False)
+    st, res = pr_pull(ctx, g, alpha, tau, norm, max_iter, precision, init, ranks, tr, ws)
+    res["status"] = st
+    res["ranks"] = ranks
+    res["trace"] = tr[:res["iterations"]] if trace else None
+    return res

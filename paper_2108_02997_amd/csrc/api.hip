@@ -1,0 +1,521 @@
+// api.hip -- the C ABI of libprpull.so (declared in include/prpull.h): argument checks,
+// workspace carving, graph prep caching and the on-device-convergence iteration loop.
+//
+// The loop: updates are launched in chunks of `chunk` kernels, alternating the two iterate
+// buffers.  A chunk is captured once into a HIP graph (on a private capture stream) and
+// replayed on the caller's stream; once an update meets the stopping rule the remaining
+// kernels of the chunk return at entry.  After each chunk the host reads the 64-byte solve
+// state from pinned memory and stops when the device says so.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/prpull.h"
+#include "internal.h"
+
+namespace prpull {
+
+std::string &last_error_ref() {
+  static thread_local std::string s;
+  return s;
+}
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  last_error_ref() = buf;
+}
+
+hipError_t launch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, const double *init, void *y,
+                       double alpha, SolveState *st, double *bpart, int64_t bpart_cap);
+hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterParams &p);
+hipError_t launch_convert(hipStream_t s, const float *y32, double *y64, int32_t N, SolveState *st);
+hipError_t launch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *y, int32_t N, double *ranks);
+hipError_t launch_validate(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
+                           int32_t E, uint32_t *cnt, int32_t *flags, int32_t *host_flags);
+
+struct GraphEntry {
+  std::vector<unsigned char> key;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
+}  // namespace prpull
+
+using namespace prpull;
+
+struct pr_ctx {
+  int device = 0;
+  hipStream_t capture = nullptr;  // private stream used only for graph capture
+  SolveState *hstate = nullptr;   // pinned host copy of the solve state
+  unsigned long long *hscratch = nullptr;  // pinned host words for small read-backs
+  std::map<const void *, PrepHeader> preps;  // prep buffers prepared in this context
+  std::vector<GraphEntry> graphs;
+  uint64_t clock = 0;
+  // tunables (pr_set_option)
+  int64_t max_grid = 2048;
+  int64_t chunk = 8;
+  int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+struct Carver {
+  char *base;
+  size_t used = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  void *take(size_t n) {
+    void *p = base ? base + used : nullptr;
+    used += align_up(n, 256);
+    return p;
+  }
+};
+
+bool bad_graph_sizes(int64_t N, int64_t E) {
+  if (N < 1 || N > 2147483646LL) {
+    set_error("N must be in [1, 2^31-2], got %lld", (long long)N);
+    return true;
+  }
+  if (E < 0 || E > 2147483647LL) {
+    set_error("E must be in [0, 2^31-1], got %lld", (long long)E);
+    return true;
+  }
+  return false;
+}
+
+// Workspace layout of one solve.
+struct Layout {
+  SolveState *st;
+  double *bpart;
+  double *hpart;
+  uint32_t *hcnt;
+  double *y64[2];
+  float *y32[2];
+  void *prep;
+  size_t total;
+};
+
+Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep) {
+  Carver c(ws);
+  Layout L{};
+  L.st = (SolveState *)c.take(sizeof(SolveState));
+  L.bpart = (double *)c.take(4 * sizeof(double) * (size_t)kMaxGrid);
+  const int64_t slots = max_slots(N, E);
+  L.hpart = (double *)c.take(sizeof(double) * (size_t)slots);
+  L.hcnt = (uint32_t *)c.take(sizeof(uint32_t) * (size_t)slots);
+  L.y64[0] = (double *)c.take(sizeof(double) * (size_t)N);
+  L.y64[1] = (double *)c.take(sizeof(double) * (size_t)N);
+  if (precision == PR_MIXED) {
+    L.y32[0] = (float *)c.take(sizeof(float) * (size_t)N);
+    L.y32[1] = (float *)c.take(sizeof(float) * (size_t)N);
+  }
+  L.prep = with_prep ? c.take(prep_bytes(N, E)) : nullptr;
+  L.total = c.used;
+  return L;
+}
+
+int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep,
+                 PrepHeader *out) {
+  PrepHeader h{};
+  h.magic = kPrepMagic;
+  h.version = 1;
+  h.N = N;
+  h.E = E;
+  h.tile = kTile;
+  h.rows = kRows;
+  h.desc_off = (int64_t)align_up(sizeof(PrepHeader), 256);
+  h.scan_off = h.desc_off + (int64_t)align_up((size_t)(max_desc(N, E) + 1) * sizeof(int4), 256);
+  char *base = (char *)prep;
+  PR_HIP(launch_prepare(s, off, N, (int4 *)(base + h.desc_off), (unsigned long long *)(base + h.scan_off),
+                        ctx->hscratch));
+  const unsigned long long tot = ctx->hscratch[0];
+  h.ndesc = (int32_t)(tot >> 32);
+  h.nslots = (int32_t)(tot & 0xffffffffull);
+  if (h.ndesc < 1 || h.ndesc > max_desc(N, E) || h.nslots > max_slots(N, E)) {
+    set_error("internal: tile partition out of bounds (ndesc %d, slots %d)", h.ndesc, h.nslots);
+    return PR_EDEVICE;
+  }
+  memcpy(ctx->hscratch + 8, &h, sizeof h);
+  PR_HIP(hipMemcpyAsync(prep, ctx->hscratch + 8, sizeof h, hipMemcpyHostToDevice, s));
+  PR_HIP(hipStreamSynchronize(s));
+  ctx->preps[prep] = h;
+  *out = h;
+  return PR_OK;
+}
+
+int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E, PrepHeader *out) {
+  auto it = ctx->preps.find(prep);
+  PrepHeader h{};
+  if (it != ctx->preps.end()) {
+    h = it->second;
+  } else {
+    PR_HIP(hipMemcpyAsync(ctx->hscratch + 8, prep, sizeof h, hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    memcpy(&h, ctx->hscratch + 8, sizeof h);
+  }
+  if (h.magic != kPrepMagic || h.version != 1) {
+    set_error("prep buffer was not written by pr_prepare");
+    return PR_EINVAL;
+  }
+  if (h.N != N || h.E != E || h.tile != kTile || h.rows != kRows) {
+    set_error("prep buffer belongs to another graph (N=%lld E=%lld, expected N=%lld E=%lld)", (long long)h.N,
+              (long long)h.E, (long long)N, (long long)E);
+    return PR_EINVAL;
+  }
+  *out = h;
+  return PR_OK;
+}
+
+hipGraphExec_t cached_graph(pr_ctx *ctx, const std::vector<unsigned char> &key) {
+  for (auto &g : ctx->graphs)
+    if (g.key == key) {
+      g.last_use = ++ctx->clock;
+      return g.exec;
+    }
+  return nullptr;
+}
+
+void store_graph(pr_ctx *ctx, const std::vector<unsigned char> &key, hipGraphExec_t exec) {
+  constexpr size_t kMaxGraphs = 32;
+  if (ctx->graphs.size() >= kMaxGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < ctx->graphs.size(); ++i)
+      if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+    (void)hipGraphExecDestroy(ctx->graphs[lru].exec);
+    ctx->graphs.erase(ctx->graphs.begin() + (long)lru);
+  }
+  ctx->graphs.push_back(GraphEntry{key, exec, ++ctx->clock});
+}
+
+// Launch `chunk` updates alternating bufs[0] -> bufs[1] -> bufs[0] ... on stream s.
+int launch_chunk(pr_ctx *ctx, hipStream_t s, bool fp32, unsigned grid, IterParams p, void *const bufs[2]) {
+  const int chunk = (int)ctx->chunk;
+  if (ctx->loop_mode == 1) {
+    for (int k = 0; k < chunk; ++k) {
+      p.y_in = bufs[k & 1];
+      p.y_out = bufs[(k + 1) & 1];
+      PR_HIP(launch_update(s, fp32, grid, p));
+    }
+    return PR_OK;
+  }
+  std::vector<unsigned char> key(sizeof(IterParams) + 3 * sizeof(int64_t) + 2 * sizeof(void *));
+  {
+    IterParams q = p;
+    q.y_in = bufs[0];
+    q.y_out = bufs[1];
+    int64_t meta[3] = {fp32 ? 1 : 0, (int64_t)grid, chunk};
+    unsigned char *k = key.data();
+    memcpy(k, &q, sizeof q);
+    memcpy(k + sizeof q, meta, sizeof meta);
+    memcpy(k + sizeof q + sizeof meta, bufs, 2 * sizeof(void *));
+  }
+  hipGraphExec_t exec = cached_graph(ctx, key);
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    PR_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < chunk && err == hipSuccess; ++k) {
+      p.y_in = bufs[k & 1];
+      p.y_out = bufs[(k + 1) & 1];
+      err = launch_update(ctx->capture, fp32, grid, p);
+    }
+    hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      set_error("graph capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+      return PR_EDEVICE;
+    }
+    err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) {
+      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(err));
+      return PR_EDEVICE;
+    }
+    store_graph(ctx, key, exec);
+  }
+  PR_HIP(hipGraphLaunch(exec, s));
+  return PR_OK;
+}
+
+// Run one phase until the device sets `stop`; returns the buffer index holding the newest iterate.
+int run_phase(pr_ctx *ctx, hipStream_t s, bool fp32, unsigned grid, const IterParams &p, void *const bufs[2],
+              SolveState *dst, int *final_buf) {
+  for (;;) {
+    int rc = launch_chunk(ctx, s, fp32, grid, p, bufs);
+    if (rc != PR_OK) return rc;
+    PR_HIP(hipMemcpyAsync(ctx->hstate, dst, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    if (ctx->hstate->stop) break;
+    if (ctx->hstate->iter >= p.max_iter) {  // cannot happen: the kernel stops at max_iter
+      set_error("internal: iteration limit passed without stop");
+      return PR_EDEVICE;
+    }
+  }
+  *final_buf = ctx->hstate->phase_iter & 1;
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pr_last_error(void) { return last_error_ref().c_str(); }
+
+const char *pr_version(void) { return "prpull 0.1 (gfx950)"; }
+
+int pr_create(pr_ctx **out, int device) {
+  if (!out) {
+    set_error("pr_create: out is NULL");
+    return PR_EINVAL;
+  }
+  *out = nullptr;
+  int n = 0;
+  PR_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) {
+    set_error("pr_create: device %d not present (%d devices)", device, n);
+    return PR_EDEVICE;
+  }
+  DeviceGuard g(device);
+  pr_ctx *c = new pr_ctx();
+  c->device = device;
+  hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hstate, sizeof(SolveState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscratch, 64 * sizeof(unsigned long long), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error("pr_create: %s", hipGetErrorString(e));
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    if (c->hstate) (void)hipHostFree(c->hstate);
+    if (c->hscratch) (void)hipHostFree(c->hscratch);
+    delete c;
+    return PR_EDEVICE;
+  }
+  *out = c;
+  return PR_OK;
+}
+
+void pr_destroy(pr_ctx *ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  for (auto &e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+  if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+  if (ctx->hscratch) (void)hipHostFree(ctx->hscratch);
+  delete ctx;
+}
+
+int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
+  if (!ctx || !key) {
+    set_error("pr_set_option: NULL argument");
+    return PR_EINVAL;
+  }
+  if (!strcmp(key, "grid")) {
+    if (value < 1 || value > kMaxGrid) {
+      set_error("grid must be in [1, %d]", kMaxGrid);
+      return PR_EINVAL;
+    }
+    ctx->max_grid = value;
+  } else if (!strcmp(key, "chunk")) {
+    if (value < 2 || value > 64 || (value & 1)) {
+      set_error("chunk must be even and in [2, 64]");
+      return PR_EINVAL;
+    }
+    ctx->chunk = value;
+  } else if (!strcmp(key, "loop")) {
+    if (value != 0 && value != 1) {
+      set_error("loop must be 0 (graph) or 1 (direct)");
+      return PR_EINVAL;
+    }
+    ctx->loop_mode = value;
+  } else {
+    set_error("unknown option '%s'", key);
+    return PR_EINVAL;
+  }
+  return PR_OK;
+}
+
+size_t pr_prep_bytes(int64_t N, int64_t E) {
+  if (N < 1 || E < 0) return 0;
+  return prep_bytes(N, E);
+}
+
+int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, int64_t E, void *prep,
+               size_t prep_bytes_) {
+  if (!ctx || !in_offsets || !prep) {
+    set_error("pr_prepare: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (prep_bytes_ < prep_bytes(N, E)) {
+    set_error("pr_prepare: prep buffer has %zu bytes, needs %zu", prep_bytes_, prep_bytes(N, E));
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  PrepHeader h;
+  return prepare_into(ctx, (hipStream_t)stream, in_offsets, N, E, prep, &h);
+}
+
+int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                      const int32_t *outdeg, int64_t N, int64_t E, void *workspace, size_t workspace_bytes) {
+  if (!ctx || !in_offsets || !outdeg || !workspace || (E > 0 && !in_indices)) {
+    set_error("pr_validate_graph: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  const size_t need = align_up(4 * (size_t)N, 256) + 256;
+  if (workspace_bytes < need) {
+    set_error("pr_validate_graph: workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  uint32_t *cnt = (uint32_t *)workspace;
+  int32_t *flags = (int32_t *)((char *)workspace + align_up(4 * (size_t)N, 256));
+  int32_t *hf = (int32_t *)ctx->hscratch;
+  PR_HIP(launch_validate((hipStream_t)stream, in_offsets, in_indices, outdeg, (int32_t)N, (int32_t)E, cnt, flags, hf));
+  if (hf[0] || hf[1] || hf[2]) {
+    set_error("malformed CSR:%s%s%s (first offending offset %d, index position %d, vertex %d)",
+              hf[0] ? " offsets" : "", hf[1] ? " indices" : "", hf[2] ? " out-degrees" : "", hf[0] ? hf[3] : -1,
+              hf[1] ? hf[4] : -1, hf[2] ? hf[5] : -1);
+    return PR_EGRAPH;
+  }
+  return PR_OK;
+}
+
+size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep) {
+  if (N < 1 || E < 0 || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
+  return carve(nullptr, N, E, precision, with_prep != 0).total;
+}
+
+int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+            int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
+            int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
+            size_t workspace_bytes, pr_result *out) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices)) {
+    set_error("pr_pull: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (!(alpha >= 0.0 && alpha <= 1.0)) {
+    set_error("alpha must be in [0, 1], got %g", alpha);
+    return PR_EINVAL;
+  }
+  if (!(tau >= 0.0)) {
+    set_error("tau must be >= 0 and not NaN, got %g", tau);
+    return PR_EINVAL;
+  }
+  if (norm < PR_L1 || norm > PR_LINF) {
+    set_error("norm must be PR_L1, PR_L2 or PR_LINF, got %d", norm);
+    return PR_EINVAL;
+  }
+  if (max_iter < 1) {
+    set_error("max_iter must be >= 1, got %d", max_iter);
+    return PR_EINVAL;
+  }
+  if (precision != PR_FP64 && precision != PR_MIXED) {
+    set_error("precision must be PR_FP64 or PR_MIXED, got %d", precision);
+    return PR_EINVAL;
+  }
+  const Layout L = carve(workspace, N, E, precision, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_pull: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc;
+  const void *pp = prep;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
+  PR_HIP(launch_fill_u32(s, L.hcnt, h.nslots, 0u));
+  const unsigned grid = (unsigned)std::min<int64_t>(h.ndesc, ctx->max_grid);
+
+  IterParams p{};
+  p.off = in_offsets;
+  p.idx = in_indices;
+  p.outdeg = outdeg;
+  p.desc = (const int4 *)((const char *)pp + h.desc_off);
+  p.ndesc = h.ndesc;
+  p.N = (int32_t)N;
+  p.alpha = alpha;
+  p.tau = tau;
+  p.norm = norm;
+  p.max_iter = max_iter;
+  p.st = L.st;
+  p.bpart = L.bpart;
+  p.hpart = L.hpart;
+  p.hcnt = L.hcnt;
+  p.trace = norm_trace;
+
+  int fp32_iters = 0, fbuf = 0;
+  const void *final_y = nullptr;
+  bool final_fp32 = false;
+  if (precision == PR_MIXED) {
+    PR_HIP(launch_init(s, true, outdeg, (int32_t)N, init, L.y32[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 1;
+    void *b32[2] = {L.y32[0], L.y32[1]};
+    rc = run_phase(ctx, s, true, grid, p, b32, L.st, &fbuf);
+    if (rc != PR_OK) return rc;
+    fp32_iters = ctx->hstate->iter;
+    if (ctx->hstate->done) {
+      final_y = b32[fbuf];
+      final_fp32 = true;
+    } else {
+      PR_HIP(launch_convert(s, L.y32[fbuf], L.y64[0], (int32_t)N, L.st));
+      p.phase = 2;
+      void *b64[2] = {L.y64[0], L.y64[1]};
+      rc = run_phase(ctx, s, false, grid, p, b64, L.st, &fbuf);
+      if (rc != PR_OK) return rc;
+      final_y = b64[fbuf];
+    }
+  } else {
+    PR_HIP(launch_init(s, false, outdeg, (int32_t)N, init, L.y64[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 0;
+    void *b64[2] = {L.y64[0], L.y64[1]};
+    rc = run_phase(ctx, s, false, grid, p, b64, L.st, &fbuf);
+    if (rc != PR_OK) return rc;
+    final_y = b64[fbuf];
+  }
+  PR_HIP(launch_output(s, final_fp32, outdeg, final_y, (int32_t)N, ranks));
+  PR_HIP(hipMemcpyAsync(ctx->hstate, L.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  const SolveState &hs = *ctx->hstate;
+  out->iterations = hs.iter;
+  out->converged = hs.converged;
+  out->fp32_iters = precision == PR_MIXED ? fp32_iters : 0;
+  out->fp64_iters = hs.iter - out->fp32_iters;
+  out->final_err[0] = hs.err[0];
+  out->final_err[1] = hs.err[1];
+  out->final_err[2] = hs.err[2];
+  return hs.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+}  // extern "C"

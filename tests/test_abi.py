@@ -1,0 +1,45 @@
+"""The C ABI library loads and exports every function include/prpull.h declares (no GPU)."""
+import ctypes
+import os
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2108_02997_amd import _lib  # noqa: E402
+
+
+def test_library_exports_every_declared_function():
+    names = _lib.header_functions()
+    assert "pr_pull" in names and "pr_prepare" in names
+    lib = _lib.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(_lib.SIGNATURES), "binding lacks a declared function"
+
+
+def test_sizes_without_device():
+    lib = _lib.load()
+    assert lib.pr_workspace_bytes(1000, 8000, 0, 0) > 16000
+    assert lib.pr_workspace_bytes(1000, 8000, 1, 0) > lib.pr_workspace_bytes(1000, 8000, 0, 0)
+    assert lib.pr_workspace_bytes(1000, 8000, 0, 1) > lib.pr_workspace_bytes(1000, 8000, 0, 0)
+    assert lib.pr_workspace_bytes(0, 8000, 0, 0) == 0
+    assert lib.pr_workspace_bytes(10, 10, 5, 0) == 0
+    assert lib.pr_prep_bytes(1 << 20, 16 << 20) > 16 * (1 << 14)
+    assert b"gfx950" in lib.pr_version()
+
+
+def test_no_context_without_device():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    assert lib.pr_create(ctypes.byref(h), 0) < 0
+    assert lib.pr_last_error()
+
+
+def test_null_arguments_rejected_on_host():
+    lib = _lib.load()
+    assert lib.pr_pull(None, None, None, None, None, 10, 10, None, 0.85, 1e-6, 1, 10, 0, None, None, None, None,
+                       0, None) == _lib.PR_EINVAL
+    assert lib.pr_set_option(None, b"grid", 3) == _lib.PR_EINVAL

@@ -1,0 +1,255 @@
+"""Parity of the HIP pull PageRank (pr_pull through the C ABI) with the CPU oracle.
+
+FP64 bar: ranks within 1e-12 in L1 of the oracle's and the same number of iterations, unless
+the oracle's error at the deciding iteration lies within 1e-4 (relative) of tau, where one
+iteration either way is accepted (the GPU sums in another order, which moves the error by
+about 1e-13 relative and can flip a near-tie).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2108_02997_amd as pr
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return pr
+
+
+@pytest.fixture(scope="module")
+def ctx(pr):
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def dev(pr, g):
+    return pr.DeviceGraph.from_host(g)
+
+
+def oracle_run(g, **kw):
+    return oracle.pagerank_graph(g, trace=True, **kw)
+
+
+def iterations_ok(gpu_it, ref, tau, norm):
+    k = ref["iterations"]
+    if gpu_it == k:
+        return True
+    if abs(gpu_it - k) > 1:
+        return False
+    tr = ref["trace"][:, norm - 1]
+    near = [tr[i] for i in (k - 1, k - 2) if 0 <= i < len(tr)]
+    return any(abs(e - tau) <= 1e-4 * tau for e in near)
+
+
+def check_fp64(pr, ctx, g, alpha=0.85, tau=1e-6, norm=1, max_iter=500, init=None, dg=None):
+    dg = dg or dev(pr, g)
+    init_t = None if init is None else torch.from_numpy(np.asarray(init, dtype=np.float64)).cuda()
+    res = pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, max_iter=max_iter, init=init_t, trace=True)
+    ref = oracle_run(g, alpha=alpha, tau=tau, norm=norm, max_iter=max_iter, init=init)
+    ranks = res["ranks"].cpu().numpy()
+    assert iterations_ok(res["iterations"], ref, tau, norm), (res["iterations"], ref["iterations"])
+    if res["iterations"] == ref["iterations"]:
+        l1 = np.abs(ranks - ref["ranks"]).sum()
+        assert l1 <= 1e-12, l1
+        assert res["converged"] == ref["converged"]
+        # Trace entries differ by rounding only.  The largest term: the dangling sum D is added in
+        # another order (a tree on the GPU, ascending in the oracle); its rounding error, at most
+        # about (number of dangling vertices) * 2^-53 * D, shifts all N ranks by alpha*dD/N and so
+        # every L1 entry by alpha*dD.  Per-vertex roundings of r_v add a few 2^-52 * sum(r).
+        atol = 2.0 ** -50 * (g.N + 16)
+        np.testing.assert_allclose(res["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)
+    return res, ref
+
+
+# ------------------------------------------------------------------ the small configuration
+
+def test_c1_parity_all_norms(pr, ctx):
+    g = gg.workload_c1()
+    dg = dev(pr, g)
+    for norm in (1, 2, 3):
+        for tau in (1e-3, 1e-6, 1e-10):
+            check_fp64(pr, ctx, g, tau=tau, norm=norm, dg=dg)
+
+
+def test_c1_headline_setting(pr, ctx):
+    g = gg.workload_c1()
+    res, ref = check_fp64(pr, ctx, g, alpha=0.85, tau=1e-6, norm=1)
+    assert res["status"] == 0 and res["iterations"] == ref["iterations"]
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.95, 1.0])
+def test_alpha_range(pr, ctx, alpha):
+    check_fp64(pr, ctx, gg.rmat(13, seed=3), alpha=alpha, tau=1e-10, norm=3)
+
+
+# ------------------------------------------------------------------ tiny graphs and edge cases
+
+@pytest.mark.parametrize("make", [lambda: gg.cycle(7), lambda: gg.complete(40), lambda: gg.edgeless(9),
+                                  lambda: gg.edgeless(1), lambda: gg.in_star(3), lambda: gg.out_star(6),
+                                  lambda: gg.in_star(1), lambda: gg.cycle(2)])
+def test_tiny_zoo(pr, ctx, make):
+    g = make()
+    for norm in (1, 2, 3):
+        check_fp64(pr, ctx, g, tau=1e-12, norm=norm)
+
+
+def test_two_triangles_from_given_start(pr, ctx):
+    g = gg.two_triangles()
+    init = [1 / 3, 1 / 3, 1 / 3, 0, 0, 0]
+    res, ref = check_fp64(pr, ctx, g, alpha=0.85, tau=1e-6, norm=1, init=init)
+    assert res["iterations"] == 75
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_multigraphs(pr, ctx, seed):
+    rng = np.random.default_rng(seed)
+    N = int(rng.integers(1, 300))
+    g = gg.random_small(N, int(rng.integers(0, 6 * N)), seed, dedupe=False, self_loops=True)
+    check_fp64(pr, ctx, g, alpha=float(rng.uniform(0, 1)), tau=1e-11, norm=int(rng.integers(1, 4)))
+
+
+def test_hub_segments_and_mid_rows(pr, ctx):
+    # in-degrees spanning thread rows (<=32), wave rows (33..1024) and multi-segment hubs (>1024)
+    rng = np.random.default_rng(5)
+    N = 20000
+    src, dst = [], []
+    for v, deg in ((0, 5000), (17, 1025), (18, 1024), (19, 2049), (300, 40), (301, 33), (302, 32), (9999, 4097)):
+        s = rng.choice(N, size=deg, replace=False)
+        src.extend(s.tolist())
+        dst.extend([v] * deg)
+    s = rng.integers(0, N, 60000)
+    d = rng.integers(0, N, 60000)
+    src.extend(s.tolist())
+    dst.extend(d.tolist())
+    g = gg.from_edges(N, src, dst)
+    for norm in (1, 3):
+        check_fp64(pr, ctx, g, tau=1e-11, norm=norm)
+
+
+def test_rmat_several_tiles(pr, ctx):
+    g = gg.rmat(16, seed=11)
+    for norm in (1, 2, 3):
+        check_fp64(pr, ctx, g, tau=1e-10, norm=norm)
+
+
+def test_relabelled_rmat(pr, ctx):
+    g = gg.relabel(gg.rmat(15, seed=2), gg.permutation(1 << 15, 3))
+    check_fp64(pr, ctx, g, tau=1e-9, norm=2)
+
+
+def test_max_iter_halt(pr, ctx):
+    g = gg.workload_c1()
+    dg = dev(pr, g)
+    res = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=9)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=1, max_iter=9)
+    assert res["status"] == pr.PR_NOT_CONVERGED and not res["converged"] and res["iterations"] == 9
+    assert np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+
+
+def test_resume_continues_the_sequence(pr, ctx):
+    g = gg.rmat(14, seed=4)
+    dg = dev(pr, g)
+    part = oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=1, max_iter=5)
+    full = oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=1, max_iter=12)
+    init = torch.from_numpy(part["ranks"]).cuda()
+    res = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=7, init=init)
+    assert np.abs(res["ranks"].cpu().numpy() - full["ranks"]).sum() <= 1e-12
+
+
+def test_ranks_may_alias_init(pr, ctx):
+    g = gg.rmat(12, seed=8)
+    dg = dev(pr, g)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-9, norm=1)
+    buf = torch.full((g.N,), 1.0 / g.N, dtype=torch.float64, device="cuda")
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-9, norm=1, init=buf, ranks=buf)
+    assert res["iterations"] == ref["iterations"]
+    assert np.abs(buf.cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+
+
+def test_bitwise_repeatable(pr, ctx):
+    g = gg.rmat(15, seed=6)
+    dg = dev(pr, g)
+    a = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)["ranks"].clone()
+    b = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)["ranks"].clone()
+    assert torch.equal(a, b)
+
+
+def test_loop_modes_and_grids_agree(pr, ctx):
+    g = gg.rmat(14, seed=12)
+    dg = dev(pr, g)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-10, norm=2)
+    try:
+        for loop, grid, chunk in ((1, 2048, 8), (0, 7, 4), (0, 64, 16), (1, 1, 2)):
+            ctx.set_option("loop", loop)
+            ctx.set_option("grid", grid)
+            ctx.set_option("chunk", chunk)
+            res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=2)
+            assert res["iterations"] == ref["iterations"]
+            assert np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+    finally:
+        ctx.set_option("loop", 0)
+        ctx.set_option("grid", 2048)
+        ctx.set_option("chunk", 8)
+
+
+def test_prepare_inside_workspace(pr, ctx):
+    g = gg.rmat(13, seed=1)
+    dg = dev(pr, g)
+    ranks = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    ws = torch.empty(ctx.lib.pr_workspace_bytes(g.N, g.E, 0, 1), dtype=torch.uint8, device="cuda")
+    st, res = pr.pr_pull(ctx, dg, 0.85, 1e-8, 1, 500, 0, None, ranks, None, ws, use_prep=False)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-8, norm=1)
+    assert res["iterations"] == ref["iterations"]
+    assert np.abs(ranks.cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+
+
+# ------------------------------------------------------------------ errors
+
+def test_argument_errors(pr, ctx):
+    g = gg.cycle(5)
+    dg = dev(pr, g)
+    for kw in (dict(alpha=1.5), dict(alpha=-0.5), dict(tau=-1.0), dict(tau=float("nan")), dict(norm=0),
+               dict(norm=4), dict(max_iter=0), dict(precision=7)):
+        args = dict(alpha=0.85, tau=1e-6, norm=1, max_iter=10, precision=0)
+        args.update(kw)
+        with pytest.raises(pr.PrError) as ei:
+            pr.pull(ctx, dg, **args)
+        assert ei.value.status == -1
+    ranks = torch.empty(5, dtype=torch.float64, device="cuda")
+    tiny = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pr.PrError) as ei:
+        pr.pr_pull(ctx, dg, 0.85, 1e-6, 1, 10, 0, None, ranks, None, tiny)
+    assert ei.value.status == -2
+
+
+def test_validate_graph(pr, ctx):
+    g = gg.rmat(12, seed=2)
+    dev(pr, g).validate(ctx)
+    bad_deg = gg.Graph(g.N, g.off.copy(), g.idx.copy(), g.outdeg.copy())
+    bad_deg.outdeg[5] += 1
+    bad_idx = gg.Graph(g.N, g.off.copy(), g.idx.copy(), g.outdeg.copy())
+    bad_idx.idx[10] = g.N + 3
+    bad_off = gg.Graph(g.N, g.off.copy(), g.idx.copy(), g.outdeg.copy())
+    bad_off.off[100] = bad_off.off[101] + 1
+    for b in (bad_deg, bad_idx, bad_off):
+        with pytest.raises(pr.PrError) as ei:
+            dev(pr, b).validate(ctx)
+        assert ei.value.status == -4
+
+
+def test_prep_mismatch_rejected(pr, ctx):
+    a = dev(pr, gg.rmat(10, seed=1)).prepare(ctx)
+    b = dev(pr, gg.rmat(11, seed=1))
+    b.prep = a.prep
+    with pytest.raises(pr.PrError):
+        pr.pull(ctx, b)
