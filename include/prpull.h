@@ -86,11 +86,28 @@ const char *pr_last_error(void);
 const char *pr_version(void);
 
 /* Tunables of a context (read by later solves):
- *   "grid"  : maximum number of workgroups of an update launch, 1..4096 (default 2048)
+ *   "grid"  : maximum number of workgroups of an update launch, 1..16384, or 0 (default) for one
+ *             workgroup per resident slot (compute units x occupancy of the update kernel)
  *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 8)
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
+ *   "timing": 1 = launch updates one by one, each bracketed by HIP events on the solve stream,
+ *             and accumulate their durations (pr_get_stats); graphs are not replayed meanwhile
  * Returns PR_OK or PR_EINVAL for an unknown key or a value out of range. */
 int pr_set_option(pr_ctx *ctx, const char *key, int64_t value);
+
+/* Kernel kinds reported by pr_get_stats. */
+enum {
+  PR_KERNEL_UPDATE_F64 = 0, /* one float64 update of pr_pull */
+  PR_KERNEL_UPDATE_F32 = 1, /* one float32 update (PR_MIXED first phase) */
+  PR_KERNEL_KINDS = 8
+};
+
+/* With "timing" on: number of timed launches of `kind` that did work (launches that found the
+ * solve already stopped are not counted) and the sum of their durations in milliseconds, since
+ * the context was created or pr_reset_stats was called.  Each duration spans the two events
+ * around the launch. */
+int pr_get_stats(pr_ctx *ctx, int32_t kind, int64_t *launches, double *milliseconds);
+int pr_reset_stats(pr_ctx *ctx);
 
 /* --------------------------------------------------------------- graph prep (once per graph) */
 

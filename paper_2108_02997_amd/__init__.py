@@ -41,6 +41,16 @@ class Context:
     def set_option(self, key: str, value: int):
         _lib.check("pr_set_option", self.lib.pr_set_option(self.handle, key.encode(), int(value)))
 
+    def stats(self, kind: int):
+        """(launches, milliseconds) of kernel `kind` timed with HIP events (option "timing")."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _lib.check("pr_get_stats", self.lib.pr_get_stats(self.handle, kind, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def reset_stats(self):
+        _lib.check("pr_reset_stats", self.lib.pr_reset_stats(self.handle))
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pr_destroy(self.handle)

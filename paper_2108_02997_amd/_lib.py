@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
 PR_FP64, PR_MIXED = 0, 1
+PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32 = 0, 1
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EGRAPH = 0, 1, -1, -2, -3, -4
 STATUS_NAMES = {0: "PR_OK", 1: "PR_NOT_CONVERGED", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE",
                 -4: "PR_EGRAPH"}
@@ -46,6 +47,8 @@ SIGNATURES = {
     "pr_last_error": ([], ctypes.c_char_p),
     "pr_version": ([], ctypes.c_char_p),
     "pr_set_option": ([_vp, ctypes.c_char_p, _i64], ctypes.c_int),
+    "pr_get_stats": ([_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)], ctypes.c_int),
+    "pr_reset_stats": ([_vp], ctypes.c_int),
     "pr_prep_bytes": ([_i64, _i64], _sz),
     "pr_prepare": ([_vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),
     "pr_validate_graph": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),

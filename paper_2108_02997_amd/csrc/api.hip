@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -39,6 +40,7 @@ void set_error(const char *fmt, ...) {
 hipError_t launch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, const double *init, void *y,
                        double alpha, SolveState *st, double *bpart, int64_t bpart_cap);
 hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterParams &p);
+int update_blocks_per_cu(bool fp32);
 hipError_t launch_convert(hipStream_t s, const float *y32, double *y64, int32_t N, SolveState *st);
 hipError_t launch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *y, int32_t N, double *ranks);
 hipError_t launch_validate(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
@@ -48,6 +50,16 @@ struct GraphEntry {
   std::vector<unsigned char> key;
   hipGraphExec_t exec;
   uint64_t last_use;
+  std::vector<hipEvent_t> events;  // unused (kept empty)
+};
+
+// One chunk of a solve loop: `count` launches of one update kernel; launch(s, k) issues the
+// k-th.  `key` identifies the captured graph (kernel, parameters, buffers).
+struct ChunkSpec {
+  int kind;
+  int count;
+  std::vector<unsigned char> key;
+  std::function<hipError_t(hipStream_t, int)> launch;
 };
 
 }  // namespace prpull
@@ -63,9 +75,14 @@ struct pr_ctx {
   std::vector<GraphEntry> graphs;
   uint64_t clock = 0;
   // tunables (pr_set_option)
-  int64_t max_grid = 2048;
+  int64_t max_grid = 0;     // 0: one workgroup per resident slot (compute units x occupancy)
+  int64_t resident[2] = {1, 1};  // resident update workgroups: [float64, float32]
   int64_t chunk = 8;
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
+  int64_t timing = 0;     // 1: bracket every update launch with HIP events
+  std::vector<hipEvent_t> direct_events;
+  int64_t stat_launches[PR_KERNEL_KINDS] = {};
+  double stat_ms[PR_KERNEL_KINDS] = {};
 };
 
 namespace {
@@ -110,7 +127,6 @@ struct Layout {
   SolveState *st;
   double *bpart;
   double *hpart;
-  uint32_t *hcnt;
   double *y64[2];
   float *y32[2];
   void *prep;
@@ -124,7 +140,6 @@ Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep) 
   L.bpart = (double *)c.take(4 * sizeof(double) * (size_t)kMaxGrid);
   const int64_t slots = max_slots(N, E);
   L.hpart = (double *)c.take(sizeof(double) * (size_t)slots);
-  L.hcnt = (uint32_t *)c.take(sizeof(uint32_t) * (size_t)slots);
   L.y64[0] = (double *)c.take(sizeof(double) * (size_t)N);
   L.y64[1] = (double *)c.take(sizeof(double) * (size_t)N);
   if (precision == PR_MIXED) {
@@ -145,16 +160,19 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
   h.E = E;
   h.tile = kTile;
   h.rows = kRows;
+  h.seg = kSeg;
   h.desc_off = (int64_t)align_up(sizeof(PrepHeader), 256);
-  h.scan_off = h.desc_off + (int64_t)align_up((size_t)(max_desc(N, E) + 1) * sizeof(int4), 256);
+  h.hub_off = h.desc_off + (int64_t)align_up((size_t)(max_desc(N, E) + 1) * sizeof(int4), 256);
+  h.scan_off = h.hub_off + (int64_t)align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
   char *base = (char *)prep;
-  PR_HIP(launch_prepare(s, off, N, (int4 *)(base + h.desc_off), (unsigned long long *)(base + h.scan_off),
+  PR_HIP(launch_prepare(s, off, N, (int4 *)(base + h.desc_off), (int4 *)(base + h.hub_off), base + h.scan_off,
                         ctx->hscratch));
-  const unsigned long long tot = ctx->hscratch[0];
-  h.ndesc = (int32_t)(tot >> 32);
-  h.nslots = (int32_t)(tot & 0xffffffffull);
-  if (h.ndesc < 1 || h.ndesc > max_desc(N, E) || h.nslots > max_slots(N, E)) {
-    set_error("internal: tile partition out of bounds (ndesc %d, slots %d)", h.ndesc, h.nslots);
+  const unsigned long long tot_a = ctx->hscratch[0], tot_b = ctx->hscratch[1];
+  h.ndesc = (int32_t)tot_a;
+  h.nslots = (int32_t)(tot_b >> 32);
+  h.nhubs = (int32_t)(tot_b & 0xffffffffull);
+  if (h.ndesc < 1 || h.ndesc > max_desc(N, E) || h.nslots > max_slots(N, E) || h.nhubs > max_hubs(N, E)) {
+    set_error("internal: tile partition out of bounds (ndesc %d, slots %d, hubs %d)", h.ndesc, h.nslots, h.nhubs);
     return PR_EDEVICE;
   }
   memcpy(ctx->hscratch + 8, &h, sizeof h);
@@ -179,7 +197,7 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
     set_error("prep buffer was not written by pr_prepare");
     return PR_EINVAL;
   }
-  if (h.N != N || h.E != E || h.tile != kTile || h.rows != kRows) {
+  if (h.N != N || h.E != E || h.tile != kTile || h.rows != kRows || h.seg != kSeg) {
     set_error("prep buffer belongs to another graph (N=%lld E=%lld, expected N=%lld E=%lld)", (long long)h.N,
               (long long)h.E, (long long)N, (long long)E);
     return PR_EINVAL;
@@ -188,93 +206,125 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
   return PR_OK;
 }
 
-hipGraphExec_t cached_graph(pr_ctx *ctx, const std::vector<unsigned char> &key) {
+int make_events(std::vector<hipEvent_t> &ev, size_t n) {
+  while (ev.size() < n) {
+    hipEvent_t e;
+    PR_HIP(hipEventCreate(&e));
+    ev.push_back(e);
+  }
+  return PR_OK;
+}
+
+// Issue one chunk on stream s (captured graph or direct launches); *events receives the
+// timestamps bracketing each launch when timing is on, else nullptr.
+int run_chunk(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const std::vector<hipEvent_t> **events) {
+  *events = nullptr;
+  const bool timed = ctx->timing != 0;
+  // events recorded inside a captured graph cannot be timed, so timed chunks launch one by one
+  if (ctx->loop_mode == 1 || timed) {
+    if (timed) {
+      int rc = make_events(ctx->direct_events, (size_t)c.count + 1);
+      if (rc != PR_OK) return rc;
+      PR_HIP(hipEventRecord(ctx->direct_events[0], s));
+    }
+    for (int k = 0; k < c.count; ++k) {
+      PR_HIP(c.launch(s, k));
+      if (timed) PR_HIP(hipEventRecord(ctx->direct_events[k + 1], s));
+    }
+    if (timed) *events = &ctx->direct_events;
+    return PR_OK;
+  }
+  std::vector<unsigned char> key = c.key;
+  const int64_t meta[2] = {c.kind, c.count};
+  key.insert(key.end(), (const unsigned char *)meta, (const unsigned char *)meta + sizeof meta);
+  GraphEntry *entry = nullptr;
   for (auto &g : ctx->graphs)
     if (g.key == key) {
       g.last_use = ++ctx->clock;
-      return g.exec;
+      entry = &g;
     }
-  return nullptr;
-}
-
-void store_graph(pr_ctx *ctx, const std::vector<unsigned char> &key, hipGraphExec_t exec) {
-  constexpr size_t kMaxGraphs = 32;
-  if (ctx->graphs.size() >= kMaxGraphs) {
-    size_t lru = 0;
-    for (size_t i = 1; i < ctx->graphs.size(); ++i)
-      if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
-    (void)hipGraphExecDestroy(ctx->graphs[lru].exec);
-    ctx->graphs.erase(ctx->graphs.begin() + (long)lru);
-  }
-  ctx->graphs.push_back(GraphEntry{key, exec, ++ctx->clock});
-}
-
-// Launch `chunk` updates alternating bufs[0] -> bufs[1] -> bufs[0] ... on stream s.
-int launch_chunk(pr_ctx *ctx, hipStream_t s, bool fp32, unsigned grid, IterParams p, void *const bufs[2]) {
-  const int chunk = (int)ctx->chunk;
-  if (ctx->loop_mode == 1) {
-    for (int k = 0; k < chunk; ++k) {
-      p.y_in = bufs[k & 1];
-      p.y_out = bufs[(k + 1) & 1];
-      PR_HIP(launch_update(s, fp32, grid, p));
-    }
-    return PR_OK;
-  }
-  std::vector<unsigned char> key(sizeof(IterParams) + 3 * sizeof(int64_t) + 2 * sizeof(void *));
-  {
-    IterParams q = p;
-    q.y_in = bufs[0];
-    q.y_out = bufs[1];
-    int64_t meta[3] = {fp32 ? 1 : 0, (int64_t)grid, chunk};
-    unsigned char *k = key.data();
-    memcpy(k, &q, sizeof q);
-    memcpy(k + sizeof q, meta, sizeof meta);
-    memcpy(k + sizeof q + sizeof meta, bufs, 2 * sizeof(void *));
-  }
-  hipGraphExec_t exec = cached_graph(ctx, key);
-  if (!exec) {
+  if (!entry) {
+    std::vector<hipEvent_t> ev;
     hipGraph_t g = nullptr;
     PR_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (int k = 0; k < chunk && err == hipSuccess; ++k) {
-      p.y_in = bufs[k & 1];
-      p.y_out = bufs[(k + 1) & 1];
-      err = launch_update(ctx->capture, fp32, grid, p);
-    }
+    for (int k = 0; k < c.count && err == hipSuccess; ++k) err = c.launch(ctx->capture, k);
     hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+    hipGraphExec_t exec = nullptr;
+    if (err == hipSuccess && e2 == hipSuccess) err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
     if (err != hipSuccess || e2 != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
+      for (auto e : ev) (void)hipEventDestroy(e);
       set_error("graph capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e2));
       return PR_EDEVICE;
     }
-    err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (err != hipSuccess) {
-      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(err));
-      return PR_EDEVICE;
+    constexpr size_t kMaxGraphs = 48;
+    if (ctx->graphs.size() >= kMaxGraphs) {
+      size_t lru = 0;
+      for (size_t i = 1; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+      (void)hipGraphExecDestroy(ctx->graphs[lru].exec);
+      for (auto e : ctx->graphs[lru].events) (void)hipEventDestroy(e);
+      ctx->graphs.erase(ctx->graphs.begin() + (long)lru);
     }
-    store_graph(ctx, key, exec);
+    ctx->graphs.push_back(GraphEntry{key, exec, ++ctx->clock, ev});
+    entry = &ctx->graphs.back();
   }
-  PR_HIP(hipGraphLaunch(exec, s));
+  PR_HIP(hipGraphLaunch(entry->exec, s));
   return PR_OK;
 }
 
-// Run one phase until the device sets `stop`; returns the buffer index holding the newest iterate.
-int run_phase(pr_ctx *ctx, hipStream_t s, bool fp32, unsigned grid, const IterParams &p, void *const bufs[2],
-              SolveState *dst, int *final_buf) {
-  for (;;) {
-    int rc = launch_chunk(ctx, s, fp32, grid, p, bufs);
+// Replay chunks until the device sets head.stop; `head` is the device LoopHead of the solve.
+// Returns the parity of the updates done in the phase (index of the buffer holding the newest
+// iterate when updates alternate two buffers starting from buffer 0).
+int run_until_stop(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const LoopHead *head, int max_updates,
+                   int *final_buf) {
+  LoopHead *h = (LoopHead *)ctx->hstate;
+  int before = 0;
+  for (int rounds = 0;; ++rounds) {
+    const std::vector<hipEvent_t> *ev = nullptr;
+    int rc = run_chunk(ctx, s, c, &ev);
     if (rc != PR_OK) return rc;
-    PR_HIP(hipMemcpyAsync(ctx->hstate, dst, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipMemcpyAsync(h, head, sizeof(LoopHead), hipMemcpyDeviceToHost, s));
     PR_HIP(hipStreamSynchronize(s));
-    if (ctx->hstate->stop) break;
-    if (ctx->hstate->iter >= p.max_iter) {  // cannot happen: the kernel stops at max_iter
-      set_error("internal: iteration limit passed without stop");
+    const int did = h->phase_iter - before;
+    if (ev && did > 0) {
+      float ms = 0.f;
+      for (int k = 0; k < did && k < c.count; ++k) {
+        PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
+        ctx->stat_ms[c.kind] += ms;
+        ctx->stat_launches[c.kind] += 1;
+      }
+    }
+    before = h->phase_iter;
+    if (h->stop) break;
+    if (rounds > max_updates) {  // cannot happen: the kernels stop at max_iter
+      set_error("internal: update limit passed without stop");
       return PR_EDEVICE;
     }
   }
-  *final_buf = ctx->hstate->phase_iter & 1;
+  *final_buf = h->phase_iter & 1;
   return PR_OK;
+}
+
+ChunkSpec update_chunk(pr_ctx *ctx, bool fp32, unsigned grid, const IterParams &p, void *b0, void *b1) {
+  ChunkSpec c;
+  c.kind = fp32 ? PR_KERNEL_UPDATE_F32 : PR_KERNEL_UPDATE_F64;
+  c.count = (int)ctx->chunk;
+  IterParams q = p;
+  q.y_in = b0;
+  q.y_out = b1;
+  const int64_t g = grid;
+  c.key.resize(sizeof q + sizeof g);
+  memcpy(c.key.data(), &q, sizeof q);
+  memcpy(c.key.data() + sizeof q, &g, sizeof g);
+  c.launch = [fp32, grid, p, b0, b1](hipStream_t s, int k) {
+    IterParams r = p;
+    r.y_in = (k & 1) ? b1 : b0;
+    r.y_out = (k & 1) ? b0 : b1;
+    return launch_update(s, fp32, grid, r);
+  };
+  return c;
 }
 
 }  // namespace
@@ -300,6 +350,10 @@ int pr_create(pr_ctx **out, int device) {
   DeviceGuard g(device);
   pr_ctx *c = new pr_ctx();
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  c->resident[0] = (int64_t)cus * update_blocks_per_cu(false);
+  c->resident[1] = (int64_t)cus * update_blocks_per_cu(true);
   hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hstate, sizeof(SolveState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscratch, 64 * sizeof(unsigned long long), hipHostMallocDefault);
@@ -318,7 +372,11 @@ int pr_create(pr_ctx **out, int device) {
 void pr_destroy(pr_ctx *ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
-  for (auto &e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
+  for (auto &e : ctx->graphs) {
+    (void)hipGraphExecDestroy(e.exec);
+    for (auto ev : e.events) (void)hipEventDestroy(ev);
+  }
+  for (auto ev : ctx->direct_events) (void)hipEventDestroy(ev);
   if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
   if (ctx->hscratch) (void)hipHostFree(ctx->hscratch);
@@ -331,8 +389,8 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
     return PR_EINVAL;
   }
   if (!strcmp(key, "grid")) {
-    if (value < 1 || value > kMaxGrid) {
-      set_error("grid must be in [1, %d]", kMaxGrid);
+    if (value < 0 || value > kMaxGrid) {
+      set_error("grid must be in [0, %d] (0 = resident workgroups)", kMaxGrid);
       return PR_EINVAL;
     }
     ctx->max_grid = value;
@@ -342,6 +400,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->chunk = value;
+  } else if (!strcmp(key, "timing")) {
+    if (value != 0 && value != 1) {
+      set_error("timing must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->timing = value;
   } else if (!strcmp(key, "loop")) {
     if (value != 0 && value != 1) {
       set_error("loop must be 0 (graph) or 1 (direct)");
@@ -351,6 +415,28 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
   } else {
     set_error("unknown option '%s'", key);
     return PR_EINVAL;
+  }
+  return PR_OK;
+}
+
+int pr_get_stats(pr_ctx *ctx, int32_t kind, int64_t *launches, double *milliseconds) {
+  if (!ctx || !launches || !milliseconds || kind < 0 || kind >= PR_KERNEL_KINDS) {
+    set_error("pr_get_stats: bad argument");
+    return PR_EINVAL;
+  }
+  *launches = ctx->stat_launches[kind];
+  *milliseconds = ctx->stat_ms[kind];
+  return PR_OK;
+}
+
+int pr_reset_stats(pr_ctx *ctx) {
+  if (!ctx) {
+    set_error("pr_reset_stats: NULL context");
+    return PR_EINVAL;
+  }
+  for (int k = 0; k < PR_KERNEL_KINDS; ++k) {
+    ctx->stat_launches[k] = 0;
+    ctx->stat_ms[k] = 0.0;
   }
   return PR_OK;
 }
@@ -455,8 +541,8 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   if (rc != PR_OK) return rc;
 
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
-  PR_HIP(launch_fill_u32(s, L.hcnt, h.nslots, 0u));
-  const unsigned grid = (unsigned)std::min<int64_t>(h.ndesc, ctx->max_grid);
+  const int64_t gcap = ctx->max_grid > 0 ? ctx->max_grid : ctx->resident[precision == PR_MIXED ? 1 : 0];
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)h.ndesc, gcap, kMaxGrid}));
 
   IterParams p{};
   p.off = in_offsets;
@@ -472,7 +558,9 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   p.st = L.st;
   p.bpart = L.bpart;
   p.hpart = L.hpart;
-  p.hcnt = L.hcnt;
+  p.hubs = (const int4 *)((const char *)pp + h.hub_off);
+  p.nhubs = h.nhubs;
+  p.grid = (int32_t)grid;
   p.trace = norm_trace;
 
   int fp32_iters = 0, fbuf = 0;
@@ -481,37 +569,35 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   if (precision == PR_MIXED) {
     PR_HIP(launch_init(s, true, outdeg, (int32_t)N, init, L.y32[0], alpha, L.st, L.bpart, kMaxGrid));
     p.phase = 1;
-    void *b32[2] = {L.y32[0], L.y32[1]};
-    rc = run_phase(ctx, s, true, grid, p, b32, L.st, &fbuf);
+    rc = run_until_stop(ctx, s, update_chunk(ctx, true, grid, p, L.y32[0], L.y32[1]), &L.st->head, max_iter, &fbuf);
     if (rc != PR_OK) return rc;
-    fp32_iters = ctx->hstate->iter;
-    if (ctx->hstate->done) {
-      final_y = b32[fbuf];
+    fp32_iters = ((LoopHead *)ctx->hstate)->iter;
+    if (((LoopHead *)ctx->hstate)->done) {
+      final_y = L.y32[fbuf];
       final_fp32 = true;
     } else {
       PR_HIP(launch_convert(s, L.y32[fbuf], L.y64[0], (int32_t)N, L.st));
       p.phase = 2;
-      void *b64[2] = {L.y64[0], L.y64[1]};
-      rc = run_phase(ctx, s, false, grid, p, b64, L.st, &fbuf);
+      rc = run_until_stop(ctx, s, update_chunk(ctx, false, grid, p, L.y64[0], L.y64[1]), &L.st->head, max_iter,
+                          &fbuf);
       if (rc != PR_OK) return rc;
-      final_y = b64[fbuf];
+      final_y = L.y64[fbuf];
     }
   } else {
     PR_HIP(launch_init(s, false, outdeg, (int32_t)N, init, L.y64[0], alpha, L.st, L.bpart, kMaxGrid));
     p.phase = 0;
-    void *b64[2] = {L.y64[0], L.y64[1]};
-    rc = run_phase(ctx, s, false, grid, p, b64, L.st, &fbuf);
+    rc = run_until_stop(ctx, s, update_chunk(ctx, false, grid, p, L.y64[0], L.y64[1]), &L.st->head, max_iter, &fbuf);
     if (rc != PR_OK) return rc;
-    final_y = b64[fbuf];
+    final_y = L.y64[fbuf];
   }
   PR_HIP(launch_output(s, final_fp32, outdeg, final_y, (int32_t)N, ranks));
   PR_HIP(hipMemcpyAsync(ctx->hstate, L.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
   PR_HIP(hipStreamSynchronize(s));
   const SolveState &hs = *ctx->hstate;
-  out->iterations = hs.iter;
+  out->iterations = hs.head.iter;
   out->converged = hs.converged;
   out->fp32_iters = precision == PR_MIXED ? fp32_iters : 0;
-  out->fp64_iters = hs.iter - out->fp32_iters;
+  out->fp64_iters = hs.head.iter - out->fp32_iters;
   out->final_err[0] = hs.err[0];
   out->final_err[1] = hs.err[1];
   out->final_err[2] = hs.err[2];

@@ -13,21 +13,27 @@ namespace prpull {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 // A tile covers consecutive rows whose first CSR entry falls in one window of kTile entries
-// and whose row ids fall in one window of kRows rows; rows longer than kTile are hubs and are
-// cut into segments of kTile entries.  A tile therefore spans fewer than 2*kTile entries.
+// and whose row ids fall in one window of kRows rows; rows longer than kTile ("long rows") get
+// tiles of their own, one per segment of at most kSeg entries.  A tile of short rows therefore
+// spans fewer than 2*kTile entries.
 constexpr int kTile = 1024;
 constexpr int kRows = 512;
 constexpr int kSpan = 2 * kTile;
 constexpr int kRowsPerLane = kRows / kBlock;  // 2
+constexpr int kSeg = 8192;
 // Rows with in-degree above kMidDeg (and at most kTile) are summed by a whole wave.
 constexpr int kMidDeg = 32;
-// Upper bound of persistent-style grid (blocks loop over tiles).
-constexpr int kMaxGrid = 4096;
+// Upper bound of the update grid (blocks loop over tiles in a fixed round-robin order).
+constexpr int kMaxGrid = 16384;
+// The finishing kernel runs as one block of kFinBlock lanes.
+constexpr int kFinBlock = 1024;
 
 // ---------------------------------------------------------------- prep layout
-// Tile descriptor: x = first row, y = number of segments (hub) or 0 (tile of rows),
-// z = segment index (hub) or -1, w = first partial slot of the hub.  Tile i ends where
-// tile i+1 starts; a sentinel with x = N follows the last tile.
+// Tile descriptor: x = first row, y = first CSR entry, z = segment index (long row) or -1 (tile
+// of short rows), w = partial slot of this segment for a hub, -1 otherwise.  Tile i ends where
+// tile i+1 starts (rows desc[i].x .. desc[i+1].x, entries desc[i].y .. desc[i+1].y); a sentinel
+// {N, E, -1, -1} follows the last tile.  Long rows of two or more segments ("hubs") are also
+// listed in a hub table: x = row, y = segments, z = first slot.
 struct PrepHeader {
   int32_t magic;
   int32_t version;
@@ -36,28 +42,34 @@ struct PrepHeader {
   int32_t tile, rows, ndesc, nslots;
   int64_t desc_off;   // byte offset of the descriptors inside the prep buffer
   int64_t scan_off;   // byte offset of the scan scratch
-  int64_t reserved[3];
+  int64_t hub_off;    // byte offset of the hub table
+  int32_t nhubs, seg;
+  int64_t reserved;
 };
 constexpr int32_t kPrepMagic = 0x50525031;  // "PRP1"
 
 size_t prep_bytes(int64_t N, int64_t E);
 int64_t max_desc(int64_t N, int64_t E);
 int64_t max_slots(int64_t N, int64_t E);
+int64_t max_hubs(int64_t N, int64_t E);
 
 // ---------------------------------------------------------------- solve state (device)
+// The first 16 bytes of every device solve state: what the host loop reads after a chunk.
+struct LoopHead {
+  int32_t stop;        // 1: the kernels of the running phase are no-ops
+  int32_t phase_iter;  // updates performed in the running phase
+  int32_t iter;        // updates performed so far (all phases)
+  int32_t done;        // 1: the whole solve is finished
+};
+
 struct alignas(64) SolveState {
+  LoopHead head;
+  int32_t converged;  // 1: an update met tau in the convergence norm
+  int32_t met32;      // the float32 phase met tau
+  int32_t pad0, pad1;
   double c0;          // teleport term for the next update
   double err[3];      // L1, L2, Linf of the last update
   double prev_l1;     // L1 of the update before (float32 stagnation test)
-  int32_t iter;       // updates performed so far (all phases)
-  int32_t stop;       // 1: the kernels of the running phase are no-ops
-  int32_t done;       // 1: the whole solve is finished
-  int32_t converged;  // 1: an update met tau in the convergence norm
-  int32_t phase_iter; // updates performed in the running phase
-  int32_t met32;      // the float32 phase met tau
-  uint32_t ticket;    // last-block counter of the iteration kernel
-  uint32_t ticket2;   // last-block counter of init/convert kernels
-  int32_t pad[4];
 };
 
 // Kernel parameters of one update (passed by value).
@@ -77,9 +89,11 @@ struct IterParams {
   int32_t phase;       // 0: float64 solve, 1: float32 phase of a mixed solve, 2: float64 phase
   int32_t pad;
   SolveState *st;
-  double *bpart;       // [gridDim.x][4] block partials: L1, sum sq, Linf, dangling sum
+  double *bpart;       // [grid][4] block partials: L1, sum sq, Linf, dangling sum
   double *hpart;       // hub segment partial sums
-  uint32_t *hcnt;      // hub segment counters (indexed by the hub's first slot)
+  const int4 *hubs;    // hub table
+  int32_t nhubs;
+  int32_t grid;        // number of blocks of the update launch (partials to reduce)
   double *trace;       // [max_iter][3] or null
 };
 
@@ -100,7 +114,8 @@ std::string &last_error_ref();
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Launchers (defined in the .hip files).
-hipError_t launch_prepare(hipStream_t s, const int32_t *off, int64_t N, int4 *desc, unsigned long long *bsum,
+// host_total receives {descriptors, hub slots << 32 | hubs}.
+hipError_t launch_prepare(hipStream_t s, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
                           unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);

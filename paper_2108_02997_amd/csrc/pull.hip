@@ -11,13 +11,13 @@
 //
 // One update = one launch of k_update over all tiles (see prep.hip), with
 //   gather   : contributions of a tile's in-edges staged through LDS (coalesced index loads);
-//   sum      : one lane per low in-degree row, one wave64 per mid row, fixed-order block
-//              reduction per hub segment and a fixed-order combine by the last segment;
+//   sum      : one lane per low in-degree row, one wave64 per mid row, one workgroup per
+//              segment of a long row (fixed-order block reduction);
 //   epilogue : r'_v = c0 + alpha*s_v, the new y_v, |r'_v - r_v| into L1/L2/Linf partials and
 //              r'_v of dangling vertices into the dangling-sum partial;
-//   finalize : the last block to finish reduces the block partials in block order and sets
-//              the errors, the next teleport term c0 = (1-alpha)/N + (alpha*D)/N, the stop flags
-//              and the trace row.
+// then k_finish (one block, after the kernel boundary) combines hub segments in segment order,
+// reduces the block partials in block order and sets the errors, the next teleport term
+// c0 = (1-alpha)/N + (alpha*D)/N, the stop flags and the trace row.
 // Every reduction has a fixed order, so results are bitwise repeatable run to run.
 #include "internal.h"
 
@@ -57,23 +57,20 @@ struct Acc {
 };
 
 template <typename VT>
-__device__ __forceinline__ void epilogue(int32_t v, double s, double c0, double alpha,
-                                         const int32_t *__restrict__ outdeg, const VT *__restrict__ yin,
+__device__ __forceinline__ void epilogue(int32_t v, double s, double c0, double alpha, int32_t dv, VT yo,
                                          VT *__restrict__ yout, Acc &a) {
 #pragma clang fp contract(off)
   const double rn = c0 + alpha * s;
-  const int32_t dv = outdeg[v];
-  const VT yo = yin[v];
   double old, rnew;
   if (dv > 0) {
     old = (double)yo * (double)dv;
     const VT y = (VT)(rn / (double)dv);
-    yout[v] = y;
+    __builtin_nontemporal_store(y, &yout[v]);
     rnew = sizeof(VT) == 8 ? rn : (double)y * (double)dv;
   } else {
     old = (double)yo;
     const VT y = (VT)rn;
-    yout[v] = y;
+    __builtin_nontemporal_store(y, &yout[v]);
     rnew = (double)y;
     a.dang += rnew;
   }
@@ -83,18 +80,17 @@ __device__ __forceinline__ void epilogue(int32_t v, double s, double c0, double 
   a.mx = fmax(a.mx, d);
 }
 
-// Finalize one update: called by every lane of the last block, with the reduced totals.
+// Finalize one update (lane 0 of the finishing kernel), with the reduced totals.
 __device__ __forceinline__ void finalize(const IterParams &p, double l1, double sq, double mx, double dang) {
 #pragma clang fp contract(off)
-  if (threadIdx.x != 0) return;
   SolveState *st = p.st;
   const double e[3] = {l1, sqrt(sq), mx};
   st->err[0] = e[0];
   st->err[1] = e[1];
   st->err[2] = e[2];
-  const int32_t it = st->iter + 1;
-  st->iter = it;
-  st->phase_iter = st->phase_iter + 1;
+  const int32_t it = st->head.iter + 1;
+  st->head.iter = it;
+  st->head.phase_iter = st->head.phase_iter + 1;
   if (p.trace) {
     p.trace[3 * (int64_t)(it - 1) + 0] = e[0];
     p.trace[3 * (int64_t)(it - 1) + 1] = e[1];
@@ -107,33 +103,61 @@ __device__ __forceinline__ void finalize(const IterParams &p, double l1, double 
     // float32 phase: hand over to float64 once tau is met or the L1 change stops shrinking
     // (in exact arithmetic the L1 change never grows: the update is an alpha-contraction in L1)
     if (met) st->met32 = 1;
-    if (met || !(l1 < st->prev_l1)) st->stop = 1;
+    if (met || !(l1 < st->prev_l1)) st->head.stop = 1;
     st->prev_l1 = l1;
     if (it >= p.max_iter) {
-      st->stop = 1;
-      st->done = 1;
+      st->head.stop = 1;
+      st->head.done = 1;
     }
   } else {
     if (met) {
       st->converged = 1;
-      st->stop = 1;
-      st->done = 1;
+      st->head.stop = 1;
+      st->head.done = 1;
     } else if (it >= p.max_iter) {
-      st->stop = 1;
-      st->done = 1;
+      st->head.stop = 1;
+      st->head.done = 1;
     }
   }
-  st->ticket = 0;
+}
+
+// Fixed-order reduction over a block of NT lanes; every lane gets the result.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double *lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = lds[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) s += lds[i];
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max_n(double v, double *lds) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = lds[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) s = fmax(s, lds[i]);
+  return s;
 }
 
 // ------------------------------------------------------------------ the update kernel
+// Blocks take tiles i = blockIdx.x, blockIdx.x + grid, ... and write their four partial sums
+// with plain stores; all cross-block combining happens in k_finish, after the kernel boundary
+// (device-scope fences would write back and invalidate the whole L2 of each XCD).
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
   __shared__ VT vals[kSpan];
   __shared__ double red[kWaves];
-  __shared__ int s_last;
   const SolveState *st = p.st;
-  if (st->stop) return;
+  if (st->head.stop) return;
   const double c0 = st->c0;
   const double alpha = p.alpha;
   const VT *__restrict__ yin = (const VT *)p.y_in;
@@ -142,20 +166,38 @@ __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
   const int32_t *__restrict__ idx = p.idx;
   const int t = threadIdx.x, lane = t & 63;
   Acc a = {0.0, 0.0, 0.0, 0.0};
+  constexpr int kPer = kSpan / kBlock;
+  (void)off;
 
   for (int32_t i = blockIdx.x; i < p.ndesc; i += gridDim.x) {
     const int4 d = p.desc[i];
+    const int4 dn = p.desc[i + 1];
+    const int32_t e0 = d.y, e1 = dn.y;
     if (d.z < 0) {
-      // ---- tile of rows [v0, v1): stage the contributions of its entries into LDS
-      const int32_t v0 = d.x, v1 = p.desc[i + 1].x;
-      const int32_t e0 = off[v0];
-      const int32_t n = off[v1] - e0;  // < kSpan
-      constexpr int kPer = kSpan / kBlock;
+      // ---- tile of short rows [d.x, dn.x) with entries [e0, e1), e1 - e0 < kSpan.
+      // One round trip for the index stream and the rows' own data, one for the gather.
+      const int32_t v0 = d.x, v1 = dn.x;
+      const int32_t n = e1 - e0;
       int32_t u[kPer];
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
         const int j = t + k * kBlock;
-        u[k] = j < n ? idx[e0 + j] : -1;
+        u[k] = j < n ? __builtin_nontemporal_load(idx + e0 + j) : -1;
+      }
+      int32_t ra[kRowsPerLane], rb[kRowsPerLane], dv[kRowsPerLane];
+      VT yo[kRowsPerLane];
+#pragma unroll
+      for (int q = 0; q < kRowsPerLane; ++q) {
+        const int32_t v = v0 + t + q * kBlock;
+        ra[q] = rb[q] = 0;
+        dv[q] = 0;
+        yo[q] = (VT)0;
+        if (v < v1) {
+          ra[q] = __builtin_nontemporal_load(off + v) - e0;
+          rb[q] = __builtin_nontemporal_load(off + v + 1) - e0;
+          dv[q] = __builtin_nontemporal_load(p.outdeg + v);
+          yo[q] = __builtin_nontemporal_load(yin + v);
+        }
       }
       VT x[kPer];
 #pragma unroll
@@ -170,121 +212,104 @@ __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
       for (int q = 0; q < kRowsPerLane; ++q) {
         const int32_t v = v0 + t + q * kBlock;
         const bool mine = v < v1;
-        int32_t ra = 0, rb = 0;
-        if (mine) {
-          ra = off[v] - e0;
-          rb = off[v + 1] - e0;
-        }
-        const bool mid = mine && (rb - ra) > kMidDeg;
+        const bool mid = mine && (rb[q] - ra[q]) > kMidDeg;
         if (mine && !mid) {
           VT s = (VT)0;
-          for (int32_t j = ra; j < rb; ++j) s += vals[j];
-          epilogue<VT>(v, (double)s, c0, alpha, p.outdeg, yin, yout, a);
+          for (int32_t j = ra[q]; j < rb[q]; ++j) s += vals[j];
+          epilogue<VT>(v, (double)s, c0, alpha, dv[q], yo[q], yout, a);
         }
         unsigned long long m = __ballot(mid);
         while (m) {
           const int src = __ffsll((long long)m) - 1;
           m &= m - 1;
-          const int32_t wa = __shfl(ra, src, 64), wb = __shfl(rb, src, 64);
+          const int32_t wa = __shfl(ra[q], src, 64), wb = __shfl(rb[q], src, 64);
           VT s = (VT)0;
           for (int32_t j = wa + lane; j < wb; j += 64) s += vals[j];
           s = wave_sum(s);
-          if (lane == src) epilogue<VT>(v, (double)s, c0, alpha, p.outdeg, yin, yout, a);
+          if (lane == src) epilogue<VT>(v, (double)s, c0, alpha, dv[q], yo[q], yout, a);
         }
       }
       __syncthreads();
     } else {
-      // ---- one kTile-entry segment of a hub row
-      const int32_t v = d.x, ns = d.y, sg = d.z, slot = d.w;
-      const int32_t e0 = off[v] + sg * kTile;
-      const int32_t e1 = min(e0 + kTile, off[v + 1]);
-      const int32_t n = e1 - e0;
-      constexpr int kPer = kTile / kBlock;
-      int32_t u[kPer];
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const int j = t + k * kBlock;
-        u[k] = j < n ? idx[e0 + j] : -1;
-      }
+      // ---- one segment [e0, e1) (at most kSeg entries) of a long row, summed by the block
+      const int32_t v = d.x, slot = d.w;
       VT s = (VT)0;
+      for (int32_t c = e0; c < e1; c += kSpan) {
+        const int32_t n = min(kSpan, e1 - c);
+        int32_t u[kPer];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) s += u[k] >= 0 ? yin[u[k]] : (VT)0;
+        for (int k = 0; k < kPer; ++k) {
+          const int j = t + k * kBlock;
+          u[k] = j < n ? __builtin_nontemporal_load(idx + c + j) : -1;
+        }
+        VT x[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? yin[u[k]] : (VT)0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) s += x[k];
+      }
       const double seg = block_sum((double)s, red);
       if (t == 0) {
-        p.hpart[slot + sg] = seg;
-        __threadfence();
-        const uint32_t tk = atomicAdd(&p.hcnt[slot], 1u);
-        s_last = tk == (uint32_t)(ns - 1);
+        if (slot < 0)
+          epilogue<VT>(v, seg, c0, alpha, p.outdeg[v], yin[v], yout, a);
+        else
+          p.hpart[slot] = seg;
       }
-      __syncthreads();
-      if (s_last) {
-        __threadfence();
-        double h = 0.0;
-        for (int32_t q = t; q < ns; q += kBlock) h += p.hpart[slot + q];
-        h = block_sum(h, red);
-        if (t == 0) {
-          p.hcnt[slot] = 0;
-          epilogue<VT>(v, h, c0, alpha, p.outdeg, yin, yout, a);
-        }
-      }
-      __syncthreads();
     }
   }
 
-  // ---- block partials, then the last block reduces them in block order
-  const double l1 = block_sum(a.l1, red);
-  const double sq = block_sum(a.sq, red);
-  double mx = wave_max(a.mx);
-  __syncthreads();
-  if (lane == 0) red[t >> 6] = mx;
-  __syncthreads();
-  mx = red[0];
-#pragma unroll
-  for (int i = 1; i < kWaves; ++i) mx = fmax(mx, red[i]);
-  const double dang = block_sum(a.dang, red);
+  const double l1 = block_sum_n<kBlock>(a.l1, red);
+  const double sq = block_sum_n<kBlock>(a.sq, red);
+  const double mx = block_max_n<kBlock>(a.mx, red);
+  const double dang = block_sum_n<kBlock>(a.dang, red);
   if (t == 0) {
     double *bp = p.bpart + 4 * (int64_t)blockIdx.x;
     bp[0] = l1;
     bp[1] = sq;
     bp[2] = mx;
     bp[3] = dang;
-    __threadfence();
-    const uint32_t tk = atomicAdd(&p.st->ticket, 1u);
-    s_last = tk == gridDim.x - 1;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double r1 = 0.0, r2 = 0.0, r3 = 0.0, r4 = 0.0;
-  for (int32_t b = t; b < (int32_t)gridDim.x; b += kBlock) {
+}
+
+// One block: hub rows (segment partials combined in segment order, then the epilogue), the
+// update kernel's block partials in block order, and the finalize.
+template <typename VT>
+__global__ __launch_bounds__(kFinBlock) void k_finish(IterParams p) {
+  __shared__ double red[kFinBlock / 64];
+  SolveState *st = p.st;
+  if (st->head.stop) return;
+  const double c0 = st->c0;
+  const VT *__restrict__ yin = (const VT *)p.y_in;
+  VT *__restrict__ yout = (VT *)p.y_out;
+  Acc a = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t h = threadIdx.x; h < p.nhubs; h += kFinBlock) {
+    const int4 hb = p.hubs[h];
+    double s = 0.0;
+    for (int32_t q = 0; q < hb.y; ++q) s += p.hpart[hb.z + q];
+    epilogue<VT>(hb.x, s, c0, p.alpha, p.outdeg[hb.x], yin[hb.x], yout, a);
+  }
+  for (int32_t b = threadIdx.x; b < p.grid; b += kFinBlock) {
     const double *bp = p.bpart + 4 * (int64_t)b;
-    r1 += bp[0];
-    r2 += bp[1];
-    r3 = fmax(r3, bp[2]);
-    r4 += bp[3];
+    a.l1 += bp[0];
+    a.sq += bp[1];
+    a.mx = fmax(a.mx, bp[2]);
+    a.dang += bp[3];
   }
-  r1 = block_sum(r1, red);
-  r2 = block_sum(r2, red);
-  r4 = block_sum(r4, red);
-  r3 = wave_max(r3);
-  __syncthreads();
-  if (lane == 0) red[t >> 6] = r3;
-  __syncthreads();
-  double m3 = red[0];
-#pragma unroll
-  for (int i = 1; i < kWaves; ++i) m3 = fmax(m3, red[i]);
-  finalize(p, r1, r2, m3, r4);
+  const double l1 = block_sum_n<kFinBlock>(a.l1, red);
+  const double sq = block_sum_n<kFinBlock>(a.sq, red);
+  const double mx = block_max_n<kFinBlock>(a.mx, red);
+  const double dang = block_sum_n<kFinBlock>(a.dang, red);
+  if (threadIdx.x == 0) finalize(p, l1, sq, mx, dang);
 }
 
 // ------------------------------------------------------------------ init, convert, output
-// y0 from the start vector (or 1/N), and c0 of the first update from its dangling sum.
+// y0 from the start vector (or 1/N); per-block dangling sums of the start vector.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_init(const int32_t *__restrict__ outdeg, int32_t N,
                                                  const double *__restrict__ init, VT *__restrict__ y,
-                                                 double alpha, SolveState *st, double *bpart) {
+                                                 double *bpart) {
 #pragma clang fp contract(off)
   __shared__ double red[kWaves];
-  __shared__ int s_last;
   double dang = 0.0;
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
     const double r0 = init ? init[v] : 1.0 / (double)N;
@@ -298,40 +323,42 @@ __global__ __launch_bounds__(kBlock) void k_init(const int32_t *__restrict__ out
     }
   }
   dang = block_sum(dang, red);
-  if (threadIdx.x == 0) {
-    bpart[blockIdx.x] = dang;
-    __threadfence();
-    s_last = atomicAdd(&st->ticket2, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+  if (threadIdx.x == 0) bpart[blockIdx.x] = dang;
+}
+
+// One block: c0 of the first update from the start vector's dangling sum; resets the state.
+__global__ __launch_bounds__(kFinBlock) void k_init_finish(const double *__restrict__ bpart, int32_t nb, int32_t N,
+                                                           double alpha, SolveState *st) {
+#pragma clang fp contract(off)
+  __shared__ double red[kFinBlock / 64];
   double D = 0.0;
-  for (int32_t b = threadIdx.x; b < (int32_t)gridDim.x; b += kBlock) D += bpart[b];
-  D = block_sum(D, red);
+  for (int32_t b = threadIdx.x; b < nb; b += kFinBlock) D += bpart[b];
+  D = block_sum_n<kFinBlock>(D, red);
   if (threadIdx.x == 0) {
     const double Nd = (double)N;
     st->c0 = (1.0 - alpha) / Nd + (alpha * D) / Nd;
-    st->iter = 0;
-    st->phase_iter = 0;
-    st->stop = 0;
-    st->done = 0;
+    st->head.iter = 0;
+    st->head.phase_iter = 0;
+    st->head.stop = 0;
+    st->head.done = 0;
     st->converged = 0;
     st->met32 = 0;
     st->prev_l1 = __builtin_huge_val();
-    st->ticket = 0;
-    st->ticket2 = 0;
   }
 }
 
-// Float32 iterate -> float64 iterate (same implied ranks), and re-arm the update kernels.
+// Float32 iterate -> float64 iterate (same implied ranks).
 __global__ __launch_bounds__(kBlock) void k_convert(const float *__restrict__ y32, double *__restrict__ y64,
-                                                    int32_t N, SolveState *st) {
+                                                    int32_t N) {
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock)
     y64[v] = (double)y32[v];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->stop = st->done;
-    st->phase_iter = 0;
+}
+
+// Re-arm the update kernels for the float64 phase (after k_convert, kernel-ordered).
+__global__ void k_rearm(SolveState *st) {
+  if (threadIdx.x == 0) {
+    st->head.stop = st->head.done;
+    st->head.phase_iter = 0;
   }
 }
 
@@ -357,23 +384,36 @@ hipError_t launch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t 
                        double alpha, SolveState *st, double *bpart, int64_t bpart_cap) {
   const unsigned g = grid_for(N, bpart_cap < 1024 ? bpart_cap : 1024);
   if (fp32)
-    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(kBlock), 0, s, outdeg, N, init, (float *)y, alpha, st, bpart);
+    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(kBlock), 0, s, outdeg, N, init, (float *)y, bpart);
   else
-    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(kBlock), 0, s, outdeg, N, init, (double *)y, alpha, st,
-                       bpart);
+    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(kBlock), 0, s, outdeg, N, init, (double *)y, bpart);
+  hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kFinBlock), 0, s, (const double *)bpart, (int32_t)g, N, alpha, st);
   return hipGetLastError();
 }
 
+// Resident workgroups of the update kernel per compute unit.
+int update_blocks_per_cu(bool fp32) {
+  int n = 0;
+  hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_update<float>, kBlock, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_update<double>, kBlock, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+// One update = the tile kernel and the one-block finishing kernel.
 hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterParams &p) {
-  if (fp32)
+  if (fp32) {
     hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(kBlock), 0, s, p);
-  else
+    hipLaunchKernelGGL(k_finish<float>, dim3(1), dim3(kFinBlock), 0, s, p);
+  } else {
     hipLaunchKernelGGL(k_update<double>, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(k_finish<double>, dim3(1), dim3(kFinBlock), 0, s, p);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_convert(hipStream_t s, const float *y32, double *y64, int32_t N, SolveState *st) {
-  hipLaunchKernelGGL(k_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32, y64, N, st);
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32, y64, N);
+  hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

@@ -119,11 +119,13 @@ def test_random_multigraphs(pr, ctx, seed):
 
 
 def test_hub_segments_and_mid_rows(pr, ctx):
-    # in-degrees spanning thread rows (<=32), wave rows (33..1024) and multi-segment hubs (>1024)
+    # in-degrees spanning lane rows (<=32), wave rows (33..1024), one-segment long rows
+    # (1025..8192) and hubs of several 8192-entry segments, with ragged ends
     rng = np.random.default_rng(5)
-    N = 20000
+    N = 40000
     src, dst = [], []
-    for v, deg in ((0, 5000), (17, 1025), (18, 1024), (19, 2049), (300, 40), (301, 33), (302, 32), (9999, 4097)):
+    for v, deg in ((0, 5000), (17, 1025), (18, 1024), (19, 2049), (300, 40), (301, 33), (302, 32), (9999, 4097),
+                   (20000, 8192), (20001, 8193), (20002, 30001), (39999, 16384)):
         s = rng.choice(N, size=deg, replace=False)
         src.extend(s.tolist())
         dst.extend([v] * deg)
@@ -189,7 +191,7 @@ def test_loop_modes_and_grids_agree(pr, ctx):
     dg = dev(pr, g)
     ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-10, norm=2)
     try:
-        for loop, grid, chunk in ((1, 2048, 8), (0, 7, 4), (0, 64, 16), (1, 1, 2)):
+        for loop, grid, chunk in ((1, 2048, 8), (0, 7, 4), (0, 64, 16), (1, 1, 2), (0, 16384, 8)):
             ctx.set_option("loop", loop)
             ctx.set_option("grid", grid)
             ctx.set_option("chunk", chunk)
@@ -198,7 +200,7 @@ def test_loop_modes_and_grids_agree(pr, ctx):
             assert np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
     finally:
         ctx.set_option("loop", 0)
-        ctx.set_option("grid", 2048)
+        ctx.set_option("grid", 0)
         ctx.set_option("chunk", 8)
 
 
