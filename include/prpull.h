@@ -99,6 +99,8 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value);
 enum {
   PR_KERNEL_UPDATE_F64 = 0, /* one float64 update of pr_pull */
   PR_KERNEL_UPDATE_F32 = 1, /* one float32 update (PR_MIXED first phase) */
+  PR_KERNEL_BATCH_F64 = 2,  /* one float64 update of pr_pull_batch (all active columns) */
+  PR_KERNEL_BATCH_F32 = 3,  /* one float32 update of pr_pull_batch */
   PR_KERNEL_KINDS = 8
 };
 
@@ -151,6 +153,41 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
             const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double alpha, double tau,
             int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
             double *norm_trace, void *workspace, size_t workspace_bytes, pr_result *out);
+
+/* ------------------------------------------------------------------ several problems, one graph */
+
+/* One problem of a batch: the parameters of sections 2 and 3 for one rank vector. */
+typedef struct {
+  double alpha;     /* damping factor in [0, 1] */
+  double tau;       /* tolerance >= 0 */
+  int32_t norm;     /* PR_L1, PR_L2 or PR_LINF */
+  int32_t max_iter; /* >= 1 */
+} pr_problem;
+
+/* Device workspace bytes of pr_pull_batch for K problems (1..16). */
+size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep);
+
+/* K problems on one graph in one pass per update over its edges: the damping-factor sweep of
+ * section 2 (and any mix of tolerances and error functions of sections 3-4).  The K rank
+ * vectors are iterated together as rows of a K-wide array, so each in-edge fetches one row
+ * for every problem; each problem keeps its own teleport term, error, stopping decision and
+ * iteration count, and stops being updated once it stops (its ranks are those of its own
+ * last update, exactly as if solved alone).
+ *   K          : 1..16
+ *   probs      : host, K problems
+ *   precision  : PR_FP64, or PR_MIXED (a float32 phase for all columns, then float64 updates
+ *                until each column's float64 update meets its tau)
+ *   init       : host array of K device pointers (N values each; an entry may be NULL for 1/N),
+ *                or NULL for all-uniform starts
+ *   ranks      : host array of K device pointers (N values each, out)
+ *   norm_trace : host array of K device pointers (max_iter x 3 values each) or NULL
+ *   results    : host, K entries
+ * Returns PR_OK when every problem converged, PR_NOT_CONVERGED when at least one hit its
+ * max_iter (see results[k].converged), or a negative status. */
+int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                  const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
+                  int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
+                  void *workspace, size_t workspace_bytes, pr_result *results);
 
 #ifdef __cplusplus
 }

@@ -15,10 +15,10 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
-from ._lib import (PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK, PrError,  # noqa: F401
-                   pr_result)
+from ._lib import (MAX_COLS, PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK,  # noqa: F401
+                   PrError, pr_problem, pr_result)
 
-__all__ = ["Context", "DeviceGraph", "pull", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
+__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
 
 
 def _require_gpu():
@@ -95,11 +95,14 @@ class DeviceGraph:
                                                     self.prep.data_ptr(), nbytes))
         return self
 
-    def workspace(self, ctx: Context, precision: int, with_prep: bool) -> torch.Tensor:
-        key = (precision, with_prep)
+    def workspace(self, ctx: Context, precision: int, with_prep: bool, K: int = 0) -> torch.Tensor:
+        key = (precision, with_prep, K)
         ws = self._ws.get(key)
         if ws is None:
-            nbytes = ctx.lib.pr_workspace_bytes(self.N, self.E, precision, int(with_prep))
+            if K:
+                nbytes = ctx.lib.pr_batch_workspace_bytes(self.N, self.E, K, precision, int(with_prep))
+            else:
+                nbytes = ctx.lib.pr_workspace_bytes(self.N, self.E, precision, int(with_prep))
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)
             self._ws[key] = ws
         return ws
@@ -147,3 +150,58 @@ def pull(ctx: Context, g: DeviceGraph, alpha: float = 0.85, tau: float = 1e-6, n
     res["ranks"] = ranks
     res["trace"] = tr[:res["iterations"]] if trace else None
     return res
+
+
+def pr_pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int, inits, ranks, traces,
+                  workspace: torch.Tensor, use_prep: bool = True) -> tuple[int, list]:
+    """The C entry point pr_pull_batch (at most 16 problems); returns (status, per-problem results)."""
+    K = len(problems)
+    if not 1 <= K <= MAX_COLS:
+        raise ValueError("pr_pull_batch takes 1..16 problems")
+    for t in list(ranks) + [x for x in (inits or []) if x is not None]:
+        if t.dtype != torch.float64 or t.numel() != g.N or not t.is_contiguous() or t.device != g.off.device:
+            raise ValueError("rank vectors must be contiguous float64 tensors of N elements on the graph's device")
+    probs = (pr_problem * K)(*[pr_problem(float(p["alpha"]), float(p["tau"]), int(p["norm"]), int(p["max_iter"]))
+                              for p in problems])
+    for p, tr in zip(problems, traces or [None] * K):
+        if tr is not None and (tr.dtype != torch.float64 or tr.numel() < 3 * int(p["max_iter"])):
+            raise ValueError("a norm trace must be float64 with max_iter*3 elements")
+    vp = ctypes.c_void_p
+    init_arr = (vp * K)(*[_lib.ptr(x) for x in inits]) if inits is not None else None
+    rank_arr = (vp * K)(*[r.data_ptr() for r in ranks])
+    trace_arr = (vp * K)(*[_lib.ptr(x) for x in traces]) if traces is not None else None
+    res = (pr_result * K)()
+    prep = g.prep if use_prep else None
+    st = ctx.lib.pr_pull_batch(ctx.handle, ctx.stream, g.off.data_ptr(), _lib.ptr(g.idx) if g.E else None,
+                               g.outdeg.data_ptr(), g.N, g.E, _lib.ptr(prep), K, probs, int(precision), init_arr,
+                               rank_arr, trace_arr, workspace.data_ptr(), workspace.numel(), res)
+    _lib.check("pr_pull_batch", st)
+    return st, [r.as_dict() for r in res]
+
+
+def pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int = PR_FP64, inits=None, trace: bool = False,
+               ranks=None) -> list:
+    """Solve several problems on one graph together (groups of up to 16 columns per pass).
+
+    problems: list of dicts with alpha, tau, norm, max_iter.  Returns one dict per problem with
+    ranks (tensor), iterations, converged, fp32_iters, fp64_iters, err and trace."""
+    if g.prep is None:
+        g.prepare(ctx)
+    n = len(problems)
+    if ranks is None:
+        ranks = [torch.empty(g.N, dtype=torch.float64, device=g.off.device) for _ in range(n)]
+    traces = ([torch.full((int(p["max_iter"]), 3), float("nan"), dtype=torch.float64, device=g.off.device)
+               for p in problems] if trace else None)
+    out = []
+    for s0 in range(0, n, MAX_COLS):
+        sl = slice(s0, min(n, s0 + MAX_COLS))
+        K = sl.stop - sl.start
+        ws = g.workspace(ctx, precision, False, K)
+        st, res = pr_pull_batch(ctx, g, problems[sl], precision, inits[sl] if inits is not None else None,
+                                ranks[sl], traces[sl] if traces is not None else None, ws)
+        for j, r in enumerate(res):
+            r["status"] = st
+            r["ranks"] = ranks[sl.start + j]
+            r["trace"] = traces[sl.start + j][:r["iterations"]] if trace else None
+            out.append(r)
+    return out

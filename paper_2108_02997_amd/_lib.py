@@ -18,7 +18,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
 PR_FP64, PR_MIXED = 0, 1
-PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32 = 0, 1
+PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32 = 0, 1, 2, 3
+MAX_COLS = 16
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EGRAPH = 0, 1, -1, -2, -3, -4
 STATUS_NAMES = {0: "PR_OK", 1: "PR_NOT_CONVERGED", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE",
                 -4: "PR_EGRAPH"}
@@ -31,6 +32,11 @@ class pr_result(ctypes.Structure):
     def as_dict(self):
         return dict(iterations=self.iterations, converged=bool(self.converged), fp32_iters=self.fp32_iters,
                     fp64_iters=self.fp64_iters, err=tuple(self.final_err))
+
+
+class pr_problem(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tau", ctypes.c_double), ("norm", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32)]
 
 
 class PrError(RuntimeError):
@@ -55,6 +61,10 @@ SIGNATURES = {
     "pr_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "pr_pull": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz,
                  ctypes.POINTER(pr_result)], ctypes.c_int),
+    "pr_batch_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
+    "pr_pull_batch": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem), _i32,
+                       ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _sz,
+                       ctypes.POINTER(pr_result)], ctypes.c_int),
 }
 
 _lib = None

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/prpull.h"
+#include "batch.h"
 #include "internal.h"
 
 namespace prpull {
@@ -71,6 +72,8 @@ struct pr_ctx {
   hipStream_t capture = nullptr;  // private stream used only for graph capture
   SolveState *hstate = nullptr;   // pinned host copy of the solve state
   unsigned long long *hscratch = nullptr;  // pinned host words for small read-backs
+  BatchCols *hcols = nullptr;             // pinned staging of per-column parameters
+  BatchState *hbstate = nullptr;          // pinned host copy of a batch state
   std::map<const void *, PrepHeader> preps;  // prep buffers prepared in this context
   std::vector<GraphEntry> graphs;
   uint64_t clock = 0;
@@ -327,6 +330,59 @@ ChunkSpec update_chunk(pr_ctx *ctx, bool fp32, unsigned grid, const IterParams &
   return c;
 }
 
+// Workspace layout of a K-column solve.
+struct BatchLayout {
+  BatchState *st;
+  BatchCols *cols;
+  double *bpart;
+  double *hpart;
+  float *y32[2];
+  double *y64[2];
+  void *prep;
+  size_t total;
+};
+
+int batch_cols_per_lane(int K) { return (K + 3) / 4; }
+
+BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t precision, bool with_prep) {
+  Carver c(ws);
+  BatchLayout L{};
+  const int64_t kp = 4 * batch_cols_per_lane(K);
+  L.st = (BatchState *)c.take(sizeof(BatchState));
+  L.cols = (BatchCols *)c.take(sizeof(BatchCols));
+  L.bpart = (double *)c.take(sizeof(double) * 4 * kMaxCols * (size_t)kMaxGrid);
+  L.hpart = (double *)c.take(sizeof(double) * kMaxCols * (size_t)max_slots(N, E));
+  if (precision == PR_MIXED) {
+    L.y32[0] = (float *)c.take(sizeof(float) * (size_t)(N * kp));
+    L.y32[1] = (float *)c.take(sizeof(float) * (size_t)(N * kp));
+  }
+  L.y64[0] = (double *)c.take(sizeof(double) * (size_t)(N * kp));
+  L.y64[1] = (double *)c.take(sizeof(double) * (size_t)(N * kp));
+  L.prep = with_prep ? c.take(prep_bytes(N, E)) : nullptr;
+  L.total = c.used;
+  return L;
+}
+
+ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int C, unsigned grid, const BatchParams &p, void *b0, void *b1) {
+  ChunkSpec c;
+  c.kind = fp32 ? PR_KERNEL_BATCH_F32 : PR_KERNEL_BATCH_F64;
+  c.count = (int)ctx->chunk;
+  BatchParams q = p;
+  q.y_in = b0;
+  q.y_out = b1;
+  const int64_t meta[2] = {grid, C};
+  c.key.resize(sizeof q + sizeof meta);
+  memcpy(c.key.data(), &q, sizeof q);
+  memcpy(c.key.data() + sizeof q, meta, sizeof meta);
+  c.launch = [fp32, C, grid, p, b0, b1](hipStream_t s, int k) {
+    BatchParams r = p;
+    r.y_in = (k & 1) ? b1 : b0;
+    r.y_out = (k & 1) ? b0 : b1;
+    return launch_batch_update(s, fp32, C, grid, r);
+  };
+  return c;
+}
+
 }  // namespace
 
 extern "C" {
@@ -357,11 +413,15 @@ int pr_create(pr_ctx **out, int device) {
   hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hstate, sizeof(SolveState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscratch, 64 * sizeof(unsigned long long), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hcols, sizeof(BatchCols), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hbstate, sizeof(BatchState), hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error("pr_create: %s", hipGetErrorString(e));
     if (c->capture) (void)hipStreamDestroy(c->capture);
     if (c->hstate) (void)hipHostFree(c->hstate);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
+    if (c->hcols) (void)hipHostFree(c->hcols);
+    if (c->hbstate) (void)hipHostFree(c->hbstate);
     delete c;
     return PR_EDEVICE;
   }
@@ -380,6 +440,8 @@ void pr_destroy(pr_ctx *ctx) {
   if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
   if (ctx->hscratch) (void)hipHostFree(ctx->hscratch);
+  if (ctx->hcols) (void)hipHostFree(ctx->hcols);
+  if (ctx->hbstate) (void)hipHostFree(ctx->hbstate);
   delete ctx;
 }
 
@@ -602,6 +664,145 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   out->final_err[1] = hs.err[1];
   out->final_err[2] = hs.err[2];
   return hs.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep) {
+  if (N < 1 || E < 0 || K < 1 || K > kMaxCols || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
+  return carve_batch(nullptr, N, E, K, precision, with_prep != 0).total;
+}
+
+int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                  const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
+                  int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
+                  void *workspace, size_t workspace_bytes, pr_result *results) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !probs || !workspace || !results || (E > 0 && !in_indices)) {
+    set_error("pr_pull_batch: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (K < 1 || K > kMaxCols) {
+    set_error("K must be in [1, %d], got %d", kMaxCols, K);
+    return PR_EINVAL;
+  }
+  if (precision != PR_FP64 && precision != PR_MIXED) {
+    set_error("precision must be PR_FP64 or PR_MIXED, got %d", precision);
+    return PR_EINVAL;
+  }
+  for (int k = 0; k < K; ++k) {
+    const pr_problem &q = probs[k];
+    if (!(q.alpha >= 0.0 && q.alpha <= 1.0) || !(q.tau >= 0.0) || q.norm < PR_L1 || q.norm > PR_LINF ||
+        q.max_iter < 1 || !ranks[k]) {
+      set_error("problem %d: alpha in [0,1], tau >= 0, norm 1..3, max_iter >= 1 and a ranks buffer are required", k);
+      return PR_EINVAL;
+    }
+  }
+  const BatchLayout L = carve_batch(workspace, N, E, K, precision, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_pull_batch: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc;
+  const void *pp = prep;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+  const int C = batch_cols_per_lane(K);
+  const int kp = 4 * C;
+  int max_iter = 1;
+  BatchCols &hc = *ctx->hcols;
+  memset(&hc, 0, sizeof hc);
+  for (int k = 0; k < K; ++k) {
+    hc.alpha[k] = probs[k].alpha;
+    hc.tau[k] = probs[k].tau;
+    hc.norm[k] = probs[k].norm;
+    hc.max_iter[k] = probs[k].max_iter;
+    hc.init[k] = init ? init[k] : nullptr;
+    hc.ranks[k] = ranks[k];
+    hc.trace[k] = norm_trace ? norm_trace[k] : nullptr;
+    max_iter = std::max(max_iter, probs[k].max_iter);
+  }
+  PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(BatchState) / 4, 0u));
+
+  BatchParams p{};
+  p.off = in_offsets;
+  p.idx = in_indices;
+  p.outdeg = outdeg;
+  p.desc = (const int4 *)((const char *)pp + h.desc_off);
+  p.ndesc = h.ndesc;
+  p.N = (int32_t)N;
+  p.K = K;
+  p.nhubs = h.nhubs;
+  p.hubs = (const int4 *)((const char *)pp + h.hub_off);
+  p.bpart = L.bpart;
+  p.hpart = L.hpart;
+  p.st = L.st;
+  p.cols = L.cols;
+
+  auto grid_of = [&](bool fp32) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+      cus = 1;
+    const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, C);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)h.ndesc, res, kMaxGrid}));
+  };
+  int fbuf = 0;
+  bool final_fp32 = false;
+  const void *fa = nullptr, *fb = nullptr;
+  if (precision == PR_MIXED) {
+    p.phase = 1;
+    p.grid = (int32_t)grid_of(true);
+    PR_HIP(launch_batch_init(s, true, outdeg, (int32_t)N, K, kp, L.y32[0], L.bpart, kMaxGrid, p, 1));
+    rc = run_until_stop(ctx, s, batch_chunk(ctx, true, C, (unsigned)p.grid, p, L.y32[0], L.y32[1]), &L.st->head,
+                        max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    if (((LoopHead *)ctx->hstate)->done) {
+      fa = L.y32[0];
+      fb = L.y32[1];
+      final_fp32 = true;
+    } else {
+      PR_HIP(launch_batch_convert(s, L.y32[0], L.y32[1], kp, L.y64[0], kp, (int32_t)N, K, L.st));
+      p.phase = 2;
+      p.grid = (int32_t)grid_of(false);
+      rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C, (unsigned)p.grid, p, L.y64[0], L.y64[1]),
+                          &L.st->head, max_iter, &fbuf);
+      if (rc != PR_OK) return rc;
+      fa = L.y64[0];
+      fb = L.y64[1];
+    }
+  } else {
+    p.phase = 0;
+    p.grid = (int32_t)grid_of(false);
+    PR_HIP(launch_batch_init(s, false, outdeg, (int32_t)N, K, kp, L.y64[0], L.bpart, kMaxGrid, p, 0));
+    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
+                        max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    fa = L.y64[0];
+    fb = L.y64[1];
+  }
+  PR_HIP(launch_batch_output(s, final_fp32, outdeg, fa, fb, kp, (int32_t)N, K, p));
+  PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  int all = 1;
+  for (int k = 0; k < K; ++k) {
+    const BatchColumn &cs = ctx->hbstate->col[k];
+    results[k].iterations = cs.iters;
+    results[k].converged = cs.converged;
+    results[k].fp32_iters = cs.fp32_iters;
+    results[k].fp64_iters = cs.iters - cs.fp32_iters;
+    results[k].final_err[0] = cs.err[0];
+    results[k].final_err[1] = cs.err[1];
+    results[k].final_err[2] = cs.err[2];
+    all &= cs.converged;
+  }
+  return all ? PR_OK : PR_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -1,0 +1,114 @@
+// batch.h -- device state and parameters of the K-column solves (batch.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace prpull {
+
+constexpr int kMaxCols = 16;
+
+struct BatchColumn {
+  double c0;        // teleport term of the column's next update
+  double err[3];    // L1, L2, Linf of its last update
+  double prev_l1;   // L1 of the update before (float32 stagnation test)
+  int32_t iters;    // updates of this column, all phases
+  int32_t fp32_iters;
+  int32_t phase_updates;  // updates in the running phase (its parity names the newest buffer)
+  int32_t converged;
+  int32_t done;     // 1: no further updates in any phase
+  int32_t active;   // 1: updated by the running phase
+  int32_t met32;
+  int32_t pad;
+};
+
+struct alignas(64) BatchState {
+  LoopHead head;    // stop: no active column left in the running phase
+  int32_t phase;    // 0: float64 solve, 1: float32 phase of a mixed solve, 2: its float64 phase
+  int32_t pad[3];
+  BatchColumn col[kMaxCols];
+};
+
+// Per-column parameters, in device memory (written once per solve).
+struct BatchCols {
+  double alpha[kMaxCols];
+  double tau[kMaxCols];
+  int32_t norm[kMaxCols];
+  int32_t max_iter[kMaxCols];
+  const double *init[kMaxCols];
+  double *ranks[kMaxCols];
+  double *trace[kMaxCols];
+};
+
+struct BatchParams {
+  const int32_t *off;
+  const int32_t *idx;
+  const int32_t *outdeg;
+  const int4 *desc;
+  int32_t ndesc;
+  int32_t N;
+  const void *y_in;
+  void *y_out;
+  int32_t K;       // columns (problems), 1..16
+  int32_t grid;    // blocks of the update launch
+  int32_t nhubs;
+  int32_t phase;
+  const int4 *hubs;
+  double *bpart;   // [grid][Kp][4]
+  double *hpart;   // [slots][Kp]
+  BatchState *st;
+  const BatchCols *cols;
+};
+
+// Finalize column k of one update (one lane per column).
+__device__ __forceinline__ void batch_finalize_column(const BatchParams &p, int k, double l1, double sq, double mx,
+                                                      double dang) {
+#pragma clang fp contract(off)
+  BatchColumn &cs = p.st->col[k];
+  const double e[3] = {l1, sqrt(sq), mx};
+  cs.err[0] = e[0];
+  cs.err[1] = e[1];
+  cs.err[2] = e[2];
+  const int32_t it = cs.iters + 1;
+  cs.iters = it;
+  cs.phase_updates += 1;
+  if (p.phase == 1) cs.fp32_iters += 1;
+  const BatchCols &cp = *p.cols;
+  if (cp.trace[k]) {
+    cp.trace[k][3 * (int64_t)(it - 1) + 0] = e[0];
+    cp.trace[k][3 * (int64_t)(it - 1) + 1] = e[1];
+    cp.trace[k][3 * (int64_t)(it - 1) + 2] = e[2];
+  }
+  const double N = (double)p.N;
+  cs.c0 = (1.0 - cp.alpha[k]) / N + (cp.alpha[k] * dang) / N;
+  const int nk = cp.norm[k];
+  const bool met = (nk == 1 ? e[0] : nk == 2 ? e[1] : e[2]) < cp.tau[k];
+  if (p.phase == 1) {
+    if (met) cs.met32 = 1;
+    if (met || !(l1 < cs.prev_l1)) cs.active = 0;
+    cs.prev_l1 = l1;
+    if (it >= cp.max_iter[k]) {
+      cs.active = 0;
+      cs.done = 1;
+    }
+  } else {
+    if (met) {
+      cs.converged = 1;
+      cs.active = 0;
+      cs.done = 1;
+    } else if (it >= cp.max_iter[k]) {
+      cs.active = 0;
+      cs.done = 1;
+    }
+  }
+}
+
+hipError_t launch_batch_update(hipStream_t s, bool fp32, int C, unsigned grid, const BatchParams &p);
+int batch_blocks_per_cu(bool fp32, int C);
+hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
+                             void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase);
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
+                                int32_t kp64, int32_t N, int32_t K, BatchState *st);
+hipError_t launch_batch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *ya, const void *yb,
+                               int32_t kp, int32_t N, int32_t K, const BatchParams &p);
+
+}  // namespace prpull

@@ -1,0 +1,536 @@
+// batch.hip -- K rank columns of one graph in one pass over its edges (paper, section 2
+// update, run for several damping factors / tolerances / error functions at once).
+//
+// State: Y[N][Kp] in the phase's type VT (Kp = 4*C, C = columns per lane, at most 16 columns),
+// row-major, so one in-edge u -> v costs one contiguous Kp*sizeof(VT)-byte row fetch that
+// serves every column: y[u][k] = r_k[u]/d_u (or r_k[u] for a dangling u), as in pull.hip.
+// A quad of four lanes owns one row fetch; lane (l & 3) handles columns (l & 3)*C .. +C-1.
+//   short rows (in-degree <= kMidDeg): one quad per row, entries in ascending order;
+//   mid rows: one wave per row, entry j on quad j % 16, xor reduction across the quads;
+//   long-row segments: one block per segment, reduction across quads and waves; hubs leave
+//   per-column segment partials for k_batch_finish.
+// Every column has its own c0, alpha, tau, norm, iteration count and stop decision; a column
+// that stops is masked (no writes) and keeps its last iterate in the buffer given by its own
+// update parity.  k_batch_finish (one block) combines hubs, reduces the block partials per
+// column in block order and finalizes every active column.
+#include "batch.h"
+
+namespace prpull {
+
+template <typename T>
+__device__ __forceinline__ T xor_sum_quads(T v) {
+  // sum over the 16 quads of a wave; lanes with equal (lane & 3) end with equal bits
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ __forceinline__ double xor_max_quads(double v) {
+  v = fmax(v, __shfl_xor(v, 4, 64));
+  v = fmax(v, __shfl_xor(v, 8, 64));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  v = fmax(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
+template <typename VT, int C>
+struct Row {
+  VT v[C];
+};
+
+template <typename VT, int C>
+__device__ __forceinline__ Row<VT, C> load_row(const VT *__restrict__ y, int32_t u, int kp, int c0) {
+  Row<VT, C> r;
+  const VT *p = y + (int64_t)u * kp + c0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) r.v[c] = p[c];
+  return r;
+}
+
+struct BAcc {
+  double l1, sq, mx, dang;
+};
+
+// Per-column epilogue of one row for the lane's C columns.
+template <typename VT, int C>
+__device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VT *__restrict__ yin,
+                                               VT *__restrict__ yout, int kp, int col0, const double (&c0)[C],
+                                               const double (&alpha)[C], const bool (&act)[C], BAcc (&a)[C]) {
+#pragma clang fp contract(off)
+  const int64_t base = (int64_t)v * kp + col0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    if (!act[c]) continue;
+    const double rn = c0[c] + alpha[c] * s[c];
+    const VT yo = yin[base + c];
+    double old, rnew;
+    if (dv > 0) {
+      old = (double)yo * (double)dv;
+      const VT y = (VT)(rn / (double)dv);
+      yout[base + c] = y;
+      rnew = sizeof(VT) == 8 ? rn : (double)y * (double)dv;
+    } else {
+      old = (double)yo;
+      const VT y = (VT)rn;
+      yout[base + c] = y;
+      rnew = (double)y;
+      a[c].dang += rnew;
+    }
+    const double d = fabs(rnew - old);
+    a[c].l1 += d;
+    a[c].sq += d * d;
+    a[c].mx = fmax(a[c].mx, d);
+  }
+}
+
+template <typename VT, int C>
+__global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
+  constexpr int KP = 4 * C;
+  __shared__ int32_t sidx[kSpan];
+  __shared__ double sred[kWaves][KP];
+  __shared__ double sacc[kWaves][KP][4];
+  const BatchState *st = p.st;
+  if (st->head.stop) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int qp = lane & 3, quad = t >> 2;  // quad 0..63 in the block
+  const int col0 = qp * C;
+  double c0[C], alpha[C];
+  bool act[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = col0 + c;
+    act[c] = k < p.K && st->col[k].active;
+    c0[c] = st->col[k].c0;
+    alpha[c] = p.cols->alpha[k];
+  }
+  const VT *__restrict__ yin = (const VT *)p.y_in;
+  VT *__restrict__ yout = (VT *)p.y_out;
+  const int32_t *__restrict__ off = p.off;
+  const int32_t *__restrict__ idx = p.idx;
+  BAcc a[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) a[c] = BAcc{0.0, 0.0, 0.0, 0.0};
+
+  for (int32_t i = blockIdx.x; i < p.ndesc; i += gridDim.x) {
+    const int4 d = p.desc[i];
+    const int4 dn = p.desc[i + 1];
+    const int32_t e0 = d.y, e1 = dn.y;
+    if (d.z < 0) {
+      // ---- tile of short rows: stage the index slice, then rows by quads (short) / waves (mid)
+      const int32_t v0 = d.x, v1 = dn.x, n = e1 - e0;
+      for (int j = t; j < n; j += kBlock) sidx[j] = __builtin_nontemporal_load(idx + e0 + j);
+      __syncthreads();
+      const int32_t nrows = v1 - v0;
+      for (int32_t r0 = 0; r0 < nrows; r0 += kBlock / 4) {
+        const int32_t r = r0 + quad;
+        const bool mine = r < nrows;
+        const int32_t v = v0 + r;
+        int32_t ra = 0, rb = 0, dv = 0;
+        if (mine) {
+          ra = off[v] - e0;
+          rb = off[v + 1] - e0;
+          dv = p.outdeg[v];
+        }
+        const bool mid = mine && (rb - ra) > kMidDeg;
+        if (mine && !mid) {
+          VT s[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) s[c] = (VT)0;
+          int32_t j = ra;
+          for (; j + 4 <= rb; j += 4) {
+            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
+            const Row<VT, C> x1 = load_row<VT, C>(yin, sidx[j + 1], KP, col0);
+            const Row<VT, C> x2 = load_row<VT, C>(yin, sidx[j + 2], KP, col0);
+            const Row<VT, C> x3 = load_row<VT, C>(yin, sidx[j + 3], KP, col0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] = (((s[c] + x0.v[c]) + x1.v[c]) + x2.v[c]) + x3.v[c];
+          }
+          for (; j < rb; ++j) {
+            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+          }
+          double sd[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) sd[c] = (double)s[c];
+          batch_epilogue<VT, C>(v, sd, dv, yin, yout, KP, col0, c0, alpha, act, a);
+        }
+        // mid rows of this wave's 16 quads, one at a time, by all 16 quads
+        unsigned long long m = __ballot(mid && qp == 0);
+        while (m) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int32_t wa = __shfl(ra, src, 64), wb = __shfl(rb, src, 64);
+          const int32_t wv = __shfl(v, src, 64), wd = __shfl(dv, src, 64);
+          VT s[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) s[c] = (VT)0;
+          for (int32_t j = wa + (lane >> 2); j < wb; j += 16) {
+            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+          }
+          double sd[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) sd[c] = (double)xor_sum_quads(s[c]);
+          if (lane < 4) batch_epilogue<VT, C>(wv, sd, wd, yin, yout, KP, col0, c0, alpha, act, a);
+        }
+      }
+      __syncthreads();
+    } else {
+      // ---- one segment [e0, e1) of a long row: quads stride the entries
+      const int32_t v = d.x, slot = d.w;
+      VT s[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c] = (VT)0;
+      for (int32_t c8 = e0 + quad; c8 < e1; c8 += 4 * (kBlock / 4)) {
+        int32_t u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int32_t j = c8 + k * (kBlock / 4);
+          u[k] = j < e1 ? __builtin_nontemporal_load(idx + j) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (u[k] >= 0) {
+            const Row<VT, C> x0 = load_row<VT, C>(yin, u[k], KP, col0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+          }
+        }
+      }
+      double tot[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) tot[c] = xor_sum_quads((double)s[c]);
+      __syncthreads();
+      if (lane < 4) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sred[wave][col0 + c] = tot[c];
+      }
+      __syncthreads();
+      if (t < 4) {
+        double segd[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          double x = sred[0][col0 + c];
+#pragma unroll
+          for (int w = 1; w < kWaves; ++w) x += sred[w][col0 + c];
+          segd[c] = x;
+        }
+        if (slot < 0) {
+          // one-segment long row: finish here
+          batch_epilogue<VT, C>(v, segd, p.outdeg[v], yin, yout, KP, col0, c0, alpha, act, a);
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) p.hpart[(int64_t)slot * KP + col0 + c] = segd[c];
+        }
+      }
+    }
+  }
+
+  // ---- block partials per column: lanes with equal qp reduce across quads and waves
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    a[c].l1 = xor_sum_quads(a[c].l1);
+    a[c].sq = xor_sum_quads(a[c].sq);
+    a[c].mx = xor_max_quads(a[c].mx);
+    a[c].dang = xor_sum_quads(a[c].dang);
+  }
+  __syncthreads();
+  if (lane < 4) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sacc[wave][col0 + c][0] = a[c].l1;
+      sacc[wave][col0 + c][1] = a[c].sq;
+      sacc[wave][col0 + c][2] = a[c].mx;
+      sacc[wave][col0 + c][3] = a[c].dang;
+    }
+  }
+  __syncthreads();
+  if (t < KP * 4) {
+    const int k = t >> 2, f = t & 3;
+    double x = sacc[0][k][f];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) x = f == 2 ? fmax(x, sacc[w][k][f]) : x + sacc[w][k][f];
+    p.bpart[((int64_t)blockIdx.x * KP + k) * 4 + f] = x;
+  }
+}
+
+// One block of kFinBlock lanes: lane t works on column t % 16 (columns >= Kp idle).
+template <typename VT, int C>
+__global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
+  constexpr int KP = 4 * C;
+  constexpr int kGroups = kFinBlock / 16;
+  __shared__ double sacc[kGroups][16][4];
+  BatchState *st = p.st;
+  if (st->head.stop) return;
+  const int t = threadIdx.x, k = t & 15, g = t >> 4;
+  const VT *__restrict__ yin = (const VT *)p.y_in;
+  VT *__restrict__ yout = (VT *)p.y_out;
+  BAcc a = {0.0, 0.0, 0.0, 0.0};
+  const bool col = k < p.K && k < KP && st->col[k].active;
+  if (col) {
+    const double c0 = st->col[k].c0, alpha = p.cols->alpha[k];
+    for (int32_t h = g; h < p.nhubs; h += kGroups) {
+      const int4 hb = p.hubs[h];
+      double s = 0.0;
+#pragma unroll 1
+      for (int32_t q = 0; q < hb.y; ++q) s += p.hpart[(int64_t)(hb.z + q) * KP + k];
+      double sv[1] = {s};
+      double c0a[1] = {c0}, ala[1] = {alpha};
+      bool act[1] = {true};
+      BAcc aa[1] = {a};
+      // the epilogue addresses column k of row hb.x
+      batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, c0a, ala, act, aa);
+      a = aa[0];
+    }
+    for (int32_t b = g; b < p.grid; b += kGroups) {
+      const double *bp = p.bpart + ((int64_t)b * KP + k) * 4;
+      a.l1 += bp[0];
+      a.sq += bp[1];
+      a.mx = fmax(a.mx, bp[2]);
+      a.dang += bp[3];
+    }
+  }
+  sacc[g][k][0] = a.l1;
+  sacc[g][k][1] = a.sq;
+  sacc[g][k][2] = a.mx;
+  sacc[g][k][3] = a.dang;
+  __syncthreads();
+  if (t < 16) {
+    double l1 = 0.0, sq = 0.0, mx = 0.0, dang = 0.0;
+#pragma unroll 1
+    for (int gg = 0; gg < kGroups; ++gg) {
+      l1 += sacc[gg][t][0];
+      sq += sacc[gg][t][1];
+      mx = fmax(mx, sacc[gg][t][2]);
+      dang += sacc[gg][t][3];
+    }
+    if (t < p.K && st->col[t].active) batch_finalize_column(p, t, l1, sq, mx, dang);
+  }
+  __syncthreads();
+  if (t == 0) {
+    int any = 0, all_done = 1;
+#pragma unroll 1
+    for (int c = 0; c < p.K; ++c) {
+      any |= st->col[c].active;
+      all_done &= st->col[c].done;
+    }
+    st->head.iter += 1;
+    st->head.phase_iter += 1;
+    st->head.stop = !any;
+    st->head.done = all_done;
+  }
+}
+
+// Start vectors: column k from init[k] (or 1/N); per-block, per-column dangling sums.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_batch_init(const int32_t *__restrict__ outdeg, int32_t N, int32_t K,
+                                                       int32_t kp, BatchParams p, VT *__restrict__ y,
+                                                       double *bpart) {
+#pragma clang fp contract(off)
+  __shared__ double red[kWaves][16];
+  double dang[16];
+  for (int c = 0; c < 16; ++c) dang[c] = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    const int32_t dv = outdeg[v];
+    for (int c = 0; c < kp; ++c) {
+      VT yy = (VT)0;
+      if (c < K) {
+        const double *ini = p.cols->init[c];
+        const double r0 = ini ? ini[v] : 1.0 / (double)N;
+        if (dv > 0) {
+          yy = (VT)(r0 / (double)dv);
+        } else {
+          yy = (VT)r0;
+          dang[c] += (double)yy;
+        }
+      }
+      y[v * kp + c] = yy;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c = 0; c < 16; ++c) {
+    double x = dang[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[w][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double x = red[0][threadIdx.x];
+    for (int i = 1; i < kWaves; ++i) x += red[i][threadIdx.x];
+    bpart[(int64_t)blockIdx.x * 16 + threadIdx.x] = x;
+  }
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_batch_init_finish(const double *__restrict__ bpart, int32_t nb,
+                                                                 int32_t N, BatchParams p, int32_t phase) {
+#pragma clang fp contract(off)
+  constexpr int kGroups = kFinBlock / 16;
+  __shared__ double s[kGroups][16];
+  const int t = threadIdx.x, k = t & 15, g = t >> 4;
+  double D = 0.0;
+  for (int32_t b = g; b < nb; b += kGroups) D += bpart[(int64_t)b * 16 + k];
+  s[g][k] = D;
+  __syncthreads();
+  BatchState *st = p.st;
+  if (t < 16) {
+    double x = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < kGroups; ++i) x += s[i][t];
+    BatchColumn &cs = st->col[t];
+    const double Nd = (double)N;
+    const double al = t < p.K ? p.cols->alpha[t] : 0.0;
+    cs.c0 = (1.0 - al) / Nd + (al * x) / Nd;
+    cs.iters = 0;
+    cs.fp32_iters = 0;
+    cs.phase_updates = 0;
+    cs.converged = 0;
+    cs.done = t < p.K ? 0 : 1;
+    cs.active = t < p.K ? 1 : 0;
+    cs.prev_l1 = __builtin_huge_val();
+    cs.err[0] = cs.err[1] = cs.err[2] = 0.0;
+  }
+  if (t == 0) {
+    st->head.iter = 0;
+    st->head.phase_iter = 0;
+    st->head.stop = 0;
+    st->head.done = 0;
+    st->phase = phase;
+  }
+}
+
+// Float32 columns -> float64 columns (each column from its own latest buffer); re-arm.
+__global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restrict__ y32a, const float *__restrict__ y32b,
+                                                          int32_t kp32, double *__restrict__ y64, int32_t kp64,
+                                                          int32_t N, int32_t K, const BatchState *st) {
+  int par[16];
+  for (int c = 0; c < 16; ++c) par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    for (int c = 0; c < kp64; ++c) {
+      double x = 0.0;
+      if (c < K) x = (double)(par[c] ? y32b : y32a)[v * kp32 + c];
+      y64[v * kp64 + c] = x;
+    }
+  }
+}
+
+__global__ void k_batch_rearm(BatchState *st, int32_t K) {
+  if (threadIdx.x == 0) {
+    int any = 0;
+    for (int c = 0; c < K; ++c) {
+      BatchColumn &cs = st->col[c];
+      cs.phase_updates = 0;
+      cs.active = !cs.done;
+      any |= cs.active;
+    }
+    st->head.phase_iter = 0;
+    st->head.stop = !any;
+    st->phase = 2;
+  }
+}
+
+// ranks[k][v] from the buffer holding column k's newest iterate.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_batch_output(const int32_t *__restrict__ outdeg, const VT *__restrict__ ya,
+                                                         const VT *__restrict__ yb, int32_t kp, int32_t N, int32_t K,
+                                                         BatchParams p) {
+  const BatchState *st = p.st;
+  int par[16];
+  for (int c = 0; c < 16; ++c) par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    const int32_t dv = outdeg[v];
+    for (int c = 0; c < K; ++c) {
+      const double y = (double)(par[c] ? yb : ya)[v * kp + c];
+      p.cols->ranks[c][v] = dv > 0 ? y * (double)dv : y;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned grid_for(int64_t n, int64_t cap) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <typename VT>
+static hipError_t batch_update_c(hipStream_t s, int C, unsigned grid, const BatchParams &p) {
+  switch (C) {
+    case 1:
+      hipLaunchKernelGGL((k_batch_update<VT, 1>), dim3(grid), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((k_batch_finish<VT, 1>), dim3(1), dim3(kFinBlock), 0, s, p);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_batch_update<VT, 2>), dim3(grid), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((k_batch_finish<VT, 2>), dim3(1), dim3(kFinBlock), 0, s, p);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_batch_update<VT, 3>), dim3(grid), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((k_batch_finish<VT, 3>), dim3(1), dim3(kFinBlock), 0, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL((k_batch_update<VT, 4>), dim3(grid), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((k_batch_finish<VT, 4>), dim3(1), dim3(kFinBlock), 0, s, p);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_update(hipStream_t s, bool fp32, int C, unsigned grid, const BatchParams &p) {
+  return fp32 ? batch_update_c<float>(s, C, grid, p) : batch_update_c<double>(s, C, grid, p);
+}
+
+int batch_blocks_per_cu(bool fp32, int C) {
+  int n = 0;
+  hipError_t e;
+  if (fp32) {
+    e = C == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 1>, kBlock, 0)
+      : C == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 2>, kBlock, 0)
+      : C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 3>, kBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 4>, kBlock, 0);
+  } else {
+    e = C == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 1>, kBlock, 0)
+      : C == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 2>, kBlock, 0)
+      : C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 3>, kBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 4>, kBlock, 0);
+  }
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
+                             void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase) {
+  const unsigned g = grid_for(N, bpart_blocks < 1024 ? bpart_blocks : 1024);
+  if (fp32)
+    hipLaunchKernelGGL(k_batch_init<float>, dim3(g), dim3(kBlock), 0, s, outdeg, N, K, kp, p, (float *)y, bpart);
+  else
+    hipLaunchKernelGGL(k_batch_init<double>, dim3(g), dim3(kBlock), 0, s, outdeg, N, K, kp, p, (double *)y, bpart);
+  hipLaunchKernelGGL(k_batch_init_finish, dim3(1), dim3(kFinBlock), 0, s, (const double *)bpart, (int32_t)g, N, p,
+                     phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
+                                int32_t kp64, int32_t N, int32_t K, BatchState *st) {
+  hipLaunchKernelGGL(k_batch_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32a, y32b, kp32, y64, kp64, N,
+                     K, (const BatchState *)st);
+  hipLaunchKernelGGL(k_batch_rearm, dim3(1), dim3(64), 0, s, st, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *ya, const void *yb,
+                               int32_t kp, int32_t N, int32_t K, const BatchParams &p) {
+  if (fp32)
+    hipLaunchKernelGGL(k_batch_output<float>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, outdeg,
+                       (const float *)ya, (const float *)yb, kp, N, K, p);
+  else
+    hipLaunchKernelGGL(k_batch_output<double>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, outdeg,
+                       (const double *)ya, (const double *)yb, kp, N, K, p);
+  return hipGetLastError();
+}
+
+}  // namespace prpull

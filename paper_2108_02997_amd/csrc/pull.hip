@@ -98,7 +98,7 @@ __device__ __forceinline__ void finalize(const IterParams &p, double l1, double 
   }
   const double N = (double)p.N;
   st->c0 = (1.0 - p.alpha) / N + (p.alpha * dang) / N;
-  const bool met = e[p.norm - 1] < p.tau;
+  const bool met = (p.norm == 1 ? e[0] : p.norm == 2 ? e[1] : e[2]) < p.tau;
   if (p.phase == 1) {
     // float32 phase: hand over to float64 once tau is met or the L1 change stops shrinking
     // (in exact arithmetic the L1 change never grows: the update is an alpha-contraction in L1)

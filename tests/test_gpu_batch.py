@@ -1,0 +1,163 @@
+"""Parity of the K-column path (pr_pull_batch) and of mixed precision with the CPU oracle.
+
+Every column of a batch must match its own single-problem oracle run: same iteration count
+(tie margin as in test_gpu_pull) and, in FP64, ranks within 1e-12 in L1.  Mixed-precision
+results are checked against the L1 fixed-point bound of the section-2 map: for alpha < 1,
+||r_k - r*||_1 <= alpha/(1-alpha) * ||r_k - r_{k-1}||_1, so two solves whose last L1 changes are
+e_a and e_b differ by at most alpha/(1-alpha) * (e_a + e_b), plus float64 rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_pull import iterations_ok  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2108_02997_amd as pr
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return pr
+
+
+@pytest.fixture(scope="module")
+def ctx(pr):
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def sweep_problems(tau=1e-10, norm=3, max_iter=500):
+    return [dict(alpha=a, tau=tau, norm=norm, max_iter=max_iter) for a in gg.ALPHA_SWEEP]
+
+
+def check_column(res, g, p, init=None, l1_tol=1e-12):
+    ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"], max_iter=p["max_iter"],
+                                init=init, trace=True)
+    assert iterations_ok(res["iterations"], ref, p["tau"], p["norm"]), (p, res["iterations"], ref["iterations"])
+    if res["iterations"] == ref["iterations"]:
+        d = np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert d <= l1_tol, (p, d)
+        assert res["converged"] == ref["converged"]
+    return ref
+
+
+@pytest.mark.parametrize("make", [gg.workload_c1, lambda: gg.rmat(15, seed=7)])
+def test_alpha_sweep_fp64(pr, ctx, make):
+    g = make()
+    dg = pr.DeviceGraph.from_host(g)
+    probs = sweep_problems()
+    res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_FP64, trace=True)
+    for r, p in zip(res, probs):
+        ref = check_column(r, g, p)
+        if r["iterations"] == ref["iterations"]:
+            atol = 2.0 ** -50 * (g.N + 16)
+            np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 8, 9, 12, 13, 16])
+def test_column_counts_and_mixed_settings(pr, ctx, K):
+    g = gg.rmat(13, seed=K)
+    dg = pr.DeviceGraph.from_host(g)
+    rng = np.random.default_rng(K)
+    probs = [dict(alpha=float(rng.choice([0.5, 0.85, 0.95, 1.0])), tau=float(rng.choice([1e-4, 1e-8, 1e-11])),
+                  norm=int(rng.integers(1, 4)), max_iter=int(rng.choice([3, 500]))) for _ in range(K)]
+    res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_FP64)
+    for r, p in zip(res, probs):
+        check_column(r, g, p)
+
+
+def test_more_than_sixteen_problems_are_grouped(pr, ctx):
+    g = gg.workload_c1()
+    dg = pr.DeviceGraph.from_host(g)
+    probs = [dict(alpha=a, tau=t, norm=n, max_iter=500) for a in gg.ALPHA_SWEEP for t, n in ((1e-6, 1), (1e-9, 3))]
+    res = pr.pull_batch(ctx, dg, probs)
+    assert len(res) == 22
+    for r, p in zip(res, probs):
+        check_column(r, g, p)
+
+
+def test_per_column_starts(pr, ctx):
+    g = gg.rmat(12, seed=3)
+    dg = pr.DeviceGraph.from_host(g)
+    rng = np.random.default_rng(0)
+    starts = []
+    for _ in range(3):
+        x = rng.random(g.N)
+        starts.append(x / x.sum())
+    inits = [torch.from_numpy(starts[0]).cuda(), None, torch.from_numpy(starts[2]).cuda()]
+    probs = [dict(alpha=0.85, tau=1e-9, norm=1, max_iter=500)] * 3
+    res = pr.pull_batch(ctx, dg, probs, inits=inits)
+    for r, p, s0 in zip(res, probs, (starts[0], None, starts[2])):
+        check_column(r, g, p, init=s0)
+
+
+def test_hubs_in_batch(pr, ctx):
+    rng = np.random.default_rng(9)
+    N = 40000
+    src, dst = [], []
+    for v, deg in ((0, 30001), (5, 8193), (6, 5000), (7, 1025), (8, 40)):
+        src.extend(rng.choice(N, size=deg, replace=False).tolist())
+        dst.extend([v] * deg)
+    src.extend(rng.integers(0, N, 80000).tolist())
+    dst.extend(rng.integers(0, N, 80000).tolist())
+    g = gg.from_edges(N, src, dst)
+    dg = pr.DeviceGraph.from_host(g)
+    probs = sweep_problems(tau=1e-11, norm=1)[:7]
+    for r, p in zip(pr.pull_batch(ctx, dg, probs), probs):
+        check_column(r, g, p)
+
+
+def test_batch_repeatable(pr, ctx):
+    g = gg.rmat(14, seed=2)
+    dg = pr.DeviceGraph.from_host(g)
+    a = [r["ranks"].clone() for r in pr.pull_batch(ctx, dg, sweep_problems())]
+    b = [r["ranks"].clone() for r in pr.pull_batch(ctx, dg, sweep_problems())]
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def mixed_bound(alpha, e_gpu, e_ref):
+    return alpha / (1 - alpha) * (e_gpu + e_ref) + 1e-13
+
+
+@pytest.mark.parametrize("norm,tau", [(1, 1e-10), (3, 1e-10), (2, 1e-8), (1, 1e-4)])
+def test_mixed_single_against_oracle(pr, ctx, norm, tau):
+    g = gg.rmat(15, seed=5)
+    dg = pr.DeviceGraph.from_host(g)
+    res = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, precision=pr.PR_MIXED)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=tau, norm=norm)
+    assert res["converged"] and res["fp64_iters"] >= 1 and res["fp32_iters"] >= 1
+    assert res["err"][norm - 1] < tau  # the deciding update is a float64 one
+    d = np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum()
+    assert d <= mixed_bound(0.85, res["err"][0], ref["err"][0]), d
+
+
+def test_mixed_batch_sweep(pr, ctx):
+    g = gg.rmat(15, seed=6)
+    dg = pr.DeviceGraph.from_host(g)
+    probs = sweep_problems(tau=1e-10, norm=3)[:-1]  # alpha < 1 for the bound
+    res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
+    for r, p in zip(res, probs):
+        ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"])
+        assert r["converged"] and r["fp64_iters"] >= 1
+        assert r["err"][2] < p["tau"]
+        d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
+
+
+def test_batch_errors(pr, ctx):
+    g = gg.cycle(5)
+    dg = pr.DeviceGraph.from_host(g)
+    with pytest.raises(pr.PrError) as ei:
+        pr.pull_batch(ctx, dg, [dict(alpha=1.2, tau=1e-6, norm=1, max_iter=10)])
+    assert ei.value.status == -1
+    with pytest.raises(ValueError):
+        pr.pr_pull_batch(ctx, dg, [], 0, None, [], None, torch.empty(8, dtype=torch.uint8, device="cuda"))
