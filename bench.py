@@ -5,11 +5,15 @@ Workload (one "step"): the damping-factor sweep of the paper's section 2 -- elev
 vectors for alpha = 0.50, 0.55, ..., 1.00 -- on a seeded R-MAT graph of scale 24 (16,777,216
 vertices, edge factor 16, a,b,c,d = .57,.19,.19,.05, seed 24, duplicates and self-loops removed),
 each solved to tau = 1e-10 in the L-infinity norm (section 3) from the uniform start, max 500
-iterations.  The graph is synthetic: the paper's SuiteSparse graphs are not available.
+iterations, all eleven together in one batched solve (pr_pull_batch; float32 gather with
+float64 norms, teleport terms and final float64 updates).  The graph is synthetic: the paper's
+SuiteSparse graphs are not available.
 
 Reported:
   value          column-edge updates per second of the timed sweep (sum over the eleven columns
                  of E * iterations, divided by the step time), in GTEPS
+  sweep          per-column iterations, the same sweep as eleven sequential float64 solves
+                 (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
   roofline       the dominant kernel's algorithmic bytes per launch over its average launch
                  duration, timed with HIP events on the solve stream inside the timed steps
   cpu_baseline   the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
@@ -86,6 +90,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--path", choices=["batch_mixed", "batch_fp64"], default="batch_mixed",
+                    help="the timed sweep: batched mixed precision (default) or batched float64")
+    ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 sweep")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -117,14 +124,18 @@ def main():
 
     alphas = gg.ALPHA_SWEEP
     tau, norm, max_iter = 1e-10, pr.PR_LINF, 500
-    ranks = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
+    problems = [dict(alpha=a, tau=tau, norm=norm, max_iter=max_iter) for a in alphas]
+    K = len(problems)
+    ranks_b = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
+    ranks_s = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
+    batch_prec = pr.PR_FP64 if args.path == "batch_fp64" else pr.PR_MIXED
 
-    def sweep():
-        out = []
-        for a, r in zip(alphas, ranks):
-            res = pr.pull(ctx, dg, alpha=a, tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64, ranks=r)
-            out.append(res)
-        return out
+    def sweep_batch():
+        return pr.pull_batch(ctx, dg, problems, precision=batch_prec, ranks=ranks_b)
+
+    def sweep_sequential():
+        return [pr.pull(ctx, dg, alpha=p["alpha"], tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64,
+                        ranks=r) for p, r in zip(problems, ranks_s)]
 
     if args.calibrate:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -142,36 +153,59 @@ def main():
         log("device copy 1 GiB: %.0f GB/s (read+write)" % copy_gbs)
         del src, dst
 
-    for i in range(args.warmup):
-        sweep()
-        log("warmup %d done" % (i + 1))
-    torch.cuda.synchronize()
+    def timed(fn, reps, tag):
+        ts, out = [], None
+        for i in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            log("%s %d: %.2f ms" % (tag, i + 1, ts[-1] * 1e3))
+        return ts, out
 
+    # the plain FP64 reference: 11 sequential solves (untimed warm-up, then timed)
+    sweep_sequential()
+    seq_times, seq_res = timed(sweep_sequential, args.seq_reps, "sequential fp64 sweep")
+    seq_s = float(np.mean(seq_times))
+
+    for i in range(args.warmup):
+        sweep_batch()
+        log("warmup %d done" % (i + 1))
     ctx.reset_stats()
     ctx.set_option("timing", 1)
-    times = []
-    results = None
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        results = sweep()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        log("step %d: %.2f ms" % (i + 1, times[-1] * 1e3))
+    times, results = timed(sweep_batch, args.steps, "step (batched sweep)")
     ctx.set_option("timing", 0)
-    n_upd, ms_upd = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
     step_s = float(np.mean(times))
     iters = [r["iterations"] for r in results]
     col_edges = sum(E * k for k in iters)
     gteps = col_edges / step_s / 1e9
 
-    # roofline of the dominant kernel: one float64 update moves 4E (indices) + 4(N+1) (offsets) +
-    # 4N (out-degrees) + 8N (read previous iterate) + 8N (write new iterate) bytes
-    bytes_per_update = 4 * E + 4 * (N + 1) + 4 * N + 16 * N
-    avg_update_s = (ms_upd / n_upd) * 1e-3 if n_upd else float("nan")
-    achieved = bytes_per_update / avg_update_s / 1e9
-    digest = source_digest(["paper_2108_02997_amd/csrc/pull.hip", "paper_2108_02997_amd/csrc/internal.h"])
-    traffic = read_traffic("update_f64_rmat_s%d" % args.scale, digest)
+    # dominant kernel: the batched update of the first phase (float32 for the mixed path).
+    # Algorithmic bytes of one launch with K_a active columns: 4E (indices) + 4(N+1) (offsets)
+    # + 4N (out-degrees) + 2*s*K_a*N (read and write of the active columns, s bytes each).
+    dom_kind = pr._lib.PR_KERNEL_BATCH_F32 if batch_prec == pr.PR_MIXED else pr._lib.PR_KERNEL_BATCH_F64
+    s_bytes = 4 if batch_prec == pr.PR_MIXED else 8
+    phase1 = [r["fp32_iters"] for r in results] if batch_prec == pr.PR_MIXED else iters
+    n_dom, ms_dom = ctx.stats(dom_kind)
+    launches = max(phase1)
+    alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(launches)]
+    alg_per_launch = float(np.mean(alg))
+    avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
+    achieved = alg_per_launch / avg_launch_s / 1e9
+    n_f64, ms_f64 = ctx.stats(pr._lib.PR_KERNEL_BATCH_F64)
+    kname = "k_batch_update<float,%d>" % (4 if K > 8 else (K + 3) // 4) if batch_prec == pr.PR_MIXED else \
+        "k_batch_update<double,%d>" % ((K + 3) // 4)
+    digest = source_digest(["paper_2108_02997_amd/csrc/batch.hip", "paper_2108_02997_amd/csrc/batch.h",
+                            "paper_2108_02997_amd/csrc/internal.h"])
+    traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if s_bytes == 4 else "f64", args.scale), digest)
+
+    # section 2 report: L1 distance of every column to the alpha = 0.85 column; and the batched
+    # result against the sequential FP64 solves
+    i85 = list(alphas).index(0.85)
+    l1_vs_085 = [pr.l1_distance(ctx, r["ranks"], results[i85]["ranks"]) for r in results]
+    l1_vs_fp64 = [pr.l1_distance(ctx, rb, rs) for rb, rs in zip(ranks_b, ranks_s)]
+    linf_vs_fp64 = [float((rb - rs).abs().max()) for rb, rs in zip(ranks_b, ranks_s)]
 
     line = {
         "metric": METRIC,
@@ -184,27 +218,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if batch_prec == pr.PR_MIXED else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "alpha sweep (11 columns, alpha=0.50..1.00) to tau=1e-10 Linf on R-MAT scale %d, edge factor "
-                        "16, (.57,.19,.19,.05), seed %d; 11 sequential FP64 pull solves" % (args.scale, args.seed),
-            "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": "sequential_fp64",
+            "workload": "alpha sweep: 11 rank columns alpha=0.50..1.00 solved together to tau=1e-10 (Linf) on R-MAT "
+                        "scale %d, edge factor 16, (.57,.19,.19,.05), seed %d; %s" % (
+                            args.scale, args.seed, "float32 gather + float64 norms/c0/refinement"
+                            if batch_prec == pr.PR_MIXED else "float64"),
+            "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path,
         },
         "roofline": {
-            "kernel": "k_update<double>",
+            "kernel": kname,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_per_update,
-            "avg_launch_us": round(avg_update_s * 1e6, 2),
-            "launches_timed": n_upd,
+            "algorithmic_bytes_per_launch": round(alg_per_launch),
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "launches_timed": n_dom,
         },
-        "sweep": {"iterations": iters, "alphas": list(alphas), "column_edges": col_edges,
-                  "prep_ms": round(prep_ms, 2)},
+        "sweep": {
+            "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],
+            "fp64_iters": [r["fp64_iters"] for r in results], "converged": [r["converged"] for r in results],
+            "column_edges": col_edges, "prep_ms": round(prep_ms, 2),
+            "sequential_fp64_ms": round(seq_s * 1e3, 3),
+            "sequential_fp64_iterations": [r["iterations"] for r in seq_res],
+            "speedup_vs_sequential_fp64": round(seq_s / step_s, 3),
+            "l1_vs_alpha_085": [round(x, 6) for x in l1_vs_085],
+            "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
+            "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
+        },
     }
 
     if not args.no_cpu:

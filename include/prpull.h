@@ -90,6 +90,9 @@ const char *pr_version(void);
  *             workgroup per resident slot (compute units x occupancy of the update kernel)
  *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 8)
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
+ *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
+ *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
+ *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
  *   "timing": 1 = launch updates one by one, each bracketed by HIP events on the solve stream,
  *             and accumulate their durations (pr_get_stats); graphs are not replayed meanwhile
  * Returns PR_OK or PR_EINVAL for an unknown key or a value out of range. */
@@ -188,6 +191,12 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
                   const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
                   int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
                   void *workspace, size_t workspace_bytes, pr_result *results);
+
+/* L1 distance sum_v |x_v - y_v| of two device vectors of N float64 values, reduced in a fixed
+ * order (section 2 reports each damping factor's ranks by this distance to the alpha = 0.85
+ * ranks).  workspace: device, at least 8200 bytes.  out: host.  Synchronises the stream. */
+int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, int64_t N, void *workspace,
+                   size_t workspace_bytes, double *out);
 
 #ifdef __cplusplus
 }

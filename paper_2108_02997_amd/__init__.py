@@ -152,6 +152,17 @@ def pull(ctx: Context, g: DeviceGraph, alpha: float = 0.85, tau: float = 1e-6, n
     return res
 
 
+def l1_distance(ctx: Context, x: torch.Tensor, y: torch.Tensor) -> float:
+    """pr_l1_distance: sum |x - y| of two float64 device vectors, reduced in the library."""
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or x.numel() != y.numel():
+        raise ValueError("two float64 vectors of equal length are required")
+    ws = torch.empty(8200, dtype=torch.uint8, device=x.device)
+    out = ctypes.c_double()
+    _lib.check("pr_l1_distance", ctx.lib.pr_l1_distance(ctx.handle, ctx.stream, x.data_ptr(), y.data_ptr(),
+                                                        x.numel(), ws.data_ptr(), ws.numel(), ctypes.byref(out)))
+    return out.value
+
+
 def pr_pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int, inits, ranks, traces,
                   workspace: torch.Tensor, use_prep: bool = True) -> tuple[int, list]:
     """The C entry point pr_pull_batch (at most 16 problems); returns (status, per-problem results)."""

@@ -43,6 +43,7 @@ hipError_t launch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t 
 hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterParams &p);
 int update_blocks_per_cu(bool fp32);
 hipError_t launch_convert(hipStream_t s, const float *y32, double *y64, int32_t N, SolveState *st);
+hipError_t launch_l1(hipStream_t s, const double *x, const double *y, int64_t N, double *part, int32_t nb);
 hipError_t launch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *y, int32_t N, double *ranks);
 hipError_t launch_validate(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
                            int32_t E, uint32_t *cnt, int32_t *flags, int32_t *host_flags);
@@ -83,6 +84,8 @@ struct pr_ctx {
   int64_t chunk = 8;
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
   int64_t timing = 0;     // 1: bracket every update launch with HIP events
+  int64_t batch_chunk = 2;  // updates between host checks of a batch solve (compaction points)
+  int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
   double stat_ms[PR_KERNEL_KINDS] = {};
@@ -158,25 +161,36 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
                  PrepHeader *out) {
   PrepHeader h{};
   h.magic = kPrepMagic;
-  h.version = 1;
+  h.version = 2;
   h.N = N;
   h.E = E;
-  h.tile = kTile;
-  h.rows = kRows;
   h.seg = kSeg;
-  h.desc_off = (int64_t)align_up(sizeof(PrepHeader), 256);
-  h.hub_off = h.desc_off + (int64_t)align_up((size_t)(max_desc(N, E) + 1) * sizeof(int4), 256);
-  h.scan_off = h.hub_off + (int64_t)align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
+  int64_t o = (int64_t)align_up(sizeof(PrepHeader), 256);
+  for (int i = 0; i < 2; ++i) {
+    PrepPart &pp = h.part[i];
+    pp.tile = kPartTile[i];
+    pp.rows = kPartRows[i];
+    pp.desc_off = o;
+    o += (int64_t)align_up((size_t)(max_desc(N, E, pp.tile, pp.rows) + 1) * sizeof(int4), 256);
+    pp.hub_off = o;
+    o += (int64_t)align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
+  }
+  h.scan_off = o;
   char *base = (char *)prep;
-  PR_HIP(launch_prepare(s, off, N, (int4 *)(base + h.desc_off), (int4 *)(base + h.hub_off), base + h.scan_off,
-                        ctx->hscratch));
-  const unsigned long long tot_a = ctx->hscratch[0], tot_b = ctx->hscratch[1];
-  h.ndesc = (int32_t)tot_a;
-  h.nslots = (int32_t)(tot_b >> 32);
-  h.nhubs = (int32_t)(tot_b & 0xffffffffull);
-  if (h.ndesc < 1 || h.ndesc > max_desc(N, E) || h.nslots > max_slots(N, E) || h.nhubs > max_hubs(N, E)) {
-    set_error("internal: tile partition out of bounds (ndesc %d, slots %d, hubs %d)", h.ndesc, h.nslots, h.nhubs);
-    return PR_EDEVICE;
+  for (int i = 0; i < 2; ++i) {
+    PrepPart &pp = h.part[i];
+    PR_HIP(launch_prepare(s, i, off, N, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off), base + h.scan_off,
+                          ctx->hscratch));
+    const unsigned long long tot_a = ctx->hscratch[0], tot_b = ctx->hscratch[1];
+    pp.ndesc = (int32_t)tot_a;
+    pp.nslots = (int32_t)(tot_b >> 32);
+    pp.nhubs = (int32_t)(tot_b & 0xffffffffull);
+    if (pp.ndesc < 1 || pp.ndesc > max_desc(N, E, pp.tile, pp.rows) || pp.nslots > max_slots(N, E) ||
+        pp.nhubs > max_hubs(N, E)) {
+      set_error("internal: tile partition %d out of bounds (ndesc %d, slots %d, hubs %d)", i, pp.ndesc, pp.nslots,
+                pp.nhubs);
+      return PR_EDEVICE;
+    }
   }
   memcpy(ctx->hscratch + 8, &h, sizeof h);
   PR_HIP(hipMemcpyAsync(prep, ctx->hscratch + 8, sizeof h, hipMemcpyHostToDevice, s));
@@ -196,11 +210,11 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
     PR_HIP(hipStreamSynchronize(s));
     memcpy(&h, ctx->hscratch + 8, sizeof h);
   }
-  if (h.magic != kPrepMagic || h.version != 1) {
+  if (h.magic != kPrepMagic || h.version != 2) {
     set_error("prep buffer was not written by pr_prepare");
     return PR_EINVAL;
   }
-  if (h.N != N || h.E != E || h.tile != kTile || h.rows != kRows || h.seg != kSeg) {
+  if (h.N != N || h.E != E || h.seg != kSeg || h.part[0].tile != kTile || h.part[1].tile != kTileB) {
     set_error("prep buffer belongs to another graph (N=%lld E=%lld, expected N=%lld E=%lld)", (long long)h.N,
               (long long)h.E, (long long)N, (long long)E);
     return PR_EINVAL;
@@ -342,22 +356,27 @@ struct BatchLayout {
   size_t total;
 };
 
-int batch_cols_per_lane(int K) { return (K + 3) / 4; }
+// Columns per lane: rows of 4C values.  For float32 a 64-byte row (C = 4) is preferred over a
+// 48-byte one once K > 8: a row fetch then touches exactly one 64-byte line.
+int batch_cols_per_lane(int K, bool fp32) {
+  if (fp32 && K > 8) return 4;
+  return (K + 3) / 4;
+}
 
 BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t precision, bool with_prep) {
   Carver c(ws);
   BatchLayout L{};
-  const int64_t kp = 4 * batch_cols_per_lane(K);
+  const int64_t kp32 = 4 * batch_cols_per_lane(K, true), kp64 = 4 * batch_cols_per_lane(K, false);
   L.st = (BatchState *)c.take(sizeof(BatchState));
   L.cols = (BatchCols *)c.take(sizeof(BatchCols));
   L.bpart = (double *)c.take(sizeof(double) * 4 * kMaxCols * (size_t)kMaxGrid);
   L.hpart = (double *)c.take(sizeof(double) * kMaxCols * (size_t)max_slots(N, E));
   if (precision == PR_MIXED) {
-    L.y32[0] = (float *)c.take(sizeof(float) * (size_t)(N * kp));
-    L.y32[1] = (float *)c.take(sizeof(float) * (size_t)(N * kp));
+    L.y32[0] = (float *)c.take(sizeof(float) * (size_t)(N * kp32));
+    L.y32[1] = (float *)c.take(sizeof(float) * (size_t)(N * kp32));
   }
-  L.y64[0] = (double *)c.take(sizeof(double) * (size_t)(N * kp));
-  L.y64[1] = (double *)c.take(sizeof(double) * (size_t)(N * kp));
+  L.y64[0] = (double *)c.take(sizeof(double) * (size_t)(N * kp64));
+  L.y64[1] = (double *)c.take(sizeof(double) * (size_t)(N * kp64));
   L.prep = with_prep ? c.take(prep_bytes(N, E)) : nullptr;
   L.total = c.used;
   return L;
@@ -462,6 +481,18 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->chunk = value;
+  } else if (!strcmp(key, "batch_chunk")) {
+    if (value < 1 || value > 64) {
+      set_error("batch_chunk must be in [1, 64]");
+      return PR_EINVAL;
+    }
+    ctx->batch_chunk = value;
+  } else if (!strcmp(key, "compact")) {
+    if (value != 0 && value != 1) {
+      set_error("compact must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->compact = value;
   } else if (!strcmp(key, "timing")) {
     if (value != 0 && value != 1) {
       set_error("timing must be 0 or 1");
@@ -604,14 +635,15 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
 
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
   const int64_t gcap = ctx->max_grid > 0 ? ctx->max_grid : ctx->resident[precision == PR_MIXED ? 1 : 0];
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)h.ndesc, gcap, kMaxGrid}));
+  const PrepPart &part = h.part[0];
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
 
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
   p.outdeg = outdeg;
-  p.desc = (const int4 *)((const char *)pp + h.desc_off);
-  p.ndesc = h.ndesc;
+  p.desc = (const int4 *)((const char *)pp + part.desc_off);
+  p.ndesc = part.ndesc;
   p.N = (int32_t)N;
   p.alpha = alpha;
   p.tau = tau;
@@ -620,8 +652,8 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   p.st = L.st;
   p.bpart = L.bpart;
   p.hpart = L.hpart;
-  p.hubs = (const int4 *)((const char *)pp + h.hub_off);
-  p.nhubs = h.nhubs;
+  p.hubs = (const int4 *)((const char *)pp + part.hub_off);
+  p.nhubs = part.nhubs;
   p.grid = (int32_t)grid;
   p.trace = norm_trace;
 
@@ -713,96 +745,242 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     rc = get_prep(ctx, s, prep, N, E, &h);
   }
   if (rc != PR_OK) return rc;
-  const int C = batch_cols_per_lane(K);
-  const int kp = 4 * C;
   int max_iter = 1;
-  BatchCols &hc = *ctx->hcols;
-  memset(&hc, 0, sizeof hc);
-  for (int k = 0; k < K; ++k) {
-    hc.alpha[k] = probs[k].alpha;
-    hc.tau[k] = probs[k].tau;
-    hc.norm[k] = probs[k].norm;
-    hc.max_iter[k] = probs[k].max_iter;
-    hc.init[k] = init ? init[k] : nullptr;
-    hc.ranks[k] = ranks[k];
-    hc.trace[k] = norm_trace ? norm_trace[k] : nullptr;
-    max_iter = std::max(max_iter, probs[k].max_iter);
-  }
-  PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
-  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(BatchState) / 4, 0u));
+  for (int k = 0; k < K; ++k) max_iter = std::max(max_iter, probs[k].max_iter);
 
+  const PrepPart &part = h.part[1];
   BatchParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
   p.outdeg = outdeg;
-  p.desc = (const int4 *)((const char *)pp + h.desc_off);
-  p.ndesc = h.ndesc;
+  p.desc = (const int4 *)((const char *)pp + part.desc_off);
+  p.ndesc = part.ndesc;
   p.N = (int32_t)N;
-  p.K = K;
-  p.nhubs = h.nhubs;
-  p.hubs = (const int4 *)((const char *)pp + h.hub_off);
+  p.nhubs = part.nhubs;
+  p.hubs = (const int4 *)((const char *)pp + part.hub_off);
   p.bpart = L.bpart;
   p.hpart = L.hpart;
   p.st = L.st;
   p.cols = L.cols;
-
-  auto grid_of = [&](bool fp32) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
-      cus = 1;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
+  auto grid_of = [&](bool fp32, int C) {
     const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, C);
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)h.ndesc, res, kMaxGrid}));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, res, kMaxGrid}));
   };
-  int fbuf = 0;
-  bool final_fp32 = false;
-  const void *fa = nullptr, *fb = nullptr;
-  if (precision == PR_MIXED) {
-    p.phase = 1;
-    p.grid = (int32_t)grid_of(true);
-    PR_HIP(launch_batch_init(s, true, outdeg, (int32_t)N, K, kp, L.y32[0], L.bpart, kMaxGrid, p, 1));
-    rc = run_until_stop(ctx, s, batch_chunk(ctx, true, C, (unsigned)p.grid, p, L.y32[0], L.y32[1]), &L.st->head,
-                        max_iter, &fbuf);
-    if (rc != PR_OK) return rc;
-    if (((LoopHead *)ctx->hstate)->done) {
-      fa = L.y32[0];
-      fb = L.y32[1];
-      final_fp32 = true;
-    } else {
-      PR_HIP(launch_batch_convert(s, L.y32[0], L.y32[1], kp, L.y64[0], kp, (int32_t)N, K, L.st));
-      p.phase = 2;
-      p.grid = (int32_t)grid_of(false);
-      rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C, (unsigned)p.grid, p, L.y64[0], L.y64[1]),
-                          &L.st->head, max_iter, &fbuf);
-      if (rc != PR_OK) return rc;
-      fa = L.y64[0];
-      fb = L.y64[1];
+
+  // The running layout: slot i holds original problem orig[i]; `master` keeps every original
+  // problem's latest column state on the host.
+  int orig[kMaxCols];
+  BatchColumn master[kMaxCols];
+  memset(master, 0, sizeof master);
+  int Kc = K;
+  for (int i = 0; i < K; ++i) orig[i] = i;
+  // Write the per-slot parameters (slot order) with the given map/ranks choice and wait for the
+  // copy, so the pinned staging buffer may be rewritten afterwards.
+  auto write_cols = [&](int n, const int *slot_orig, const int *map, bool with_ranks, const bool *rank_sel) -> int {
+    BatchCols &hc = *ctx->hcols;
+    memset(&hc, 0, sizeof hc);
+    for (int i = 0; i < n; ++i) {
+      const int k = slot_orig[i];
+      hc.alpha[i] = probs[k].alpha;
+      hc.tau[i] = probs[k].tau;
+      hc.norm[i] = probs[k].norm;
+      hc.max_iter[i] = probs[k].max_iter;
+      hc.init[i] = init ? init[k] : nullptr;
+      hc.ranks[i] = with_ranks && (!rank_sel || rank_sel[i]) ? ranks[k] : nullptr;
+      hc.trace[i] = norm_trace ? norm_trace[k] : nullptr;
+      hc.map[i] = map ? map[i] : -1;
     }
-  } else {
-    p.phase = 0;
-    p.grid = (int32_t)grid_of(false);
-    PR_HIP(launch_batch_init(s, false, outdeg, (int32_t)N, K, kp, L.y64[0], L.bpart, kMaxGrid, p, 0));
-    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
+    PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    return PR_OK;
+  };
+  auto stat_chunk = [&](int kind, const std::vector<hipEvent_t> *ev, int did, int count) -> int {
+    if (!ev || did <= 0) return PR_OK;
+    float ms = 0.f;
+    for (int k = 0; k < did && k < count; ++k) {
+      PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
+      ctx->stat_ms[kind] += ms;
+      ctx->stat_launches[kind] += 1;
+    }
+    return PR_OK;
+  };
+
+  const bool mixed = precision == PR_MIXED;
+  const bool fp32 = mixed;  // first phase arithmetic
+  int C = batch_cols_per_lane(Kc, fp32), kp = 4 * C;
+  void *b0 = fp32 ? (void *)L.y32[0] : (void *)L.y64[0];
+  void *b1 = fp32 ? (void *)L.y32[1] : (void *)L.y64[1];
+  const int C64 = batch_cols_per_lane(K, false), kp64 = 4 * C64;
+
+  rc = write_cols(Kc, orig, nullptr, false, nullptr);
+  if (rc != PR_OK) return rc;
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(BatchState) / 4, 0u));
+  p.K = Kc;
+  p.phase = mixed ? 1 : 0;
+  p.grid = (int32_t)grid_of(fp32, C);
+  PR_HIP(launch_batch_init(s, fp32, outdeg, (int32_t)N, Kc, kp, b0, L.bpart, kMaxGrid, p, p.phase));
+
+  // ---- first phase, with compaction of the active columns into narrower rows
+  int before = 0;
+  for (int rounds = 0;; ++rounds) {
+    ChunkSpec cs = batch_chunk(ctx, fp32, C, (unsigned)p.grid, p, b0, b1);
+    cs.count = (int)ctx->batch_chunk;
+    const std::vector<hipEvent_t> *ev = nullptr;
+    rc = run_chunk(ctx, s, cs, &ev);
+    if (rc != PR_OK) return rc;
+    PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    BatchState &hs = *ctx->hbstate;
+    rc = stat_chunk(cs.kind, ev, hs.head.phase_iter - before, cs.count);
+    if (rc != PR_OK) return rc;
+    before = hs.head.phase_iter;
+    for (int i = 0; i < Kc; ++i) master[orig[i]] = hs.col[i];
+    if (hs.head.stop) break;
+    if (rounds > max_iter + 2) {
+      set_error("internal: update limit passed without stop");
+      return PR_EDEVICE;
+    }
+    int act[kMaxCols], nact = 0;
+    bool leaving[kMaxCols];
+    for (int i = 0; i < Kc; ++i) {
+      leaving[i] = !hs.col[i].active;
+      if (hs.col[i].active) act[nact++] = i;
+    }
+    const int C2 = batch_cols_per_lane(nact, fp32);
+    if (ctx->compact == 0 || nact == Kc || 4 * C2 >= kp) continue;
+    // (a) columns leaving the layout: float32 -> their float64 columns (mixed), or final ranks
+    if (mixed) {
+      int map[kMaxCols];
+      for (int i = 0; i < Kc; ++i) map[i] = leaving[i] ? orig[i] : -1;
+      rc = write_cols(Kc, orig, map, false, nullptr);
+      if (rc != PR_OK) return rc;
+      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+                                  L.cols));
+    } else {
+      rc = write_cols(Kc, orig, nullptr, true, leaving);
+      if (rc != PR_OK) return rc;
+      p.K = Kc;
+      PR_HIP(launch_batch_output(s, false, outdeg, b0, b1, kp, (int32_t)N, Kc, p));
+    }
+    // (b) repack the active columns (all at the same parity) into the other buffer
+    const int par = hs.col[act[0]].phase_updates & 1;
+    void *cur = par ? b1 : b0, *oth = par ? b0 : b1;
+    int norig[kMaxCols];
+    for (int i = 0; i < nact; ++i) norig[i] = orig[act[i]];
+    rc = write_cols(nact, norig, act, false, nullptr);
+    if (rc != PR_OK) return rc;
+    PR_HIP(launch_batch_compact(s, fp32, cur, kp, oth, 4 * C2, (int32_t)N, nact, L.cols));
+    // (c) the slot states follow their columns; the repacked buffer becomes buffer 0
+    BatchState ns = hs;
+    for (int i = 0; i < kMaxCols; ++i) {
+      if (i < nact) {
+        ns.col[i] = hs.col[act[i]];
+        ns.col[i].phase_updates = 0;
+      } else {
+        memset(&ns.col[i], 0, sizeof ns.col[i]);
+        ns.col[i].done = 1;
+      }
+    }
+    hs = ns;
+    PR_HIP(hipMemcpyAsync(L.st, &hs, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    Kc = nact;
+    for (int i = 0; i < nact; ++i) orig[i] = norig[i];
+    C = C2;
+    kp = 4 * C2;
+    b0 = oth;
+    b1 = cur;
+    p.K = Kc;
+    p.grid = (int32_t)grid_of(fp32, C);
+    before = 0;
+    hs.head.phase_iter = 0;
+    PR_HIP(launch_fill_u32(s, (uint32_t *)&L.st->head.phase_iter, 1, 0u));
+  }
+
+  const BatchColumn *fin = master;
+  if (mixed) {
+    // remaining float32 columns -> float64, then the float64 phase over all K problems
+    int map[kMaxCols];
+    for (int i = 0; i < Kc; ++i) map[i] = orig[i];
+    rc = write_cols(Kc, orig, map, false, nullptr);
+    if (rc != PR_OK) return rc;
+    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+                                L.cols));
+    int all[kMaxCols];
+    for (int i = 0; i < K; ++i) all[i] = i;
+    rc = write_cols(K, all, nullptr, true, nullptr);
+    if (rc != PR_OK) return rc;
+    BatchState &hs = *ctx->hbstate;
+    memset(&hs, 0, sizeof hs);
+    for (int i = 0; i < kMaxCols; ++i) {
+      if (i < K) {
+        hs.col[i] = master[i];
+      } else {
+        hs.col[i].done = 1;
+      }
+    }
+    hs.phase = 2;
+    PR_HIP(hipMemcpyAsync(L.st, &hs, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    PR_HIP(launch_batch_rearm(s, L.st, K));
+    p.K = K;
+    p.phase = 2;
+    p.grid = (int32_t)grid_of(false, C64);
+    int fbuf = 0;
+    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C64, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
                         max_iter, &fbuf);
     if (rc != PR_OK) return rc;
-    fa = L.y64[0];
-    fb = L.y64[1];
+    PR_HIP(launch_batch_output(s, false, outdeg, L.y64[0], L.y64[1], kp64, (int32_t)N, K, p));
+    PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    fin = ctx->hbstate->col;
+  } else {
+    rc = write_cols(Kc, orig, nullptr, true, nullptr);
+    if (rc != PR_OK) return rc;
+    p.K = Kc;
+    PR_HIP(launch_batch_output(s, false, outdeg, b0, b1, kp, (int32_t)N, Kc, p));
+    PR_HIP(hipStreamSynchronize(s));
   }
-  PR_HIP(launch_batch_output(s, final_fp32, outdeg, fa, fb, kp, (int32_t)N, K, p));
-  PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
-  PR_HIP(hipStreamSynchronize(s));
-  int all = 1;
+  int all_conv = 1;
   for (int k = 0; k < K; ++k) {
-    const BatchColumn &cs = ctx->hbstate->col[k];
-    results[k].iterations = cs.iters;
-    results[k].converged = cs.converged;
-    results[k].fp32_iters = cs.fp32_iters;
-    results[k].fp64_iters = cs.iters - cs.fp32_iters;
-    results[k].final_err[0] = cs.err[0];
-    results[k].final_err[1] = cs.err[1];
-    results[k].final_err[2] = cs.err[2];
-    all &= cs.converged;
+    const BatchColumn &c = fin[k];
+    results[k].iterations = c.iters;
+    results[k].converged = c.converged;
+    results[k].fp32_iters = c.fp32_iters;
+    results[k].fp64_iters = c.iters - c.fp32_iters;
+    results[k].final_err[0] = c.err[0];
+    results[k].final_err[1] = c.err[1];
+    results[k].final_err[2] = c.err[2];
+    all_conv &= c.converged;
   }
-  return all ? PR_OK : PR_NOT_CONVERGED;
+  return all_conv ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, int64_t N, void *workspace,
+                   size_t workspace_bytes, double *out) {
+  if (!ctx || !x || !y || !workspace || !out) {
+    set_error("pr_l1_distance: NULL argument");
+    return PR_EINVAL;
+  }
+  if (N < 1) {
+    set_error("pr_l1_distance: N must be >= 1");
+    return PR_EINVAL;
+  }
+  constexpr int32_t nb = 1024;
+  if (workspace_bytes < (nb + 1) * sizeof(double)) {
+    set_error("pr_l1_distance: workspace needs %zu bytes", (size_t)(nb + 1) * sizeof(double));
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  double *part = (double *)workspace;
+  PR_HIP(launch_l1(s, x, y, N, part, nb));
+  PR_HIP(hipMemcpyAsync(ctx->hscratch, part + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  memcpy(out, ctx->hscratch, sizeof(double));
+  return PR_OK;
 }
 
 }  // extern "C"

@@ -35,8 +35,9 @@ struct BatchCols {
   int32_t norm[kMaxCols];
   int32_t max_iter[kMaxCols];
   const double *init[kMaxCols];
-  double *ranks[kMaxCols];
+  double *ranks[kMaxCols];   // NULL: k_batch_output skips the column
   double *trace[kMaxCols];
+  int32_t map[kMaxCols];     // k_batch_convert / k_batch_compact: source or destination column, -1 skips
 };
 
 struct BatchParams {
@@ -107,7 +108,10 @@ int batch_blocks_per_cu(bool fp32, int C);
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase);
 hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
-                                int32_t kp64, int32_t N, int32_t K, BatchState *st);
+                                int32_t kp64, int32_t N, int32_t K, const BatchState *st, const BatchCols *cols);
+hipError_t launch_batch_rearm(hipStream_t s, BatchState *st, int32_t K);
+hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32_t kp_src, void *dst, int32_t kp_dst,
+                                int32_t N, int32_t K, const BatchCols *cols);
 hipError_t launch_batch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *ya, const void *yb,
                                int32_t kp, int32_t N, int32_t K, const BatchParams &p);
 

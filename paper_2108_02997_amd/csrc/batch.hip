@@ -5,8 +5,9 @@
 // row-major, so one in-edge u -> v costs one contiguous Kp*sizeof(VT)-byte row fetch that
 // serves every column: y[u][k] = r_k[u]/d_u (or r_k[u] for a dangling u), as in pull.hip.
 // A quad of four lanes owns one row fetch; lane (l & 3) handles columns (l & 3)*C .. +C-1.
-//   short rows (in-degree <= kMidDeg): one quad per row, entries in ascending order;
-//   mid rows: one wave per row, entry j on quad j % 16, xor reduction across the quads;
+//   tiles of short rows (partition B: fewer than kSpanB entries): every quad fetches the rows
+//   of kPerQ entries into LDS, then one quad sums each row of in-degree <= kMidDeg in ascending
+//   entry order and one wave each longer row (entry j on quad j % 16, xor reduction);
 //   long-row segments: one block per segment, reduction across quads and waves; hubs leave
 //   per-column segment partials for k_batch_finish.
 // Every column has its own c0, alpha, tau, norm, iteration count and stop decision; a column
@@ -88,7 +89,10 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
 template <typename VT, int C>
 __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
   constexpr int KP = 4 * C;
-  __shared__ int32_t sidx[kSpan];
+  constexpr int kQuads = kBlock / 4;             // 64 quads per block
+  constexpr int kPerQ = kSpanB / kQuads;         // entries gathered per quad per tile (8)
+  constexpr int kRowsQ = kRowsB / kQuads;        // rows owned per quad per tile (2)
+  __shared__ VT vals[kSpanB * KP];
   __shared__ double sred[kWaves][KP];
   __shared__ double sacc[kWaves][KP][4];
   const BatchState *st = p.st;
@@ -118,59 +122,77 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
     const int4 dn = p.desc[i + 1];
     const int32_t e0 = d.y, e1 = dn.y;
     if (d.z < 0) {
-      // ---- tile of short rows: stage the index slice, then rows by quads (short) / waves (mid)
+      // ---- tile of short rows [d.x, dn.x), entries [e0, e1), fewer than kSpanB.
+      // Phase 1: every quad fetches the rows of kPerQ entries (entry j on quad j % 64) and the
+      // metadata of its rows; phase 2: row sums from LDS, one quad per short row, one wave per
+      // mid row; then the epilogue.
       const int32_t v0 = d.x, v1 = dn.x, n = e1 - e0;
-      for (int j = t; j < n; j += kBlock) sidx[j] = __builtin_nontemporal_load(idx + e0 + j);
-      __syncthreads();
-      const int32_t nrows = v1 - v0;
-      for (int32_t r0 = 0; r0 < nrows; r0 += kBlock / 4) {
-        const int32_t r = r0 + quad;
-        const bool mine = r < nrows;
-        const int32_t v = v0 + r;
-        int32_t ra = 0, rb = 0, dv = 0;
-        if (mine) {
-          ra = off[v] - e0;
-          rb = off[v + 1] - e0;
-          dv = p.outdeg[v];
+      int32_t u[kPerQ];
+#pragma unroll
+      for (int k = 0; k < kPerQ; ++k) {
+        const int32_t j = quad + k * kQuads;
+        u[k] = j < n ? __builtin_nontemporal_load(idx + e0 + j) : -1;
+      }
+      int32_t ra[kRowsQ], rb[kRowsQ], dv[kRowsQ];
+#pragma unroll
+      for (int q = 0; q < kRowsQ; ++q) {
+        const int32_t v = v0 + quad + q * kQuads;
+        ra[q] = rb[q] = dv[q] = 0;
+        if (v < v1) {
+          ra[q] = __builtin_nontemporal_load(off + v) - e0;
+          rb[q] = __builtin_nontemporal_load(off + v + 1) - e0;
+          dv[q] = __builtin_nontemporal_load(p.outdeg + v);
         }
-        const bool mid = mine && (rb - ra) > kMidDeg;
+      }
+      Row<VT, C> x[kPerQ];
+#pragma unroll
+      for (int k = 0; k < kPerQ; ++k) {
+        if (u[k] >= 0) {
+          x[k] = load_row<VT, C>(yin, u[k], KP, col0);
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) x[k].v[c] = (VT)0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPerQ; ++k) {
+        const int32_t j = quad + k * kQuads;
+        if (j < n) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) vals[j * KP + col0 + c] = x[k].v[c];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kRowsQ; ++q) {
+        const int32_t v = v0 + quad + q * kQuads;
+        const bool mine = v < v1;
+        const bool mid = mine && (rb[q] - ra[q]) > kMidDeg;
         if (mine && !mid) {
           VT s[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) s[c] = (VT)0;
-          int32_t j = ra;
-          for (; j + 4 <= rb; j += 4) {
-            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
-            const Row<VT, C> x1 = load_row<VT, C>(yin, sidx[j + 1], KP, col0);
-            const Row<VT, C> x2 = load_row<VT, C>(yin, sidx[j + 2], KP, col0);
-            const Row<VT, C> x3 = load_row<VT, C>(yin, sidx[j + 3], KP, col0);
+          for (int32_t j = ra[q]; j < rb[q]; ++j) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) s[c] = (((s[c] + x0.v[c]) + x1.v[c]) + x2.v[c]) + x3.v[c];
-          }
-          for (; j < rb; ++j) {
-            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
-#pragma unroll
-            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+            for (int c = 0; c < C; ++c) s[c] += vals[j * KP + col0 + c];
           }
           double sd[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) sd[c] = (double)s[c];
-          batch_epilogue<VT, C>(v, sd, dv, yin, yout, KP, col0, c0, alpha, act, a);
+          batch_epilogue<VT, C>(v, sd, dv[q], yin, yout, KP, col0, c0, alpha, act, a);
         }
-        // mid rows of this wave's 16 quads, one at a time, by all 16 quads
         unsigned long long m = __ballot(mid && qp == 0);
         while (m) {
           const int src = __ffsll((long long)m) - 1;
           m &= m - 1;
-          const int32_t wa = __shfl(ra, src, 64), wb = __shfl(rb, src, 64);
-          const int32_t wv = __shfl(v, src, 64), wd = __shfl(dv, src, 64);
+          const int32_t wa = __shfl(ra[q], src, 64), wb = __shfl(rb[q], src, 64);
+          const int32_t wv = __shfl(v, src, 64), wd = __shfl(dv[q], src, 64);
           VT s[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) s[c] = (VT)0;
           for (int32_t j = wa + (lane >> 2); j < wb; j += 16) {
-            const Row<VT, C> x0 = load_row<VT, C>(yin, sidx[j], KP, col0);
 #pragma unroll
-            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+            for (int c = 0; c < C; ++c) s[c] += vals[j * KP + col0 + c];
           }
           double sd[C];
 #pragma unroll
@@ -180,25 +202,32 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
       }
       __syncthreads();
     } else {
-      // ---- one segment [e0, e1) of a long row: quads stride the entries
+      // ---- one segment [e0, e1) of a long row: quads stride the entries, kPerQ in flight
       const int32_t v = d.x, slot = d.w;
       VT s[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c] = (VT)0;
-      for (int32_t c8 = e0 + quad; c8 < e1; c8 += 4 * (kBlock / 4)) {
-        int32_t u[4];
+      for (int32_t c8 = e0 + quad; c8 < e1; c8 += kPerQ * kQuads) {
+        int32_t u[kPerQ];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int32_t j = c8 + k * (kBlock / 4);
+        for (int k = 0; k < kPerQ; ++k) {
+          const int32_t j = c8 + k * kQuads;
           u[k] = j < e1 ? __builtin_nontemporal_load(idx + j) : -1;
         }
+        Row<VT, C> x[kPerQ];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kPerQ; ++k) {
           if (u[k] >= 0) {
-            const Row<VT, C> x0 = load_row<VT, C>(yin, u[k], KP, col0);
+            x[k] = load_row<VT, C>(yin, u[k], KP, col0);
+          } else {
 #pragma unroll
-            for (int c = 0; c < C; ++c) s[c] += x0.v[c];
+            for (int c = 0; c < C; ++c) x[k].v[c] = (VT)0;
           }
+        }
+#pragma unroll
+        for (int k = 0; k < kPerQ; ++k) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) s[c] += x[k].v[c];
         }
       }
       double tot[C];
@@ -229,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
       }
     }
   }
+  __syncthreads();
 
   // ---- block partials per column: lanes with equal qp reduce across quads and waves
 #pragma unroll
@@ -238,7 +268,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
     a[c].mx = xor_max_quads(a[c].mx);
     a[c].dang = xor_sum_quads(a[c].dang);
   }
-  __syncthreads();
   if (lane < 4) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -403,21 +432,37 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_init_finish(const double *_
   }
 }
 
-// Float32 columns -> float64 columns (each column from its own latest buffer); re-arm.
+// Float32 columns -> float64 columns: column c (its newest buffer by its update parity) goes to
+// float64 column map[c] (skipped when map[c] < 0).
 __global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restrict__ y32a, const float *__restrict__ y32b,
                                                           int32_t kp32, double *__restrict__ y64, int32_t kp64,
-                                                          int32_t N, int32_t K, const BatchState *st) {
-  int par[16];
-  for (int c = 0; c < 16; ++c) par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
+                                                          int32_t N, int32_t K, const BatchState *st,
+                                                          const BatchCols *cols) {
+  int par[kMaxCols], dst[kMaxCols];
+  for (int c = 0; c < kMaxCols; ++c) {
+    par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
+    dst[c] = c < K ? cols->map[c] : -1;
+  }
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    for (int c = 0; c < kp64; ++c) {
-      double x = 0.0;
-      if (c < K) x = (double)(par[c] ? y32b : y32a)[v * kp32 + c];
-      y64[v * kp64 + c] = x;
+    for (int c = 0; c < K; ++c) {
+      if (dst[c] >= 0) y64[v * kp64 + dst[c]] = (double)(par[c] ? y32b : y32a)[v * kp32 + c];
     }
   }
 }
 
+// Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_batch_compact(const VT *__restrict__ src, int32_t kp_src,
+                                                          VT *__restrict__ dst, int32_t kp_dst, int32_t N, int32_t K,
+                                                          const BatchCols *cols) {
+  int m[kMaxCols];
+  for (int c = 0; c < kMaxCols; ++c) m[c] = c < K ? cols->map[c] : -1;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    for (int c = 0; c < kp_dst; ++c) dst[v * kp_dst + c] = (c < K && m[c] >= 0) ? src[v * kp_src + m[c]] : (VT)0;
+  }
+}
+
+// Re-arm for the float64 phase: every column not done becomes active.
 __global__ void k_batch_rearm(BatchState *st, int32_t K) {
   if (threadIdx.x == 0) {
     int any = 0;
@@ -444,8 +489,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_output(const int32_t *__restri
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
     const int32_t dv = outdeg[v];
     for (int c = 0; c < K; ++c) {
+      double *out = p.cols->ranks[c];
+      if (!out) continue;
       const double y = (double)(par[c] ? yb : ya)[v * kp + c];
-      p.cols->ranks[c][v] = dv > 0 ? y * (double)dv : y;
+      out[v] = dv > 0 ? y * (double)dv : y;
     }
   }
 }
@@ -515,10 +562,25 @@ hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, in
 }
 
 hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
-                                int32_t kp64, int32_t N, int32_t K, BatchState *st) {
+                                int32_t kp64, int32_t N, int32_t K, const BatchState *st, const BatchCols *cols) {
   hipLaunchKernelGGL(k_batch_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32a, y32b, kp32, y64, kp64, N,
-                     K, (const BatchState *)st);
+                     K, st, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rearm(hipStream_t s, BatchState *st, int32_t K) {
   hipLaunchKernelGGL(k_batch_rearm, dim3(1), dim3(64), 0, s, st, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32_t kp_src, void *dst, int32_t kp_dst,
+                                int32_t N, int32_t K, const BatchCols *cols) {
+  if (fp32)
+    hipLaunchKernelGGL(k_batch_compact<float>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, (const float *)src, kp_src,
+                       (float *)dst, kp_dst, N, K, cols);
+  else
+    hipLaunchKernelGGL(k_batch_compact<double>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, (const double *)src,
+                       kp_src, (double *)dst, kp_dst, N, K, cols);
   return hipGetLastError();
 }
 

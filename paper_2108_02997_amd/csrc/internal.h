@@ -21,6 +21,14 @@ constexpr int kRows = 512;
 constexpr int kSpan = 2 * kTile;
 constexpr int kRowsPerLane = kRows / kBlock;  // 2
 constexpr int kSeg = 8192;
+// Two partitions are kept per graph: A for the single-vector update (windows of kTile entries,
+// kRows rows) and B for the K-column update, whose tiles stage whole gathered rows through LDS
+// (windows of kTileB entries, kRowsB rows, so a tile spans fewer than kSpanB entries).
+constexpr int kTileB = 256;
+constexpr int kRowsB = 128;
+constexpr int kSpanB = 2 * kTileB;
+constexpr int kPartTile[2] = {kTile, kTileB};
+constexpr int kPartRows[2] = {kRows, kRowsB};
 // Rows with in-degree above kMidDeg (and at most kTile) are summed by a whole wave.
 constexpr int kMidDeg = 32;
 // Upper bound of the update grid (blocks loop over tiles in a fixed round-robin order).
@@ -34,22 +42,25 @@ constexpr int kFinBlock = 1024;
 // tile i+1 starts (rows desc[i].x .. desc[i+1].x, entries desc[i].y .. desc[i+1].y); a sentinel
 // {N, E, -1, -1} follows the last tile.  Long rows of two or more segments ("hubs") are also
 // listed in a hub table: x = row, y = segments, z = first slot.
+struct PrepPart {
+  int64_t desc_off;  // byte offset of the descriptors inside the prep buffer
+  int64_t hub_off;   // byte offset of the hub table
+  int32_t tile, rows, ndesc, nslots, nhubs, pad;
+};
+
 struct PrepHeader {
   int32_t magic;
   int32_t version;
   int64_t N;
   int64_t E;
-  int32_t tile, rows, ndesc, nslots;
-  int64_t desc_off;   // byte offset of the descriptors inside the prep buffer
+  int32_t seg, pad;
   int64_t scan_off;   // byte offset of the scan scratch
-  int64_t hub_off;    // byte offset of the hub table
-  int32_t nhubs, seg;
-  int64_t reserved;
+  PrepPart part[2];
 };
-constexpr int32_t kPrepMagic = 0x50525031;  // "PRP1"
+constexpr int32_t kPrepMagic = 0x50525032;  // "PRP2"
 
 size_t prep_bytes(int64_t N, int64_t E);
-int64_t max_desc(int64_t N, int64_t E);
+int64_t max_desc(int64_t N, int64_t E, int tile, int rows);
 int64_t max_slots(int64_t N, int64_t E);
 int64_t max_hubs(int64_t N, int64_t E);
 
@@ -115,7 +126,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Launchers (defined in the .hip files).
 // host_total receives {descriptors, hub slots << 32 | hubs}.
-hipError_t launch_prepare(hipStream_t s, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
+hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
                           unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);

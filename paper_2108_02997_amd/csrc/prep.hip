@@ -19,7 +19,7 @@ namespace prpull {
 constexpr int kScanChunk = 4096;                   // rows per scan block
 constexpr int kScanPerLane = kScanChunk / kBlock;  // 16 consecutive rows per lane
 
-int64_t max_desc(int64_t N, int64_t E) { return 4 * (E / kTile + 1) + N / kRows + 8; }
+int64_t max_desc(int64_t N, int64_t E, int tile, int rows) { return 4 * (E / tile + 1) + N / rows + 8; }
 int64_t max_slots(int64_t N, int64_t E) {
   (void)N;
   return 2 * (E / kSeg) + 2;
@@ -32,10 +32,13 @@ int64_t max_hubs(int64_t N, int64_t E) {
 static int64_t scan_blocks(int64_t N) { return (N + kScanChunk - 1) / kScanChunk; }
 int64_t scan_block_count(int64_t N) { return scan_blocks(N); }
 
+// Layout: header | partition A (descriptors, hubs) | partition B (descriptors, hubs) | scan scratch.
 size_t prep_bytes(int64_t N, int64_t E) {
   size_t b = align_up(sizeof(PrepHeader), 256);
-  b += align_up((size_t)(max_desc(N, E) + 1) * sizeof(int4), 256);
-  b += align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
+  for (int i = 0; i < 2; ++i) {
+    b += align_up((size_t)(max_desc(N, E, kPartTile[i], kPartRows[i]) + 1) * sizeof(int4), 256);
+    b += align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
+  }
   b += align_up((size_t)(scan_blocks(N) + 1) * 2 * sizeof(unsigned long long), 256);
   return b;
 }
@@ -47,15 +50,16 @@ struct Code {
 __device__ __forceinline__ Code operator+(Code x, Code y) { return Code{x.a + y.a, x.b + y.b}; }
 __device__ __forceinline__ Code operator-(Code x, Code y) { return Code{x.a - y.a, x.b - y.b}; }
 
+template <int TILE, int ROWS>
 __device__ __forceinline__ Code row_code(const int32_t *__restrict__ off, int32_t v) {
   const int32_t a = off[v], b = off[v + 1];
   const int32_t deg = b - a;
-  const bool lng = deg > kTile;
+  const bool lng = deg > TILE;
   bool start = true;
   if (v > 0) {
     const int32_t pa = off[v - 1];
-    const bool prev_long = (a - pa) > kTile;
-    start = lng || prev_long || (a / kTile != pa / kTile) || (v / kRows != (v - 1) / kRows);
+    const bool prev_long = (a - pa) > TILE;
+    start = lng || prev_long || (a / TILE != pa / TILE) || (v / ROWS != (v - 1) / ROWS);
   }
   if (!start) return Code{0ull, 0ull};
   if (lng) {
@@ -82,6 +86,7 @@ __device__ __forceinline__ Code block_exclusive_scan(Code x, Code *lds, Code *to
   return incl - x;
 }
 
+template <int TILE, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_prep_reduce(const int32_t *__restrict__ off, int32_t N,
                                                         Code *__restrict__ bsum) {
   __shared__ Code lds[kBlock];
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_reduce(const int32_t *__restric
   Code s{0ull, 0ull};
   for (int k = 0; k < kScanPerLane; ++k) {
     const int64_t v = base + k;
-    if (v < N) s = s + row_code(off, (int32_t)v);
+    if (v < N) s = s + row_code<TILE, ROWS>(off, (int32_t)v);
   }
   Code tot;
   block_exclusive_scan(s, lds, &tot);
@@ -115,6 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_top(Code *__restrict__ bsum, in
   }
 }
 
+template <int TILE, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_prep_write(const int32_t *__restrict__ off, int32_t N,
                                                        const Code *__restrict__ bsum, int4 *__restrict__ desc,
                                                        int4 *__restrict__ hubs) {
@@ -123,21 +129,21 @@ __global__ __launch_bounds__(kBlock) void k_prep_write(const int32_t *__restrict
   Code s{0ull, 0ull};
   for (int k = 0; k < kScanPerLane; ++k) {
     const int64_t v = base + k;
-    if (v < N) s = s + row_code(off, (int32_t)v);
+    if (v < N) s = s + row_code<TILE, ROWS>(off, (int32_t)v);
   }
   Code tot;
   Code pos = bsum[blockIdx.x] + block_exclusive_scan(s, lds, &tot);
   for (int k = 0; k < kScanPerLane; ++k) {
     const int64_t v = base + k;
     if (v >= N) break;
-    const Code c = row_code(off, (int32_t)v);
+    const Code c = row_code<TILE, ROWS>(off, (int32_t)v);
     if (c.a == 0) continue;
     const int32_t p = (int32_t)pos.a;
     const int32_t slot = (int32_t)(pos.b >> 32);
     const int32_t hub = (int32_t)(pos.b & 0xffffffffull);
     const int32_t ev = off[v];
     const int32_t deg = off[v + 1] - ev;
-    if (deg > kTile) {
+    if (deg > TILE) {
       const int32_t ns = (int32_t)c.a;
       if (ns == 1) {
         desc[p] = make_int4((int32_t)v, ev, 0, -1);
@@ -165,18 +171,26 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v) {
   return hipGetLastError();
 }
 
-// Runs the three partition kernels, copies the totals {descriptors, slots << 32 | hubs} to
-// host_total (host memory, 2 words) and synchronises the stream.
-hipError_t launch_prepare(hipStream_t s, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
-                          unsigned long long *host_total) {
+// Runs the three partition kernels of partition `part` (0: update tiles, 1: batch tiles), copies
+// the totals {descriptors, slots << 32 | hubs} to host_total (host memory, 2 words) and
+// synchronises the stream.
+template <int TILE, int ROWS>
+static hipError_t prepare_part(hipStream_t s, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, Code *bsum) {
   const int64_t nb = scan_blocks(N);
-  Code *bsum = (Code *)scan;
-  hipLaunchKernelGGL(k_prep_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, off, (int32_t)N, bsum);
+  hipLaunchKernelGGL((k_prep_reduce<TILE, ROWS>), dim3((unsigned)nb), dim3(kBlock), 0, s, off, (int32_t)N, bsum);
   hipLaunchKernelGGL(k_prep_top, dim3(1), dim3(kBlock), 0, s, bsum, nb, desc, off, (int32_t)N);
-  hipLaunchKernelGGL(k_prep_write, dim3((unsigned)nb), dim3(kBlock), 0, s, off, (int32_t)N, bsum, desc, hubs);
-  hipError_t e = hipGetLastError();
+  hipLaunchKernelGGL((k_prep_write<TILE, ROWS>), dim3((unsigned)nb), dim3(kBlock), 0, s, off, (int32_t)N, bsum, desc,
+                     hubs);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
+                          unsigned long long *host_total) {
+  Code *bsum = (Code *)scan;
+  hipError_t e = part == 0 ? prepare_part<kPartTile[0], kPartRows[0]>(s, off, N, desc, hubs, bsum)
+                           : prepare_part<kPartTile[1], kPartRows[1]>(s, off, N, desc, hubs, bsum);
   if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(host_total, bsum + nb, sizeof(Code), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(host_total, bsum + scan_blocks(N), sizeof(Code), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(s);
 }

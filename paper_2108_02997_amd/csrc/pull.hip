@@ -372,7 +372,33 @@ __global__ __launch_bounds__(kBlock) void k_output(const int32_t *__restrict__ o
   }
 }
 
+// Sum of |x_v - y_v|: per-block partials, then one block in block order.
+__global__ __launch_bounds__(kBlock) void k_l1_partial(const double *__restrict__ x, const double *__restrict__ y,
+                                                       int64_t N, double *__restrict__ part) {
+  __shared__ double red[kWaves];
+  double s = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock)
+    s += fabs(x[v] - y[v]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_l1_final(double *part, int32_t nb) {
+  __shared__ double red[kFinBlock / 64];
+  double s = 0.0;
+#pragma unroll 1
+  for (int32_t b = threadIdx.x; b < nb; b += kFinBlock) s += part[b];
+  s = block_sum_n<kFinBlock>(s, red);
+  if (threadIdx.x == 0) part[nb] = s;
+}
+
 // ------------------------------------------------------------------ launchers
+hipError_t launch_l1(hipStream_t s, const double *x, const double *y, int64_t N, double *part, int32_t nb) {
+  hipLaunchKernelGGL(k_l1_partial, dim3(nb), dim3(kBlock), 0, s, x, y, N, part);
+  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kFinBlock), 0, s, part, nb);
+  return hipGetLastError();
+}
+
 static unsigned grid_for(int64_t n, int64_t cap) {
   int64_t g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;

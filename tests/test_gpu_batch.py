@@ -161,3 +161,39 @@ def test_batch_errors(pr, ctx):
     assert ei.value.status == -1
     with pytest.raises(ValueError):
         pr.pr_pull_batch(ctx, dg, [], 0, None, [], None, torch.empty(8, dtype=torch.uint8, device="cuda"))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_compaction_changes_nothing(pr, ctx, precision):
+    # Repacking the still-active columns into narrower rows keeps every per-column sum in the
+    # same order; with the grid pinned (same block partials) the results are bitwise equal.
+    g = gg.rmat(14, seed=21)
+    dg = pr.DeviceGraph.from_host(g)
+    probs = sweep_problems(tau=1e-10, norm=3)
+    out = {}
+    try:
+        ctx.set_option("grid", 300)
+        for compact in (0, 1):
+            ctx.set_option("compact", compact)
+            out[compact] = pr.pull_batch(ctx, dg, probs, precision=precision)
+            out[compact] = [(r["iterations"], r["fp32_iters"], r["ranks"].clone()) for r in out[compact]]
+    finally:
+        ctx.set_option("compact", 1)
+        ctx.set_option("grid", 0)
+    for (i0, f0, r0), (i1, f1, r1) in zip(out[0], out[1]):
+        assert i0 == i1 and f0 == f1
+        assert torch.equal(r0, r1)
+
+
+def test_compaction_with_traces_and_max_iter(pr, ctx):
+    g = gg.rmat(13, seed=22)
+    dg = pr.DeviceGraph.from_host(g)
+    probs = [dict(alpha=a, tau=1e-10, norm=1, max_iter=m) for a, m in
+             ((0.5, 500), (0.6, 4), (0.7, 500), (0.8, 7), (0.85, 500), (0.9, 500), (0.95, 2), (1.0, 500),
+              (0.55, 500), (0.65, 500), (0.99, 500))]
+    res = pr.pull_batch(ctx, dg, probs, trace=True)
+    for r, p in zip(res, probs):
+        ref = check_column(r, g, p)
+        if r["iterations"] == ref["iterations"]:
+            atol = 2.0 ** -50 * (g.N + 16)
+            np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)
