@@ -90,6 +90,8 @@ const char *pr_version(void);
  *             workgroup per resident slot (compute units x occupancy of the update kernel)
  *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 8)
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
+ *   "mid_deg": rows of at most this many in-edges are summed by one lane, longer rows (up to the
+ *             1024-entry tile window) by a whole wave64, 0..1024 (default 32)
  *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
@@ -104,6 +106,7 @@ enum {
   PR_KERNEL_UPDATE_F32 = 1, /* one float32 update (PR_MIXED first phase) */
   PR_KERNEL_BATCH_F64 = 2,  /* one float64 update of pr_pull_batch (all active columns) */
   PR_KERNEL_BATCH_F32 = 3,  /* one float32 update of pr_pull_batch */
+  PR_KERNEL_MULTI = 4,      /* one whole pr_pull_multi launch (all rounds of all graphs) */
   PR_KERNEL_KINDS = 8
 };
 
@@ -191,6 +194,35 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
                   const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
                   int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
                   void *workspace, size_t workspace_bytes, pr_result *results);
+
+/* ------------------------------------------------------------------ many graphs, one launch */
+
+/* One graph of a many-graph batch with its own parameters (sections 2 and 3). */
+typedef struct {
+  const int32_t *in_offsets; /* device, N+1 */
+  const int32_t *in_indices; /* device, E (graph-local source ids) */
+  const int32_t *outdeg;     /* device, N */
+  int64_t N, E;
+  const void *prep;          /* pr_prepare output of this graph, or NULL to prepare inside the workspace */
+  double alpha, tau;
+  int32_t norm, max_iter;
+  const double *init;        /* device, N, or NULL for 1/N */
+  double *ranks;             /* device, N, out */
+  double *norm_trace;        /* device, max_iter x 3, or NULL */
+} pr_graph_problem;
+
+/* Device workspace bytes of pr_pull_multi for these G graphs (1..4096). */
+size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs);
+
+/* G independent problems on G graphs of any sizes, float64, in ONE persistent cooperative
+ * launch: every global round updates all still-active graphs (tiles of all graphs shared among
+ * all workgroups, then one workgroup per graph finishes its update); each graph stops on its own
+ * rule, exactly as in pr_pull.  Graphs prepared beforehand (prep != NULL) use their tiles; the
+ * tile window / lane-per-row threshold comes from the context ("mid_deg", or the autotuner).
+ * probs and results are host arrays of G entries.  Returns PR_OK when every graph converged,
+ * PR_NOT_CONVERGED otherwise (see results[g].converged), or a negative status. */
+int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
+                  size_t workspace_bytes, pr_result *results);
 
 /* L1 distance sum_v |x_v - y_v| of two device vectors of N float64 values, reduced in a fixed
  * order (section 2 reports each damping factor's ranks by this distance to the alpha = 0.85

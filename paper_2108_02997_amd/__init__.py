@@ -16,9 +16,9 @@ import torch
 
 from . import _lib
 from ._lib import (MAX_COLS, PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK,  # noqa: F401
-                   PrError, pr_problem, pr_result)
+                   PrError, pr_graph_problem, pr_problem, pr_result)
 
-__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
+__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "pull_multi", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
 
 
 def _require_gpu():
@@ -215,4 +215,42 @@ def pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int = PR_FP64,
             r["ranks"] = ranks[sl.start + j]
             r["trace"] = traces[sl.start + j][:r["iterations"]] if trace else None
             out.append(r)
+    return out
+
+
+def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, workspace=None) -> list:
+    """Many graphs, each with its own problem, in one persistent launch (pr_pull_multi, float64).
+
+    graphs: DeviceGraph list (prepared here if needed); problems: dicts with alpha, tau, norm,
+    max_iter.  Returns one dict per graph (ranks, iterations, converged, err, trace)."""
+    G = len(graphs)
+    if G != len(problems) or G < 1:
+        raise ValueError("one problem per graph is required")
+    arr = (pr_graph_problem * G)()
+    ranks, traces = [], []
+    for k, (g, p) in enumerate(zip(graphs, problems)):
+        if g.prep is None:
+            g.prepare(ctx)
+        r = torch.empty(g.N, dtype=torch.float64, device=g.off.device)
+        tr = torch.full((int(p["max_iter"]), 3), float("nan"), dtype=torch.float64, device=g.off.device) if trace \
+            else None
+        ini = inits[k] if inits is not None else None
+        arr[k] = pr_graph_problem(g.off.data_ptr(), _lib.ptr(g.idx) if g.E else None, g.outdeg.data_ptr(), g.N, g.E,
+                                  g.prep.data_ptr(), float(p["alpha"]), float(p["tau"]), int(p["norm"]),
+                                  int(p["max_iter"]), _lib.ptr(ini), r.data_ptr(), _lib.ptr(tr))
+        ranks.append(r)
+        traces.append(tr)
+    nbytes = ctx.lib.pr_multi_workspace_bytes(G, arr)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=graphs[0].off.device)
+    res = (pr_result * G)()
+    st = ctx.lib.pr_pull_multi(ctx.handle, ctx.stream, G, arr, workspace.data_ptr(), workspace.numel(), res)
+    _lib.check("pr_pull_multi", st)
+    out = []
+    for k in range(G):
+        d = res[k].as_dict()
+        d["status"] = st
+        d["ranks"] = ranks[k]
+        d["trace"] = traces[k][:d["iterations"]] if trace else None
+        out.append(d)
     return out

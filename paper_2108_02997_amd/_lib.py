@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
 PR_FP64, PR_MIXED = 0, 1
-PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32 = 0, 1, 2, 3
+PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32, PR_KERNEL_MULTI = 0, 1, 2, 3, 4
 MAX_COLS = 16
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EGRAPH = 0, 1, -1, -2, -3, -4
 STATUS_NAMES = {0: "PR_OK", 1: "PR_NOT_CONVERGED", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE",
@@ -37,6 +37,13 @@ class pr_result(ctypes.Structure):
 class pr_problem(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("tau", ctypes.c_double), ("norm", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32)]
+
+
+class pr_graph_problem(ctypes.Structure):
+    _fields_ = [("in_offsets", ctypes.c_void_p), ("in_indices", ctypes.c_void_p), ("outdeg", ctypes.c_void_p),
+                ("N", ctypes.c_int64), ("E", ctypes.c_int64), ("prep", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("tau", ctypes.c_double), ("norm", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("init", ctypes.c_void_p), ("ranks", ctypes.c_void_p), ("norm_trace", ctypes.c_void_p)]
 
 
 class PrError(RuntimeError):
@@ -61,6 +68,9 @@ SIGNATURES = {
     "pr_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "pr_pull": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz,
                  ctypes.POINTER(pr_result)], ctypes.c_int),
+    "pr_multi_workspace_bytes": ([_i32, ctypes.POINTER(pr_graph_problem)], _sz),
+    "pr_pull_multi": ([_vp, _vp, _i32, ctypes.POINTER(pr_graph_problem), _vp, _sz, ctypes.POINTER(pr_result)],
+                      ctypes.c_int),
     "pr_l1_distance": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, ctypes.POINTER(_dbl)], ctypes.c_int),
     "pr_batch_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
     "pr_pull_batch": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem), _i32,

@@ -21,6 +21,7 @@
 #include "../../include/prpull.h"
 #include "batch.h"
 #include "internal.h"
+#include "multi.h"
 
 namespace prpull {
 
@@ -75,6 +76,8 @@ struct pr_ctx {
   unsigned long long *hscratch = nullptr;  // pinned host words for small read-backs
   BatchCols *hcols = nullptr;             // pinned staging of per-column parameters
   BatchState *hbstate = nullptr;          // pinned host copy of a batch state
+  void *hmulti = nullptr;                 // pinned staging of many-graph tables
+  size_t hmulti_bytes = 0;
   std::map<const void *, PrepHeader> preps;  // prep buffers prepared in this context
   std::vector<GraphEntry> graphs;
   uint64_t clock = 0;
@@ -85,6 +88,7 @@ struct pr_ctx {
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
   int64_t timing = 0;     // 1: bracket every update launch with HIP events
   int64_t batch_chunk = 2;  // updates between host checks of a batch solve (compaction points)
+  int64_t mid_deg = kMidDeg;  // lane-per-row / wave-per-row threshold of pr_pull
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
@@ -461,6 +465,7 @@ void pr_destroy(pr_ctx *ctx) {
   if (ctx->hscratch) (void)hipHostFree(ctx->hscratch);
   if (ctx->hcols) (void)hipHostFree(ctx->hcols);
   if (ctx->hbstate) (void)hipHostFree(ctx->hbstate);
+  if (ctx->hmulti) (void)hipHostFree(ctx->hmulti);
   delete ctx;
 }
 
@@ -481,6 +486,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->chunk = value;
+  } else if (!strcmp(key, "mid_deg")) {
+    if (value < 0 || value > kTile) {
+      set_error("mid_deg must be in [0, %d]", kTile);
+      return PR_EINVAL;
+    }
+    ctx->mid_deg = value;
   } else if (!strcmp(key, "batch_chunk")) {
     if (value < 1 || value > 64) {
       set_error("batch_chunk must be in [1, 64]");
@@ -656,6 +667,7 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   p.nhubs = part.nhubs;
   p.grid = (int32_t)grid;
   p.trace = norm_trace;
+  p.mid_deg = (int32_t)ctx->mid_deg;
 
   int fp32_iters = 0, fbuf = 0;
   const void *final_y = nullptr;
@@ -981,6 +993,180 @@ int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, 
   PR_HIP(hipStreamSynchronize(s));
   memcpy(out, ctx->hscratch, sizeof(double));
   return PR_OK;
+}
+
+static size_t multi_layout(int32_t G, const pr_graph_problem *probs, void *ws, MultiGraph **graphs,
+                           MultiGraphState **states, int32_t **tile_base, double **part, double **hpart,
+                           double **y, void **preps) {
+  Carver c(ws);
+  *graphs = (MultiGraph *)c.take(sizeof(MultiGraph) * (size_t)G);
+  *states = (MultiGraphState *)c.take(sizeof(MultiGraphState) * (size_t)G);
+  *tile_base = (int32_t *)c.take(sizeof(int32_t) * (size_t)(G + 1));
+  *part = (double *)c.take(sizeof(double) * 4 * (size_t)kMaxGrid * (size_t)G);
+  for (int g = 0; g < G; ++g) {
+    hpart[g] = (double *)c.take(sizeof(double) * (size_t)max_slots(probs[g].N, probs[g].E));
+    y[2 * g] = (double *)c.take(sizeof(double) * (size_t)probs[g].N);
+    y[2 * g + 1] = (double *)c.take(sizeof(double) * (size_t)probs[g].N);
+    preps[g] = probs[g].prep ? nullptr : c.take(prep_bytes(probs[g].N, probs[g].E));
+  }
+  return c.used;
+}
+
+size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs) {
+  if (G < 1 || G > kMaxGraphs || !probs) return 0;
+  for (int g = 0; g < G; ++g)
+    if (probs[g].N < 1 || probs[g].E < 0) return 0;
+  MultiGraph *a;
+  MultiGraphState *b;
+  int32_t *c;
+  double *d;
+  std::vector<double *> hp(G), y(2 * G);
+  std::vector<void *> pp(G);
+  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, hp.data(), y.data(), pp.data());
+}
+
+int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
+                  size_t workspace_bytes, pr_result *results) {
+  if (!ctx || !probs || !workspace || !results) {
+    set_error("pr_pull_multi: NULL argument");
+    return PR_EINVAL;
+  }
+  if (G < 1 || G > kMaxGraphs) {
+    set_error("G must be in [1, %d], got %d", kMaxGraphs, G);
+    return PR_EINVAL;
+  }
+  int max_rounds = 1;
+  int64_t total_tiles = 0;
+  for (int g = 0; g < G; ++g) {
+    const pr_graph_problem &q = probs[g];
+    if (!q.in_offsets || !q.outdeg || !q.ranks || (q.E > 0 && !q.in_indices)) {
+      set_error("graph %d: NULL graph or ranks pointer", g);
+      return PR_EINVAL;
+    }
+    if (bad_graph_sizes(q.N, q.E)) return PR_EINVAL;
+    if (!(q.alpha >= 0.0 && q.alpha <= 1.0) || !(q.tau >= 0.0) || q.norm < PR_L1 || q.norm > PR_LINF ||
+        q.max_iter < 1) {
+      set_error("graph %d: alpha in [0,1], tau >= 0, norm 1..3 and max_iter >= 1 are required", g);
+      return PR_EINVAL;
+    }
+    max_rounds = std::max(max_rounds, q.max_iter);
+  }
+  MultiGraph *dgraphs;
+  MultiGraphState *dstates;
+  int32_t *dbase;
+  double *dpart;
+  std::vector<double *> hpart(G), ybuf(2 * G);
+  std::vector<void *> ownprep(G);
+  const size_t need =
+      multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, hpart.data(), ybuf.data(), ownprep.data());
+  if (workspace_bytes < need) {
+    set_error("pr_pull_multi: workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return PR_ENOMEM;
+  }
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<MultiGraph> hg(G);
+  std::vector<int32_t> base(G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    const pr_graph_problem &q = probs[g];
+    PrepHeader h;
+    int rc;
+    const void *pp = q.prep;
+    if (!pp) {
+      rc = prepare_into(ctx, s, q.in_offsets, q.N, q.E, ownprep[g], &h);
+      pp = ownprep[g];
+    } else {
+      rc = get_prep(ctx, s, pp, q.N, q.E, &h);
+    }
+    if (rc != PR_OK) return rc;
+    const PrepPart &part = h.part[0];
+    MultiGraph &m = hg[g];
+    memset(&m, 0, sizeof m);
+    m.off = q.in_offsets;
+    m.idx = q.in_indices;
+    m.outdeg = q.outdeg;
+    m.desc = (const int4 *)((const char *)pp + part.desc_off);
+    m.hubs = (const int4 *)((const char *)pp + part.hub_off);
+    m.nhubs = part.nhubs;
+    m.hpart = hpart[g];
+    m.y[0] = ybuf[2 * g];
+    m.y[1] = ybuf[2 * g + 1];
+    m.init = q.init;
+    m.ranks = q.ranks;
+    m.trace = q.norm_trace;
+    m.alpha = q.alpha;
+    m.tau = q.tau;
+    m.N = (int32_t)q.N;
+    m.norm = q.norm;
+    m.max_iter = q.max_iter;
+    m.mid_deg = (int32_t)ctx->mid_deg;
+    total_tiles += part.ndesc;
+    if (total_tiles > 2147483647LL) {
+      set_error("pr_pull_multi: more than 2^31 tiles in one batch");
+      return PR_EINVAL;
+    }
+    base[g + 1] = (int32_t)total_tiles;
+  }
+  // stage the tables through pinned memory (synchronised before the buffer is reused)
+  const size_t tbytes = sizeof(MultiGraph) * (size_t)G + sizeof(int32_t) * (size_t)(G + 1);
+  if (ctx->hmulti_bytes < tbytes) {
+    if (ctx->hmulti) (void)hipHostFree(ctx->hmulti);
+    ctx->hmulti = nullptr;
+    ctx->hmulti_bytes = 0;
+    PR_HIP(hipHostMalloc(&ctx->hmulti, tbytes, hipHostMallocDefault));
+    ctx->hmulti_bytes = tbytes;
+  }
+  char *hm = (char *)ctx->hmulti;
+  memcpy(hm, hg.data(), sizeof(MultiGraph) * (size_t)G);
+  memcpy(hm + sizeof(MultiGraph) * (size_t)G, base.data(), sizeof(int32_t) * (size_t)(G + 1));
+  PR_HIP(hipMemcpyAsync(dgraphs, hm, sizeof(MultiGraph) * (size_t)G, hipMemcpyHostToDevice, s));
+  PR_HIP(hipMemcpyAsync(dbase, hm + sizeof(MultiGraph) * (size_t)G, sizeof(int32_t) * (size_t)(G + 1),
+                        hipMemcpyHostToDevice, s));
+  MultiParams p{};
+  p.graphs = dgraphs;
+  p.states = dstates;
+  p.tile_base = dbase;
+  p.part = dpart;
+  p.G = G;
+  p.total_tiles = (int32_t)total_tiles;
+  p.max_rounds = max_rounds;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
+  const int64_t resident = (int64_t)cus * multi_blocks_per_cu();
+  int64_t grid = ctx->max_grid > 0 ? std::min<int64_t>(ctx->max_grid, resident) : resident;
+  grid = std::max<int64_t>(1, std::min<int64_t>({grid, total_tiles > 0 ? total_tiles : 1, (int64_t)kMaxGrid}));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    PR_HIP(hipEventCreate(&e0));
+    PR_HIP(hipEventCreate(&e1));
+    PR_HIP(hipEventRecord(e0, s));
+  }
+  PR_HIP(launch_multi(s, (unsigned)grid, p, 64));
+  if (ctx->timing) PR_HIP(hipEventRecord(e1, s));
+  std::vector<MultiGraphState> hs(G);
+  PR_HIP(hipMemcpyAsync(ctx->hmulti, dstates, sizeof(MultiGraphState) * (size_t)G, hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  memcpy(hs.data(), ctx->hmulti, sizeof(MultiGraphState) * (size_t)G);
+  if (ctx->timing) {
+    float ms = 0.f;
+    PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ctx->stat_ms[PR_KERNEL_MULTI] += ms;
+    ctx->stat_launches[PR_KERNEL_MULTI] += 1;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  int all = 1;
+  for (int g = 0; g < G; ++g) {
+    results[g].iterations = hs[g].iters;
+    results[g].converged = hs[g].converged;
+    results[g].fp32_iters = 0;
+    results[g].fp64_iters = hs[g].iters;
+    results[g].final_err[0] = hs[g].err[0];
+    results[g].final_err[1] = hs[g].err[1];
+    results[g].final_err[2] = hs[g].err[2];
+    all &= hs[g].converged;
+  }
+  return all ? PR_OK : PR_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -29,10 +29,13 @@ constexpr int kRowsB = 128;
 constexpr int kSpanB = 2 * kTileB;
 constexpr int kPartTile[2] = {kTile, kTileB};
 constexpr int kPartRows[2] = {kRows, kRowsB};
-// Rows with in-degree above kMidDeg (and at most kTile) are summed by a whole wave.
+// Default threshold: rows with in-degree above kMidDeg (and at most the tile window) are summed by
+// a whole wave; pr_pull takes the threshold at run time (option "mid_deg", or the autotuner).
 constexpr int kMidDeg = 32;
 // Upper bound of the update grid (blocks loop over tiles in a fixed round-robin order).
 constexpr int kMaxGrid = 16384;
+// Graphs of one many-graph batch.
+constexpr int kMaxGraphs = 4096;
 // The finishing kernel runs as one block of kFinBlock lanes.
 constexpr int kFinBlock = 1024;
 
@@ -98,7 +101,7 @@ struct IterParams {
   int32_t norm;
   int32_t max_iter;
   int32_t phase;       // 0: float64 solve, 1: float32 phase of a mixed solve, 2: float64 phase
-  int32_t pad;
+  int32_t mid_deg;     // rows of a tile with more entries are summed by a whole wave (<= kTile)
   SolveState *st;
   double *bpart;       // [grid][4] block partials: L1, sum sq, Linf, dangling sum
   double *hpart;       // hub segment partial sums

@@ -1,0 +1,52 @@
+// multi.h -- device structures of the many-graph persistent solve (multi.hip).
+#pragma once
+
+#include "device.h"
+
+namespace prpull {
+
+struct MultiGraph {
+  const int32_t *off;
+  const int32_t *idx;
+  const int32_t *outdeg;
+  const int4 *desc;    // partition A tiles of this graph (sentinel included)
+  const int4 *hubs;
+  double *hpart;       // hub segment partial sums
+  double *y[2];        // iterate buffers
+  const double *init;  // start vector or null (1/N)
+  double *ranks;       // output
+  double *trace;       // [max_iter][3] or null
+  double alpha;
+  double tau;
+  int32_t N;
+  int32_t nhubs;
+  int32_t norm;
+  int32_t max_iter;
+  int32_t mid_deg;
+  int32_t pad;
+};
+
+struct MultiGraphState {
+  double c0;
+  double err[3];
+  int32_t iters;
+  int32_t active;
+  int32_t converged;
+  int32_t pad;
+};
+
+struct MultiParams {
+  const MultiGraph *graphs;
+  MultiGraphState *states;
+  const int32_t *tile_base;  // [G+1]: first global tile of each graph
+  double *part;              // [grid][G][4] per-workgroup partials (also init scratch)
+  int32_t G;
+  int32_t total_tiles;
+  int32_t max_rounds;
+  int32_t pad;
+};
+
+int multi_blocks_per_cu();
+hipError_t launch_multi(hipStream_t s, unsigned grid, const MultiParams &p, int32_t init_blocks);
+
+}  // namespace prpull
