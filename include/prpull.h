@@ -92,6 +92,7 @@ const char *pr_version(void);
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
  *   "mid_deg": rows of at most this many in-edges are summed by one lane, longer rows (up to the
  *             1024-entry tile window) by a whole wave64, 0..1024 (default 32)
+ *   "tuned" : 1 (default) = use the autotuner's choice for graphs it has seen (pr_autotune)
  *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
@@ -223,6 +224,28 @@ size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs);
  * PR_NOT_CONVERGED otherwise (see results[g].converged), or a negative status. */
 int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
                   size_t workspace_bytes, pr_result *results);
+
+/* ------------------------------------------------------------------ autotuner */
+
+typedef struct {
+  int32_t mid_deg;    /* chosen lane-per-row / wave-per-row threshold */
+  int32_t grid;       /* chosen number of update workgroups */
+  int32_t candidates; /* configurations timed */
+  int32_t pad;
+  double best_us;     /* mean float64 update time of the choice, microseconds */
+  double default_us;  /* the same with the defaults (threshold 32, one workgroup per resident slot) */
+} pr_tune_result;
+
+/* Times four float64 updates of this graph for every candidate (threshold 8/16/32/64/128 x
+ * 1/2/4 workgroups per resident slot) and keeps the fastest in the context's table, keyed by
+ * the graph's size and tile counts; pr_pull and pr_pull_multi then use it for graphs with that
+ * signature unless "grid" / "mid_deg" were set explicitly or "tuned" is 0.  With the
+ * environment variable PRPULL_TUNE_FILE set, the table is read at pr_create and every choice is
+ * appended to that file.  ranks: device scratch of N values; workspace as for pr_pull.
+ * Statistics of pr_get_stats are left as they were. */
+int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
+                size_t workspace_bytes, pr_tune_result *out);
 
 /* L1 distance sum_v |x_v - y_v| of two device vectors of N float64 values, reduced in a fixed
  * order (section 2 reports each damping factor's ranks by this distance to the alpha = 0.85

@@ -107,6 +107,20 @@ class DeviceGraph:
             self._ws[key] = ws
         return ws
 
+    def autotune(self, ctx: Context) -> dict:
+        """pr_autotune: pick the lane/wave threshold and the update grid for this graph (kept in ctx)."""
+        if self.prep is None:
+            self.prepare(ctx)
+        ranks = torch.empty(self.N, dtype=torch.float64, device=self.off.device)
+        ws = self.workspace(ctx, PR_FP64, False)
+        out = _lib.pr_tune_result()
+        _lib.check("pr_autotune", ctx.lib.pr_autotune(ctx.handle, ctx.stream, self.off.data_ptr(),
+                                                      _lib.ptr(self.idx) if self.E else None, self.outdeg.data_ptr(),
+                                                      self.N, self.E, self.prep.data_ptr(), ranks.data_ptr(),
+                                                      ws.data_ptr(), ws.numel(), ctypes.byref(out)))
+        return dict(mid_deg=out.mid_deg, grid=out.grid, candidates=out.candidates, best_us=out.best_us,
+                    default_us=out.default_us)
+
     def validate(self, ctx: Context) -> None:
         nbytes = 4 * self.N + 512
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)

@@ -46,6 +46,11 @@ class pr_graph_problem(ctypes.Structure):
                 ("init", ctypes.c_void_p), ("ranks", ctypes.c_void_p), ("norm_trace", ctypes.c_void_p)]
 
 
+class pr_tune_result(ctypes.Structure):
+    _fields_ = [("mid_deg", ctypes.c_int32), ("grid", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+
 class PrError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__("%s returned %s: %s" % (fn, STATUS_NAMES.get(status, status), msg))
@@ -71,6 +76,8 @@ SIGNATURES = {
     "pr_multi_workspace_bytes": ([_i32, ctypes.POINTER(pr_graph_problem)], _sz),
     "pr_pull_multi": ([_vp, _vp, _i32, ctypes.POINTER(pr_graph_problem), _vp, _sz, ctypes.POINTER(pr_result)],
                       ctypes.c_int),
+    "pr_autotune": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _sz, ctypes.POINTER(pr_tune_result)],
+                    ctypes.c_int),
     "pr_l1_distance": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, ctypes.POINTER(_dbl)], ctypes.c_int),
     "pr_batch_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
     "pr_pull_batch": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem), _i32,

@@ -89,6 +89,10 @@ struct pr_ctx {
   int64_t timing = 0;     // 1: bracket every update launch with HIP events
   int64_t batch_chunk = 2;  // updates between host checks of a batch solve (compaction points)
   int64_t mid_deg = kMidDeg;  // lane-per-row / wave-per-row threshold of pr_pull
+  bool mid_deg_set = false;   // set explicitly (overrides the autotuner's choice)
+  int64_t use_tuned = 1;      // 1: use autotuned settings of graphs with a known signature
+  std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;  // signature -> (mid_deg, grid)
+  std::string tune_file;
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
@@ -406,6 +410,47 @@ ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int C, unsigned grid, const BatchP
   return c;
 }
 
+// Graph signature for the autotuner's table: sizes and the tile counts of both partitions.
+std::vector<int64_t> graph_signature(const PrepHeader &h) {
+  return {h.N, h.E, h.part[0].ndesc, h.part[0].nhubs, h.part[0].nslots, h.part[1].ndesc};
+}
+
+// (mid_deg, grid cap) for a graph: explicit options first, then the autotuner's table, then defaults.
+std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h) {
+  int32_t mid = (int32_t)ctx->mid_deg;
+  int64_t grid = ctx->max_grid;
+  if (ctx->use_tuned) {
+    auto it = ctx->tuned.find(graph_signature(h));
+    if (it != ctx->tuned.end()) {
+      if (!ctx->mid_deg_set) mid = it->second.first;
+      if (ctx->max_grid == 0) grid = it->second.second;
+    }
+  }
+  return {mid, grid};
+}
+
+void load_tune_file(pr_ctx *ctx) {
+  const char *f = getenv("PRPULL_TUNE_FILE");
+  if (!f || !*f) return;
+  ctx->tune_file = f;
+  FILE *fp = fopen(f, "r");
+  if (!fp) return;
+  long long s[6];
+  int m, g;
+  while (fscanf(fp, "%lld %lld %lld %lld %lld %lld %d %d", &s[0], &s[1], &s[2], &s[3], &s[4], &s[5], &m, &g) == 8)
+    ctx->tuned[{s[0], s[1], s[2], s[3], s[4], s[5]}] = {m, g};
+  fclose(fp);
+}
+
+void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid) {
+  if (ctx->tune_file.empty()) return;
+  FILE *fp = fopen(ctx->tune_file.c_str(), "a");
+  if (!fp) return;
+  fprintf(fp, "%lld %lld %lld %lld %lld %lld %d %d\n", (long long)sig[0], (long long)sig[1], (long long)sig[2],
+          (long long)sig[3], (long long)sig[4], (long long)sig[5], mid, grid);
+  fclose(fp);
+}
+
 }  // namespace
 
 extern "C" {
@@ -433,6 +478,7 @@ int pr_create(pr_ctx **out, int device) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
   c->resident[0] = (int64_t)cus * update_blocks_per_cu(false);
   c->resident[1] = (int64_t)cus * update_blocks_per_cu(true);
+  load_tune_file(c);
   hipError_t e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hstate, sizeof(SolveState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscratch, 64 * sizeof(unsigned long long), hipHostMallocDefault);
@@ -492,6 +538,13 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->mid_deg = value;
+    ctx->mid_deg_set = true;
+  } else if (!strcmp(key, "tuned")) {
+    if (value != 0 && value != 1) {
+      set_error("tuned must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->use_tuned = value;
   } else if (!strcmp(key, "batch_chunk")) {
     if (value < 1 || value > 64) {
       set_error("batch_chunk must be in [1, 64]");
@@ -645,7 +698,8 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   if (rc != PR_OK) return rc;
 
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
-  const int64_t gcap = ctx->max_grid > 0 ? ctx->max_grid : ctx->resident[precision == PR_MIXED ? 1 : 0];
+  const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
+  const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_MIXED ? 1 : 0];
   const PrepPart &part = h.part[0];
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
 
@@ -667,7 +721,7 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   p.nhubs = part.nhubs;
   p.grid = (int32_t)grid;
   p.trace = norm_trace;
-  p.mid_deg = (int32_t)ctx->mid_deg;
+  p.mid_deg = ts.first;
 
   int fp32_iters = 0, fbuf = 0;
   const void *final_y = nullptr;
@@ -1099,7 +1153,7 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     m.N = (int32_t)q.N;
     m.norm = q.norm;
     m.max_iter = q.max_iter;
-    m.mid_deg = (int32_t)ctx->mid_deg;
+    m.mid_deg = tuned_settings(ctx, h).first;
     total_tiles += part.ndesc;
     if (total_tiles > 2147483647LL) {
       set_error("pr_pull_multi: more than 2^31 tiles in one batch");
@@ -1167,6 +1221,93 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     all &= hs[g].converged;
   }
   return all ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
+                size_t workspace_bytes, pr_tune_result *out) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices)) {
+    set_error("pr_autotune: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  const Layout L = carve(workspace, N, E, PR_FP64, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_autotune: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  const void *pp = prep;
+  int rc;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+  // candidates: lane/wave threshold x update grid (in resident workgroups)
+  const int32_t mids[] = {8, 16, 32, 64, 128};
+  const int64_t res = ctx->resident[0];
+  const int64_t grids[] = {res, 2 * res, 4 * res};
+  const int64_t save_grid = ctx->max_grid, save_mid = ctx->mid_deg, save_timing = ctx->timing;
+  const bool save_set = ctx->mid_deg_set;
+  const int64_t save_tuned = ctx->use_tuned;
+  int64_t save_launch[PR_KERNEL_KINDS];
+  double save_ms[PR_KERNEL_KINDS];
+  memcpy(save_launch, ctx->stat_launches, sizeof save_launch);
+  memcpy(save_ms, ctx->stat_ms, sizeof save_ms);
+  ctx->use_tuned = 0;
+  ctx->mid_deg_set = true;
+  ctx->timing = 1;
+  double best = 1e300, dflt = 0.0;
+  int32_t best_mid = kMidDeg, best_grid = (int32_t)std::min<int64_t>(res, kMaxGrid);
+  int count = 0;
+  constexpr int kReps = 4;
+  for (int64_t gsz : grids) {
+    if (gsz > kMaxGrid) continue;
+    for (int32_t m : mids) {
+      ctx->max_grid = gsz;
+      ctx->mid_deg = m;
+      ctx->stat_launches[PR_KERNEL_UPDATE_F64] = 0;
+      ctx->stat_ms[PR_KERNEL_UPDATE_F64] = 0.0;
+      pr_result r;
+      rc = pr_pull(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, 0.85, 0.0, PR_L1, kReps, PR_FP64, nullptr,
+                   ranks, nullptr, workspace, workspace_bytes, &r);
+      if (rc < 0) break;
+      const double us = ctx->stat_launches[PR_KERNEL_UPDATE_F64]
+                            ? 1e3 * ctx->stat_ms[PR_KERNEL_UPDATE_F64] / ctx->stat_launches[PR_KERNEL_UPDATE_F64]
+                            : 1e300;
+      ++count;
+      if (gsz == res && m == kMidDeg) dflt = us;
+      if (us < best) {
+        best = us;
+        best_mid = m;
+        best_grid = (int32_t)gsz;
+      }
+    }
+    if (rc < 0) break;
+  }
+  ctx->max_grid = save_grid;
+  ctx->mid_deg = save_mid;
+  ctx->mid_deg_set = save_set;
+  ctx->timing = save_timing;
+  ctx->use_tuned = save_tuned;
+  memcpy(ctx->stat_launches, save_launch, sizeof save_launch);
+  memcpy(ctx->stat_ms, save_ms, sizeof save_ms);
+  if (rc < 0) return rc;
+  const std::vector<int64_t> sig = graph_signature(h);
+  ctx->tuned[sig] = {best_mid, best_grid};
+  save_tune_entry(ctx, sig, best_mid, best_grid);
+  out->mid_deg = best_mid;
+  out->grid = best_grid;
+  out->candidates = count;
+  out->pad = 0;
+  out->best_us = best;
+  out->default_us = dflt;
+  return PR_OK;
 }
 
 }  // extern "C"

@@ -255,3 +255,29 @@ def test_prep_mismatch_rejected(pr, ctx):
     b.prep = a.prep
     with pytest.raises(pr.PrError):
         pr.pull(ctx, b)
+
+
+def test_autotune_then_parity(pr, ctx):
+    g = gg.rmat(15, seed=31)
+    dg = dev(pr, g)
+    t = dg.autotune(ctx)
+    assert t["candidates"] == 15 and t["mid_deg"] in (8, 16, 32, 64, 128) and t["grid"] >= 1
+    assert t["best_us"] <= t["default_us"]
+    res, ref = check_fp64(pr, ctx, g, alpha=0.9, tau=1e-10, norm=1, dg=dg)
+    assert res["iterations"] == ref["iterations"]
+    m = pr.pull_multi(ctx, [dg, dev(pr, gg.workload_c1())],
+                      [dict(alpha=0.9, tau=1e-10, norm=1, max_iter=500), dict(alpha=0.85, tau=1e-6, norm=1,
+                                                                              max_iter=500)])
+    assert m[0]["iterations"] == ref["iterations"]
+    assert np.abs(m[0]["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+
+
+@pytest.mark.parametrize("mid", [0, 1, 1024])
+def test_row_threshold_extremes(pr, ctx, mid):
+    # mid_deg 0: every non-empty row of a tile by a wave; 1024: every row by one lane
+    g = gg.rmat(14, seed=32)
+    try:
+        ctx.set_option("mid_deg", mid)
+        check_fp64(pr, ctx, g, tau=1e-10, norm=3)
+    finally:
+        ctx.set_option("mid_deg", 32)
