@@ -247,6 +247,49 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
                 const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
                 size_t workspace_bytes, pr_tune_result *out);
 
+/* ------------------------------------------------------------------ learned warm start
+ * Not in the paper (its method is the iteration; this only proposes where the iteration starts).
+ * A per-vertex perceptron 5 -> 32 -> 32 -> 1 with ReLU, float32 weights, bfloat16 activations and
+ * float32 accumulation.  Packed weights W (pr_mlp_param_count() = 1281 floats):
+ *   W1[32][5] | b1[32] | W2[32][32] | b2[32] | W3[32] | b3
+ * Features (float32 [N][5]): log(1 + in-degree), log(1 + out-degree), log(N r_v), log(N m_v) with
+ * m_v the mean of r over v's in-edges (1/N without in-edges), target alpha.  The output y_v is
+ * added to log(N r_v): the proposed start is r0_v proportional to exp(log(N r_v) + y_v). */
+int pr_mlp_param_count(void);
+
+/* Features from the ranks r085 (device, N float64, e.g. the alpha = 0.85 solution) into feat
+ * (device, float32 [N][5]).  prep: pr_prepare output of the graph (its hub table).  For training,
+ * r_target (device, N float64, the ranks at alpha_target) and target (device, N float32) may be
+ * given together: target_v = log(r_target_v / r085_v), the value the network's output should take.
+ * Async. */
+int pr_features(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+                int64_t N, int64_t E, const void *prep, const double *r085, double alpha_target, float *feat,
+                const double *r_target, float *target);
+
+/* y = MLP(feat) (device float32 [N]); act_save (device, bfloat16 bits [N][64]: the two hidden
+ * layers after ReLU) is written for the backward pass unless NULL.  Async. */
+int pr_mlp_forward(pr_ctx *ctx, void *stream, const float *W, const float *feat, int64_t N, float *y,
+                   uint16_t *act_save);
+
+/* Gradient dW (device, 1281 floats) of the mean squared error mean_v (y_v - target_v)^2 from a
+ * forward pass's y and act_save; loss (host) receives the error.  Block partials are reduced in
+ * a fixed order (repeatable).  workspace: device, pr_mlp_backward_workspace_bytes(N).
+ * Synchronises the stream. */
+size_t pr_mlp_backward_workspace_bytes(int64_t N);
+int pr_mlp_backward(pr_ctx *ctx, void *stream, const float *W, const float *feat, const uint16_t *act_save,
+                    const float *y, const float *target, int64_t N, float *dW, void *workspace, size_t workspace_bytes,
+                    double *loss);
+
+/* One Adam update (Kingma and Ba 2015, Algorithm 1) of W with gradient dW and moments m, v (device,
+ * n_params floats each); step counts from 1.  Async. */
+int pr_adam_step(pr_ctx *ctx, void *stream, float *W, const float *dW, float *m, float *v, int32_t n_params, float lr,
+                 float beta1, float beta2, float eps, int32_t step);
+
+/* The proposed start vector r0 (device, N float64, sums to 1) from feat and the MLP output y.
+ * workspace: device, at least 8192 bytes.  Async. */
+int pr_warm_start_vector(pr_ctx *ctx, void *stream, const float *feat, const float *y, int64_t N, double *r0,
+                         void *workspace, size_t workspace_bytes);
+
 /* L1 distance sum_v |x_v - y_v| of two device vectors of N float64 values, reduced in a fixed
  * order (section 2 reports each damping factor's ranks by this distance to the alpha = 0.85
  * ranks).  workspace: device, at least 8200 bytes.  out: host.  Synchronises the stream. */

@@ -78,6 +78,14 @@ SIGNATURES = {
                       ctypes.c_int),
     "pr_autotune": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _sz, ctypes.POINTER(pr_tune_result)],
                     ctypes.c_int),
+    "pr_mlp_param_count": ([], ctypes.c_int),
+    "pr_features": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _dbl, _vp, _vp, _vp], ctypes.c_int),
+    "pr_mlp_forward": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "pr_mlp_backward_workspace_bytes": ([_i64], _sz),
+    "pr_mlp_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz, ctypes.POINTER(_dbl)], ctypes.c_int),
+    "pr_adam_step": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, _i32], ctypes.c_int),
+    "pr_warm_start_vector": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz], ctypes.c_int),
     "pr_l1_distance": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, ctypes.POINTER(_dbl)], ctypes.c_int),
     "pr_batch_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
     "pr_pull_batch": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem), _i32,

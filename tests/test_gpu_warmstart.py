@@ -1,0 +1,156 @@
+"""Learned warm start: GPU kernels against oracle.mlp, and what the trained network gains.
+
+Forward tolerance (derived, per vertex): each hidden activation is rounded to bfloat16 (relative
+error <= 2^-9), so |y_gpu - y| <= 2^-9 * (sum_j |W3_j| h2_j + sum_j |W3_j| sum_k |W2_jk| h1_k) plus
+float32 accumulation noise; the test allows twice that bound plus 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2108_02997_amd as pr
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return pr
+
+
+@pytest.fixture(scope="module")
+def ws(pr):
+    from paper_2108_02997_amd import warmstart
+    return warmstart
+
+
+@pytest.fixture(scope="module")
+def ctx(pr):
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def test_features_and_target(pr, ws, ctx):
+    rng = np.random.default_rng(0)
+    N = 40000
+    src, dst = [], []
+    for v, deg in ((0, 20000), (1, 9000), (2, 3000)):
+        src.extend(rng.choice(N, size=deg, replace=False).tolist())
+        dst.extend([v] * deg)
+    src.extend(rng.integers(0, N, 100000).tolist())
+    dst.extend(rng.integers(0, N, 100000).tolist())
+    g = gg.from_edges(N, src, dst)
+    r85 = oracle.pagerank_graph(g, alpha=0.85, tau=1e-12)["ranks"]
+    r95 = oracle.pagerank_graph(g, alpha=0.95, tau=1e-12)["ranks"]
+    dg = pr.DeviceGraph.from_host(g)
+    feat, target = ws.features(ctx, dg, torch.from_numpy(r85).cuda(), 0.95, torch.from_numpy(r95).cuda())
+    ref = omlp.features(g.N, g.off, g.idx, g.outdeg, r85, 0.95)
+    np.testing.assert_allclose(feat.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(target.cpu().numpy(), np.log(r95 / r85), rtol=2e-6, atol=2e-6)
+
+
+def forward_bound(W, cache):
+    p = omlp.unpack(W)
+    a3 = np.abs(p["W3"])
+    t1 = cache["h2"] @ a3
+    t2 = cache["h1"] @ (np.abs(p["W2"]).T @ a3)
+    return 2.0 * 2.0 ** -9 * (t1 + t2) + 1e-5
+
+
+def test_forward_backward_adam_against_oracle(pr, ws, ctx):
+    rng = np.random.default_rng(1)
+    n = 5000
+    X = np.column_stack([rng.uniform(0, 6, n), rng.uniform(0, 6, n), rng.normal(0, 2, n), rng.normal(0, 2, n),
+                         np.full(n, 0.9)]).astype(np.float32)
+    W = ws.init_params(3).cpu().numpy().astype(np.float64)
+    W[-33:-1] *= 10.0  # a less trivial last layer
+    Wt = torch.from_numpy(W.astype(np.float32)).cuda()
+    feat = torch.from_numpy(X).cuda()
+    y, act = ws.forward(ctx, Wt, feat, keep_activations=True)
+    yr, cache = omlp.forward(W.astype(np.float32).astype(np.float64), X.astype(np.float64))
+    bound = forward_bound(W.astype(np.float32).astype(np.float64), cache)
+    err = np.abs(y.cpu().numpy() - yr)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    target = (yr + rng.normal(0, 0.5, n)).astype(np.float32)
+    dW, loss = ws.backward(ctx, Wt, feat, act, y, torch.from_numpy(target).cuda())
+    # The loss and its gradient are checked at the GPU's own outputs and activations: the ReLU
+    # masks are decisions taken on the bfloat16 activations, so the FP64 chain rule is applied to
+    # the same saved activations; what remains is float32 accumulation, bounded relative to the
+    # sum of absolute terms (the same chain rule on |W| and |dy|).
+    yg = y.cpu().numpy().astype(np.float64)
+    lref, dy = omlp.mse(yg, target)
+    assert abs(loss - lref) <= 1e-6 * lref
+    bits = act.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    hv = bits.view(np.float32).astype(np.float64)
+    h1g, h2g = hv[:, :32], hv[:, 32:]
+    cache_g = dict(X=X.astype(np.float64), z1=h1g, h1=h1g, z2=h2g, h2=h2g)
+    W64 = W.astype(np.float32).astype(np.float64)
+    gref = omlp.backward(W64, cache_g, dy)
+    gabs = omlp.backward(np.abs(W64), dict(X=np.abs(cache_g["X"]), z1=h1g, h1=h1g, z2=h2g, h2=h2g), np.abs(dy))
+    g = dW.cpu().numpy()
+    assert np.all(np.abs(g - gref) <= 1e-3 * gabs + 1e-12), float(np.max(np.abs(g - gref) / (gabs + 1e-30)))
+    # repeatable: fixed-order reductions
+    dW2, loss2 = ws.backward(ctx, Wt, feat, act, y, torch.from_numpy(target).cuda())
+    assert torch.equal(dW, dW2) and loss == loss2
+    # Adam from zero moments, two steps
+    m = torch.zeros_like(Wt)
+    v = torch.zeros_like(Wt)
+    Wg = Wt.clone()
+    ws.adam_step(ctx, Wg, dW, m, v, 1, lr=1e-2)
+    ws.adam_step(ctx, Wg, dW, m, v, 2, lr=1e-2)
+    Wr, mr, vr = omlp.adam(W.astype(np.float32).astype(np.float64), g.astype(np.float64), np.zeros_like(W),
+                           np.zeros_like(W), 1, lr=1e-2)
+    Wr, mr, vr = omlp.adam(Wr, g.astype(np.float64), mr, vr, 2, lr=1e-2)
+    np.testing.assert_allclose(Wg.cpu().numpy(), Wr, rtol=1e-5, atol=1e-6)
+
+
+def test_start_vector(pr, ws, ctx):
+    rng = np.random.default_rng(2)
+    n = 3000
+    X = np.zeros((n, 5), np.float32)
+    X[:, 2] = rng.normal(0, 2, n)
+    y = rng.normal(0, 0.3, n).astype(np.float32)
+    r0 = ws.start_vector(ctx, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()).cpu().numpy()
+    np.testing.assert_allclose(r0, omlp.start_vector(X.astype(np.float64), y.astype(np.float64)), rtol=1e-12)
+    assert abs(r0.sum() - 1.0) < 1e-13
+
+
+def test_trained_network_gains_over_uniform_start(pr, ws, ctx):
+    # train on six seeded R-MAT scale-14 graphs, evaluate on an unseen scale-15 graph
+    model = ws.WarmStart(ctx, seed=0)
+    train_alphas = [0.5, 0.6, 0.7, 0.75, 0.8, 0.9, 0.95, 0.99]
+    samples = []
+    for s in range(6):
+        samples += model.make_samples(pr.DeviceGraph.from_host(gg.rmat(14, seed=2000 + s)), train_alphas)
+    hist = model.train(samples, epochs=25, lr=3e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    g = gg.rmat(15, seed=3000)
+    dg = pr.DeviceGraph.from_host(g)
+    r85 = pr.pull(ctx, dg, alpha=0.85, tau=1e-12, norm=1)["ranks"]
+    report = []
+    for alpha in (0.9, 0.95, 0.99):
+        uni = pr.pull(ctx, dg, alpha=alpha, tau=1e-10, norm=3)
+        from85 = pr.pull(ctx, dg, alpha=alpha, tau=1e-10, norm=3, init=r85)
+        mlp_r0 = model.propose(dg, r85, alpha)
+        frommlp = pr.pull(ctx, dg, alpha=alpha, tau=1e-10, norm=3, init=mlp_r0)
+        chosen, name, e, _ = model.start(dg, r85, alpha, norm=3)
+        judged = pr.pull(ctx, dg, alpha=alpha, tau=1e-10, norm=3, init=chosen)
+        report.append((alpha, uni["iterations"], from85["iterations"], frommlp["iterations"], name,
+                       judged["iterations"]))
+        # the judge never picks a start whose first update moves more than the uniform start's
+        assert e[("mlp", "r085", "uniform").index(name)] <= e[2]
+        # corrected ranks agree with the oracle's (L1 a-posteriori bound of the section-2 map)
+        ref = oracle.pagerank_graph(g, alpha=alpha, tau=1e-10, norm=3)
+        d = np.abs(frommlp["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert d <= alpha / (1 - alpha) * (frommlp["err"][0] + ref["err"][0]) + 1e-12
+    print("warm start iterations (alpha, uniform, r085, mlp, judged choice, judged):", report)
+    assert sum(r[3] for r in report) < sum(r[1] for r in report)
+    assert sum(r[5] for r in report) <= sum(r[1] for r in report)
