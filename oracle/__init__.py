@@ -106,15 +106,25 @@ def pagerank_graph(g, **kw):
     return pagerank(g.N, g.off, g.idx, g.outdeg, **kw)
 
 
+def _compensated_sum(xs):
+    """Neumaier's compensated running sum, step for step as in the C oracle."""
+    s = c = 0.0
+    for x in xs:
+        t = s + x
+        if abs(s) >= abs(x):
+            c += (s - t) + x
+        else:
+            c += (x - t) + s
+        s = t
+    return s + c
+
+
 def pagerank_py(N, off, idx, outdeg, alpha=0.85, tau=1e-6, norm=L1, max_iter=500, init=None):
     """The same definition as pure-Python loops (tiny graphs only)."""
     r = [1.0 / N] * N if init is None else [float(x) for x in init]
     errs = (0.0, 0.0, 0.0)
     for k in range(1, max_iter + 1):
-        D = 0.0
-        for u in range(N):
-            if outdeg[u] == 0:
-                D += r[u]
+        D = _compensated_sum(r[u] for u in range(N) if outdeg[u] == 0)
         c0 = (1.0 - alpha) / N + (alpha * D) / N
         rn = []
         for v in range(N):
@@ -124,7 +134,7 @@ def pagerank_py(N, off, idx, outdeg, alpha=0.85, tau=1e-6, norm=L1, max_iter=500
                 s += r[u] / float(outdeg[u])
             rn.append(c0 + alpha * s)
         d = [abs(a - b) for a, b in zip(rn, r)]
-        errs = (sum(d), math.sqrt(sum(x * x for x in d)), max(d))
+        errs = (_compensated_sum(d), math.sqrt(_compensated_sum(x * x for x in d)), max(d))
         r = rn
         if errs[norm - 1] < tau:
             return dict(ranks=np.array(r), iterations=k, converged=True, err=errs)

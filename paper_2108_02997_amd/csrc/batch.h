@@ -85,7 +85,7 @@ __device__ __forceinline__ void batch_finalize_column(const BatchParams &p, int 
   const bool met = (nk == 1 ? e[0] : nk == 2 ? e[1] : e[2]) < cp.tau[k];
   if (p.phase == 1) {
     if (met) cs.met32 = 1;
-    if (met || !(l1 < cs.prev_l1)) cs.active = 0;
+    if (met || !(l1 < cs.prev_l1) || (nk == 1 && l1 < kL1Handover)) cs.active = 0;
     cs.prev_l1 = l1;
     if (it >= cp.max_iter[k]) {
       cs.active = 0;

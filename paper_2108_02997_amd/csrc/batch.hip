@@ -55,10 +55,11 @@ struct BAcc {
 };
 
 // Per-column epilogue of one row for the lane's C columns.
+// c0 and alpha point at the teleport terms and damping factors of the lane's C columns.
 template <typename VT, int C>
 __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VT *__restrict__ yin,
-                                               VT *__restrict__ yout, int kp, int col0, const double (&c0)[C],
-                                               const double (&alpha)[C], const bool (&act)[C], BAcc (&a)[C]) {
+                                               VT *__restrict__ yout, int kp, int col0, const double *c0,
+                                               const double *alpha, const bool (&act)[C], BAcc (&a)[C]) {
 #pragma clang fp contract(off)
   const int64_t base = (int64_t)v * kp + col0;
 #pragma unroll
@@ -87,7 +88,7 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
 }
 
 template <typename VT, int C>
-__global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
+__global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k_batch_update(BatchParams p) {
   constexpr int KP = 4 * C;
   constexpr int kQuads = kBlock / 4;             // 64 quads per block
   constexpr int kPerQ = kSpanB / kQuads;         // entries gathered per quad per tile (8)
@@ -95,20 +96,24 @@ __global__ __launch_bounds__(kBlock) void k_batch_update(BatchParams p) {
   __shared__ VT vals[kSpanB * KP];
   __shared__ double sred[kWaves][KP];
   __shared__ double sacc[kWaves][KP][4];
+  __shared__ double sc0[KP], salpha[KP];  // per-column terms in LDS rather than 2*C registers
   const BatchState *st = p.st;
   if (st->head.stop) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int qp = lane & 3, quad = t >> 2;  // quad 0..63 in the block
   const int col0 = qp * C;
-  double c0[C], alpha[C];
+  if (t < KP) {
+    sc0[t] = st->col[t].c0;
+    salpha[t] = p.cols->alpha[t];
+  }
   bool act[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int k = col0 + c;
     act[c] = k < p.K && st->col[k].active;
-    c0[c] = st->col[k].c0;
-    alpha[c] = p.cols->alpha[k];
   }
+  const double *c0 = sc0 + col0, *alpha = salpha + col0;
+  __syncthreads();
   const VT *__restrict__ yin = (const VT *)p.y_in;
   VT *__restrict__ yout = (VT *)p.y_out;
   const int32_t *__restrict__ off = p.off;
@@ -308,11 +313,10 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
 #pragma unroll 1
       for (int32_t q = 0; q < hb.y; ++q) s += p.hpart[(int64_t)(hb.z + q) * KP + k];
       double sv[1] = {s};
-      double c0a[1] = {c0}, ala[1] = {alpha};
       bool act[1] = {true};
       BAcc aa[1] = {a};
       // the epilogue addresses column k of row hb.x
-      batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, c0a, ala, act, aa);
+      batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, &c0, &alpha, act, aa);
       a = aa[0];
     }
     for (int32_t b = g; b < p.grid; b += kGroups) {

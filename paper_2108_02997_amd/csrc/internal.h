@@ -38,6 +38,13 @@ constexpr int kMaxGrid = 16384;
 constexpr int kMaxGraphs = 4096;
 // The finishing kernel runs as one block of kFinBlock lanes.
 constexpr int kFinBlock = 1024;
+// Mixed precision, L1 norm: the float32 phase also hands over to float64 once the L1 change is
+// below 2^-17, i.e. 128 float32 ulps of sum(r) = 1.  Closer to its rounding floor the float32
+// iterate settles into a bias along the directions the update contracts only by alpha, and the
+// float64 phase then needs many extra updates to remove it (R-MAT scale 22, alpha 0.85,
+// tau 1e-10: 46 float32 + 27 float64 updates when waiting for tau, against 29 in float64 alone;
+// handing over near 1e-5 needs no more updates than float64 alone).
+constexpr double kL1Handover = 0x1p-17;
 
 // ---------------------------------------------------------------- prep layout
 // Tile descriptor: x = first row, y = first CSR entry, z = segment index (long row) or -1 (tile

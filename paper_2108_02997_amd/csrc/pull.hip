@@ -43,10 +43,11 @@ __device__ __forceinline__ void finalize(const IterParams &p, double l1, double 
   st->c0 = (1.0 - p.alpha) / N + (p.alpha * dang) / N;
   const bool met = (p.norm == 1 ? e[0] : p.norm == 2 ? e[1] : e[2]) < p.tau;
   if (p.phase == 1) {
-    // float32 phase: hand over to float64 once tau is met or the L1 change stops shrinking
-    // (in exact arithmetic the L1 change never grows: the update is an alpha-contraction in L1)
+    // float32 phase: hand over to float64 once tau is met, the L1 change stops shrinking (in
+    // exact arithmetic it never grows: the update is an alpha-contraction in L1) or, for the L1
+    // norm, the change is below kL1Handover
     if (met) st->met32 = 1;
-    if (met || !(l1 < st->prev_l1)) st->head.stop = 1;
+    if (met || !(l1 < st->prev_l1) || (p.norm == 1 && l1 < kL1Handover)) st->head.stop = 1;
     st->prev_l1 = l1;
     if (it >= p.max_iter) {
       st->head.stop = 1;

@@ -4,8 +4,8 @@ A per-vertex perceptron (5 -> 32 -> 32 -> 1, ReLU, float32 weights, bfloat16 act
 on ranks the solver itself produces proposes the start vector of a solve at a new alpha from the
 alpha = 0.85 ranks.  The power iteration then corrects it; a judge runs the candidate starts
 (network, alpha = 0.85 ranks, uniform) as columns of one batched update and keeps the one with
-the smallest first-update L1 change, so the uniform start of the paper's method remains the
-fallback.  Every numerical step runs in libprpull.so (pr_features, pr_mlp_forward,
+the smallest first-update change in the norm the solve stops on, so the uniform start of the
+paper's method remains the fallback.  Every numerical step runs in libprpull.so (pr_features, pr_mlp_forward,
 pr_mlp_backward, pr_adam_step, pr_warm_start_vector, pr_pull_batch); this module only sequences
 the calls and owns the tensors.
 """

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from test_gpu_pull import iterations_ok  # noqa: E402
+from test_gpu_pull import TRACE_ATOL, iterations_ok  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +59,7 @@ def test_alpha_sweep_fp64(pr, ctx, make):
     for r, p in zip(res, probs):
         ref = check_column(r, g, p)
         if r["iterations"] == ref["iterations"]:
-            atol = 2.0 ** -50 * (g.N + 16)
+            atol = TRACE_ATOL
             np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)
 
 
@@ -195,5 +195,5 @@ def test_compaction_with_traces_and_max_iter(pr, ctx):
     for r, p in zip(res, probs):
         ref = check_column(r, g, p)
         if r["iterations"] == ref["iterations"]:
-            atol = 2.0 ** -50 * (g.N + 16)
+            atol = TRACE_ATOL
             np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)

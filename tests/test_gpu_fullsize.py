@@ -1,0 +1,208 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+* R-MAT scale 22 (4,194,304 vertices, ~65 M edges), alpha = 0.85: the float64 solve to
+  tau = 1e-10 with its norm trace against the oracle's full trace; the tau x norm readout of
+  section 3 taken from both traces; mixed precision per norm against the oracle.
+* R-MAT scale 24 (16,777,216 vertices, ~263 M edges): the eleven-column damping sweep,
+  tau = 1e-10 in L-infinity, float32 gather with float64 norms and refinement (the benchmark's
+  step).  Every column: one oracle update applied to the returned ranks stays within the bound
+  that the reported last change implies, vertex by vertex.  alpha = 0.85, 0.95 and 1.00 are also
+  solved in full by the oracle and compared.
+* The uneven batch of 64 graphs (vertex counts log-uniform in [1e3, 1e6]) in one persistent
+  launch, every graph against its own oracle solve.
+
+Per-vertex bound (section 2 map G, last change e = ||r_k - r_{k-1}||_inf):
+  |G(r_k)_v - r_k_v| = |G(r_k)_v - G(r_{k-1})_v| + rounding
+                     <= alpha * e * (sum over in-edges u->v of 1/d_u + n_dangling / N) + rounding,
+because c0 moves by alpha/N times the change of the dangling sum and every gathered term by
+alpha * |delta r_u| / d_u.  Rounding: both sides sum (in-degree + a few) float64 terms of one sign,
+so (indeg_v + 8) * 2^-51 * (r_v + G_v) covers it.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_batch import check_column, mixed_bound  # noqa: E402
+from test_gpu_pull import TRACE_ATOL, iterations_ok  # noqa: E402
+
+TAUS = [10.0 ** -k for k in range(3, 11)]
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2108_02997_amd as pr
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return pr
+
+
+@pytest.fixture(scope="module")
+def ctx(pr):
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def in_weight(g):
+    """w_v = sum over in-edges u->v of 1/d_u."""
+    inv = np.zeros(g.N)
+    nz = g.outdeg > 0
+    inv[nz] = 1.0 / g.outdeg[nz]
+    dst = np.repeat(np.arange(g.N, dtype=np.int64), np.diff(g.off.astype(np.int64)))
+    return np.bincount(dst, weights=inv[g.idx], minlength=g.N)
+
+
+def check_fixed_point_step(g, w, n_dang, r, alpha, e_inf):
+    """One oracle update from r against the per-vertex bound of the module docstring."""
+    step = oracle.pagerank_graph(g, alpha=alpha, tau=0.0, norm=oracle.L1, max_iter=1, init=r)["ranks"]
+    indeg = np.diff(g.off.astype(np.int64))
+    bound = alpha * e_inf * (w + n_dang / g.N) + (indeg + 8) * 2.0 ** -51 * (np.abs(r) + np.abs(step))
+    gap = np.abs(step - r)
+    worst = int(np.argmax(gap / bound))
+    assert np.all(gap <= bound), (alpha, worst, gap[worst], bound[worst])
+    return float(gap.max())
+
+
+# ------------------------------------------------------------------ scale 22: traces and readout
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return gg.rmat(22, edge_factor=16, seed=22)
+
+
+def test_scale22_fp64_trace_and_readout(pr, ctx, rmat22):
+    g = rmat22
+    dg = pr.DeviceGraph.from_host(g)
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1, max_iter=500, trace=True)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-10, norm=1, max_iter=500, trace=True)
+    assert iterations_ok(res["iterations"], ref, 1e-10, 1), (res["iterations"], ref["iterations"])
+    tr = res["trace"].cpu().numpy()
+    k = min(len(tr), len(ref["trace"]))
+    np.testing.assert_allclose(tr[:k], ref["trace"][:k], rtol=1e-9, atol=TRACE_ATOL)
+    d1 = np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum()
+    print("scale-22 fp64: iterations %d / oracle %d, ranks L1 %.3e, largest trace difference %.3e"
+          % (res["iterations"], ref["iterations"], d1, np.abs(tr[:k] - ref["trace"][:k]).max()))
+    if res["iterations"] == ref["iterations"]:
+        assert d1 <= 1e-12
+    # every (tau, norm) stop read off the two traces; a stop decided by a near-tie may move by one
+    readout = {}
+    for norm in (1, 2, 3):
+        for tau in TAUS:
+            a = oracle.iterations_from_trace(tr, tau, norm)
+            b = oracle.iterations_from_trace(ref["trace"], tau, norm)
+            readout[(tau, norm)] = b
+            if a != b:
+                col = ref["trace"][:, norm - 1]
+                assert a is not None and b is not None and abs(a - b) == 1, (tau, norm, a, b)
+                assert min(abs(col[min(a, b) - 1] - tau), abs(col[max(a, b) - 1] - tau)) <= 1e-4 * tau
+    # iterations fall as the norm goes from L1 to L2 to L-infinity at every tau (section 3)
+    for tau in TAUS:
+        assert readout[(tau, 1)] >= readout[(tau, 2)] >= readout[(tau, 3)], tau
+    print("scale-22 readout (tau: L1/L2/Linf):",
+          {t: tuple(readout[(t, n)] for n in (1, 2, 3)) for t in TAUS})
+
+
+@pytest.mark.parametrize("norm", [1, 2, 3])
+def test_scale22_mixed_against_oracle(pr, ctx, rmat22, norm):
+    g = rmat22
+    dg = pr.DeviceGraph.from_host(g)
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=norm, precision=pr.PR_MIXED)
+    ref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-10, norm=norm)
+    assert res["converged"] and res["fp64_iters"] >= 1
+    assert res["err"][norm - 1] < 1e-10
+    r = res["ranks"].cpu().numpy()
+    d1 = np.abs(r - ref["ranks"]).sum()
+    dinf = np.abs(r - ref["ranks"]).max()
+    assert d1 <= mixed_bound(0.85, res["err"][0], ref["err"][0]), d1
+    # the mixed form may not cost more than a few updates over float64 alone
+    assert res["iterations"] <= ref["iterations"] + 3, (res["iterations"], ref["iterations"])
+    print("scale-22 mixed norm %d: iterations %d (fp32 %d + fp64 %d) vs fp64 oracle %d; L1 %.3e Linf %.3e"
+          % (norm, res["iterations"], res["fp32_iters"], res["fp64_iters"], ref["iterations"], d1, dinf))
+
+
+# ------------------------------------------------------------------ scale 24: the timed sweep
+
+@pytest.fixture(scope="module")
+def rmat24():
+    g = gg.rmat(24, edge_factor=16, seed=24)
+    return g, in_weight(g), int((g.outdeg == 0).sum())
+
+
+@pytest.fixture(scope="module")
+def dev24(pr, ctx, rmat24):
+    dg = pr.DeviceGraph.from_host(rmat24[0])
+    dg.prepare(ctx)
+    yield dg
+    del dg
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def sweep24(pr, ctx, dev24):
+    """The benchmark's step: eleven columns, mixed precision, default launch settings."""
+    probs = [dict(alpha=a, tau=1e-10, norm=3, max_iter=500) for a in gg.ALPHA_SWEEP]
+    res = pr.pull_batch(ctx, dev24, probs, precision=pr.PR_MIXED)
+    for r in res:
+        r["ranks"] = r["ranks"].cpu().numpy()
+    return probs, res
+
+
+def test_scale24_sweep_as_benchmarked(rmat24, sweep24):
+    g, w, n_dang = rmat24
+    probs, res = sweep24
+    report = []
+    for r, p in zip(res, probs):
+        a = p["alpha"]
+        assert r["converged"] and r["fp64_iters"] >= 1 and r["err"][2] < 1e-10, (p, r["iterations"])
+        # mass: the map sends sum(r) - 1 to alpha * (sum(r) - 1), so after a last change e1 in L1
+        # the excess is at most alpha/(1-alpha) * e1; at alpha = 1 the map keeps whatever the
+        # float32 phase left, a drift of float32 rounding (bounded here by 2^-16)
+        m = abs(r["ranks"].sum() - 1.0)
+        assert m <= (a / (1 - a) * r["err"][0] + 1e-12 if a < 1 else 2.0 ** -16), (a, m)
+        gap = check_fixed_point_step(g, w, n_dang, r["ranks"], a, r["err"][2])
+        report.append((a, r["iterations"], r["fp32_iters"], r["fp64_iters"], "%.2e" % m, "%.2e" % gap))
+    print("scale-24 sweep (alpha, iterations, fp32, fp64, |sum-1|, max |G(r)-r|):", report)
+
+
+@pytest.mark.parametrize("alpha", [0.85, 0.95, 1.0])
+def test_scale24_columns_against_full_oracle(pr, ctx, rmat24, dev24, sweep24, alpha):
+    g = rmat24[0]
+    p = dict(alpha=alpha, tau=1e-10, norm=3, max_iter=500)
+    ref = oracle.pagerank_graph(g, trace=True, **p)
+    # the sequential float64 solve of the benchmark's baseline
+    f64 = pr.pull(ctx, dev24, precision=pr.PR_FP64, **p)
+    assert iterations_ok(f64["iterations"], ref, 1e-10, 3), (f64["iterations"], ref["iterations"])
+    if f64["iterations"] == ref["iterations"]:
+        assert np.abs(f64["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+    # the same column of the eleven-column mixed batch
+    col = sweep24[1][list(gg.ALPHA_SWEEP).index(alpha)]
+    r = col["ranks"]
+    d1 = np.abs(r - ref["ranks"]).sum()
+    dinf = np.abs(r - ref["ranks"]).max()
+    if alpha < 1.0:
+        assert d1 <= mixed_bound(alpha, col["err"][0], ref["err"][0]), d1
+    else:
+        # no contraction bound at alpha = 1: both stopped on an L-infinity change below 1e-10,
+        # and the oracle's trace falls geometrically; allow ten times tau per vertex
+        assert dinf <= 10 * 1e-10, dinf
+    print("scale-24 alpha %.2f: mixed batch %d (fp32 %d + fp64 %d), fp64 %d, oracle %d; mixed vs oracle L1 %.3e "
+          "Linf %.3e" % (alpha, col["iterations"], col["fp32_iters"], col["fp64_iters"], f64["iterations"],
+                          ref["iterations"], d1, dinf))
+
+
+# ------------------------------------------------------------------ 64 uneven graphs, full recipe
+
+def test_uneven_batch_full_recipe(pr, ctx):
+    specs = gg.many_graph_specs()
+    hosts = [gg.make_spec_graph(s) for s in specs]
+    graphs = [pr.DeviceGraph.from_host(h) for h in hosts]
+    probs = [dict(alpha=s["alpha"], tau=s["tau"], norm=s["norm"], max_iter=500) for s in specs]
+    res = pr.pull_multi(ctx, graphs, probs)
+    for r, h, p in zip(res, hosts, probs):
+        check_column(r, h, p)
+    print("64 graphs: sum E = %d, iterations %s" % (sum(h.E for h in hosts), [r["iterations"] for r in res]))

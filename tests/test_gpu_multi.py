@@ -10,6 +10,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from test_gpu_batch import check_column  # noqa: E402
+from test_gpu_pull import TRACE_ATOL  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +44,7 @@ def test_uneven_batch_each_graph_matches_oracle(pr, ctx):
     for r, h, p in zip(res, hosts, probs):
         ref = check_column(r, h, p)
         if r["iterations"] == ref["iterations"]:
-            np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=2.0 ** -50 * (h.N + 16))
+            np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=TRACE_ATOL)
 
 
 def test_multi_edge_cases(pr, ctx):

@@ -52,6 +52,18 @@ def test_edgeless_graph_all_dangling(alpha):
     np.testing.assert_allclose(res["ranks"], 1.0 / 37, rtol=1e-14)
 
 
+def test_large_dangling_sum_is_exact_to_rounding():
+    # A million equal dangling ranks: uniform 1/N is the exact fixed point, so one update must
+    # return it to within a few ulps and the three errors must vanish to rounding.  A plain
+    # running sum of the equal terms drifts by about 2e-11 relative here, which
+    # would move every rank by that much and the L1 change to ~1.5e-11.
+    N = 1_000_003
+    g = gg.edgeless(N)
+    res = run(g, alpha=0.85, tau=0.0, norm=L1, max_iter=2)
+    assert np.max(np.abs(res["ranks"] * N - 1.0)) <= 8 * 2.0 ** -52
+    assert res["err"][0] <= 1e-15 and res["err"][2] <= 8 * 2.0 ** -52 / N
+
+
 def in_star_closed_form(L, alpha, k):
     """In-star (leaves -> hub, hub dangling), uniform start: leaves l_k and the three errors at step k."""
     N = L + 1
