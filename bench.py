@@ -1,22 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the pull-PageRank path on one MI355X.
 
-Workload (one "step"): the damping-factor sweep of the paper's section 2 -- eleven rank
-vectors for alpha = 0.50, 0.55, ..., 1.00 -- on a seeded R-MAT graph of scale 24 (16,777,216
-vertices, edge factor 16, a,b,c,d = .57,.19,.19,.05, seed 24, duplicates and self-loops removed),
-each solved to tau = 1e-10 in the L-infinity norm (section 3) from the uniform start, max 500
-iterations, all eleven together in one batched solve (pr_pull_batch; float32 gather with
-float64 norms, teleport terms and final float64 updates).  The graph is synthetic: the paper's
-SuiteSparse graphs are not available.
+Default workload (--workload sweep; one "step"): the damping-factor sweep of the paper's
+section 2 -- eleven rank vectors for alpha = 0.50, 0.55, ..., 1.00 -- on a seeded R-MAT graph of
+scale 24 (16,777,216 vertices, edge factor 16, a,b,c,d = .57,.19,.19,.05, seed 24, duplicates
+and self-loops removed), each solved to tau = 1e-10 in the L-infinity norm (section 3) from the
+uniform start, max 500 iterations, all eleven together in one batched solve (pr_pull_batch;
+float32 gather with float64 norms, teleport terms and final float64 updates).  The graph is
+synthetic: the paper's SuiteSparse graphs are not available.
 
 Reported:
-  value          column-edge updates per second of the timed sweep (sum over the eleven columns
-                 of E * iterations, divided by the step time), in GTEPS
-  sweep          per-column iterations, the same sweep as eleven sequential float64 solves
-                 (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
-  roofline       the dominant kernel's algorithmic bytes per launch over its average launch
-                 duration, timed with HIP events on the solve stream inside the timed steps
-  cpu_baseline   the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
+  value            column-edge updates per second of the timed sweep (sum over the eleven columns
+                   of E * iterations, divided by the step time), in GTEPS
+  sweep            per-column iterations, the same sweep as eleven sequential float64 solves
+                   (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
+  roofline         the dominant kernel's algorithmic bytes per launch over its average launch
+                   duration, timed with HIP events on the solve stream inside the timed steps
+  plain_fp64_gather  the same for the single-vector float64 update of the sequential solves
+  cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
+
+Other workloads (one JSON line each, same keys):
+  --workload tau        R-MAT scale 22: every (tau, norm) stop for tau = 1e-3 .. 1e-10 and the
+                        three norms, float64 against mixed precision (iterations, time, distance)
+  --workload multi      64 seeded graphs of uneven size (log-uniform 1e3 .. 1e6 vertices) with
+                        their own alpha/tau/norm, autotuned, in one persistent launch, against
+                        the sum of 64 sequential solves
+  --workload warmstart  the learned warm start: a network trained on 20 R-MAT scale-20 graphs
+                        proposes start vectors for alpha = 0.90/0.95/0.99 on an unseen scale-24
+                        graph; iterations and time from the uniform, alpha=0.85 and learned starts
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -34,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "α-sweep time to τ=1e-10 vs plain FP64; GTEPS; HBM GB/s as % of peak"
 HBM_PEAK_GBS = 8000.0
+CSRC = "paper_2108_02997_amd/csrc/"
 
 
 def log(*a):
@@ -80,38 +92,65 @@ def cpu_model():
     return "unknown"
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=24)
-    ap.add_argument("--seed", type=int, default=24)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--path", choices=["batch_mixed", "batch_fp64"], default="batch_mixed",
-                    help="the timed sweep: batched mixed precision (default) or batched float64")
-    ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 sweep")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def timed(fn, reps, tag):
     import torch
+    ts, out = [], None
+    for i in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        log("%s %d: %.2f ms" % (tag, i + 1, ts[-1] * 1e3))
+    return ts, out
 
-    import graphgen as gg
-    import paper_2108_02997_amd as pr
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a ROCm GPU", file=sys.stderr)
-        sys.exit(1)
+def single_update_bytes(N, E, s):
+    """Algorithmic bytes of one single-vector update: indices, offsets, out-degrees, read and
+    write of the s-byte state."""
+    return 4 * E + 4 * (N + 1) + 4 * N + 2 * s * N
 
-    log("generating R-MAT scale %d seed %d" % (args.scale, args.seed))
-    g = gg.rmat(args.scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=args.seed)
+
+def roofline(kernel, alg_bytes, avg_s, launches, traffic):
+    achieved = alg_bytes / avg_s / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(alg_bytes), "avg_launch_us": round(avg_s * 1e6, 2),
+            "launches_timed": launches}
+
+
+def cpu_baseline(graphs, seconds, what):
+    """The oracle (FP64, OpenMP gather) timed on a bounded number of updates over `graphs`."""
+    import oracle
+    log("cpu oracle sample")
+    t = time.perf_counter()
+    for g in graphs:
+        oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=1)
+    t1 = time.perf_counter() - t
+    k = int(max(1, min(40, round(seconds / max(t1, 1e-3)))))
+    t = time.perf_counter()
+    for g in graphs:
+        oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=k)
+    tk = time.perf_counter() - t
+    edges = sum(g.E for g in graphs) * k
+    log("cpu oracle: %d iterations in %.2f s" % (k, tk))
+    return {"value": round(edges / tk / 1e9, 4), "unit": "GTEPS", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d FP64 oracle iterations (alpha=0.85) over %s, %.1f s; host CPU %s" % (k, what, tk, cpu_model())}
+
+
+def base_line(metric, value, unit, args, ms, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": config}
+
+
+# ------------------------------------------------------------------ the damping-factor sweep
+
+def run_sweep(args, pr, gg, np, torch):
+    scale = args.scale or 24
+    seed = args.seed if args.seed is not None else 24
+    log("generating R-MAT scale %d seed %d" % (scale, seed))
+    g = gg.rmat(scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=seed)
     N, E = g.N, g.E
     log("graph N=%d E=%d dangling=%d" % (N, E, int((g.outdeg == 0).sum())))
     ctx = pr.Context(0)
@@ -153,19 +192,13 @@ def main():
         log("device copy 1 GiB: %.0f GB/s (read+write)" % copy_gbs)
         del src, dst
 
-    def timed(fn, reps, tag):
-        ts, out = [], None
-        for i in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-            log("%s %d: %.2f ms" % (tag, i + 1, ts[-1] * 1e3))
-        return ts, out
-
-    # the plain FP64 reference: 11 sequential solves (untimed warm-up, then timed)
+    # the plain FP64 reference: 11 sequential solves.  The first (untimed) pass runs with per-launch
+    # event timing to measure the single-vector float64 update; the timed passes replay graphs.
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
     sweep_sequential()
+    ctx.set_option("timing", 0)
+    n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
     seq_times, seq_res = timed(sweep_sequential, args.seq_reps, "sequential fp64 sweep")
     seq_s = float(np.mean(seq_times))
 
@@ -181,24 +214,27 @@ def main():
     col_edges = sum(E * k for k in iters)
     gteps = col_edges / step_s / 1e9
 
-    # dominant kernel: the batched update of the first phase (float32 for the mixed path).
+    # dominant kernel: the batched update of the first phase (float32 for the mixed path) on the
+    # widest rows, i.e. the launches before the first compaction of the active columns.
     # Algorithmic bytes of one launch with K_a active columns: 4E (indices) + 4(N+1) (offsets)
     # + 4N (out-degrees) + 2*s*K_a*N (read and write of the active columns, s bytes each).
-    dom_kind = pr._lib.PR_KERNEL_BATCH_F32 if batch_prec == pr.PR_MIXED else pr._lib.PR_KERNEL_BATCH_F64
-    s_bytes = 4 if batch_prec == pr.PR_MIXED else 8
-    phase1 = [r["fp32_iters"] for r in results] if batch_prec == pr.PR_MIXED else iters
+    fp32 = batch_prec == pr.PR_MIXED
+    s_bytes = 4 if fp32 else 8
+    C0 = 4 if fp32 and K > 8 else (K + 3) // 4
+    dom_kind = (pr._lib.PR_KERNEL_BATCH_F32_C1 if fp32 else pr._lib.PR_KERNEL_BATCH_F64_C1) + C0 - 1
+    phase1 = [r["fp32_iters"] for r in results] if fp32 else iters
     n_dom, ms_dom = ctx.stats(dom_kind)
-    launches = max(phase1)
-    alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(launches)]
+    per_step = max(1, round(n_dom / args.steps))
+    alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(per_step)]
     alg_per_launch = float(np.mean(alg))
     avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
-    achieved = alg_per_launch / avg_launch_s / 1e9
     n_f64, ms_f64 = ctx.stats(pr._lib.PR_KERNEL_BATCH_F64)
-    kname = "k_batch_update<float,%d>" % (4 if K > 8 else (K + 3) // 4) if batch_prec == pr.PR_MIXED else \
-        "k_batch_update<double,%d>" % ((K + 3) // 4)
-    digest = source_digest(["paper_2108_02997_amd/csrc/batch.hip", "paper_2108_02997_amd/csrc/batch.h",
-                            "paper_2108_02997_amd/csrc/internal.h"])
-    traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if s_bytes == 4 else "f64", args.scale), digest)
+    n_all, ms_all = ctx.stats(pr._lib.PR_KERNEL_BATCH_F32 if fp32 else pr._lib.PR_KERNEL_BATCH_F64)
+    kname = "k_batch_update<%s,%d>" % ("float" if fp32 else "double", C0)
+    digest = source_digest([CSRC + "batch.hip", CSRC + "batch.h", CSRC + "internal.h"])
+    traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if s_bytes == 4 else "f64", scale), digest)
+    d64 = source_digest([CSRC + "pull.hip", CSRC + "device.h", CSRC + "internal.h"])
+    traffic64 = read_traffic("update_f64_rmat_s%d" % scale, d64)
 
     # section 2 report: L1 distance of every column to the alpha = 0.85 column; and the batched
     # result against the sequential FP64 solves
@@ -207,69 +243,268 @@ def main():
     l1_vs_fp64 = [pr.l1_distance(ctx, rb, rs) for rb, rs in zip(ranks_b, ranks_s)]
     linf_vs_fp64 = [float((rb - rs).abs().max()) for rb, rs in zip(ranks_b, ranks_s)]
 
-    line = {
-        "metric": METRIC,
-        "value": round(gteps, 3),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(step_s * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if batch_prec == pr.PR_MIXED else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "alpha sweep: 11 rank columns alpha=0.50..1.00 solved together to tau=1e-10 (Linf) on R-MAT "
-                        "scale %d, edge factor 16, (.57,.19,.19,.05), seed %d; %s" % (
-                            args.scale, args.seed, "float32 gather + float64 norms/c0/refinement"
-                            if batch_prec == pr.PR_MIXED else "float64"),
-            "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path,
-        },
-        "roofline": {
-            "kernel": kname,
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": round(alg_per_launch),
-            "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "launches_timed": n_dom,
-        },
-        "sweep": {
-            "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],
-            "fp64_iters": [r["fp64_iters"] for r in results], "converged": [r["converged"] for r in results],
-            "column_edges": col_edges, "prep_ms": round(prep_ms, 2),
-            "sequential_fp64_ms": round(seq_s * 1e3, 3),
-            "sequential_fp64_iterations": [r["iterations"] for r in seq_res],
-            "speedup_vs_sequential_fp64": round(seq_s / step_s, 3),
-            "l1_vs_alpha_085": [round(x, 6) for x in l1_vs_085],
-            "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
-            "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
-        },
+    line = base_line(METRIC, round(gteps, 3), "GTEPS", args, step_s * 1e3,
+                     "f32+f64" if batch_prec == pr.PR_MIXED else "f64", {
+                         "workload": "alpha sweep: 11 rank columns alpha=0.50..1.00 solved together to tau=1e-10 "
+                                     "(Linf) on R-MAT scale %d, edge factor 16, (.57,.19,.19,.05), seed %d; %s" % (
+                                         scale, seed, "float32 gather + float64 norms/c0/refinement"
+                                         if batch_prec == pr.PR_MIXED else "float64"),
+                         "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path})
+    line["roofline"] = roofline(kname, alg_per_launch, avg_launch_s, n_dom, traffic)
+    if n64:
+        b64 = single_update_bytes(N, E, 8)
+        line["plain_fp64_gather"] = roofline("k_update<double>", b64, ms64 / n64 * 1e-3, n64, traffic64)
+        line["plain_fp64_gather"]["gteps_per_update"] = round(E / (ms64 / n64 * 1e-3) / 1e9, 2)
+    line["sweep"] = {
+        "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],
+        "fp64_iters": [r["fp64_iters"] for r in results], "converged": [r["converged"] for r in results],
+        "column_edges": col_edges, "prep_ms": round(prep_ms, 2),
+        "sequential_fp64_ms": round(seq_s * 1e3, 3),
+        "sequential_fp64_iterations": [r["iterations"] for r in seq_res],
+        "speedup_vs_sequential_fp64": round(seq_s / step_s, 3),
+        "l1_vs_alpha_085": [round(x, 6) for x in l1_vs_085],
+        "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
+        "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
+        "first_phase_updates_per_step": round(n_all / args.steps, 2) if n_all else None,
+        "first_phase_update_us_all_widths": round(1e3 * ms_all / n_all, 2) if n_all else None,
     }
-
     if not args.no_cpu:
-        import oracle
-        log("cpu oracle sample")
-        t = time.perf_counter()
-        oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=1)
-        t1 = time.perf_counter() - t
-        k = int(max(1, min(40, round(args.cpu_seconds / max(t1, 1e-3)))))
-        t = time.perf_counter()
-        oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=k)
-        tk = time.perf_counter() - t
-        line["cpu_baseline"] = {
-            "value": round(E * k / tk / 1e9, 4), "unit": "GTEPS", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "%d FP64 oracle iterations (alpha=0.85) over the full graph, %.1f s; host CPU %s"
-                      % (k, tk, cpu_model()),
-        }
-        log("cpu oracle: %d iterations in %.2f s" % (k, tk))
-    print(json.dumps(line), flush=True)
+        line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")
     ctx.close()
+    return line
+
+
+# ------------------------------------------------------------------ tau x norm readout
+
+def run_tau(args, pr, gg, np, torch):
+    scale = args.scale or 22
+    seed = args.seed if args.seed is not None else 22
+    log("generating R-MAT scale %d seed %d" % (scale, seed))
+    g = gg.rmat(scale, edge_factor=16, seed=seed)
+    N, E = g.N, g.E
+    ctx = pr.Context(0)
+    dg = pr.DeviceGraph.from_host(g, 0)
+    dg.prepare(ctx)
+    rows = []
+    total = {pr.PR_FP64: 0.0, pr.PR_MIXED: 0.0}
+    for norm in (pr.PR_L1, pr.PR_L2, pr.PR_LINF):
+        for tau in gg.TAU_DECADES:
+            res = {}
+            for prec in (pr.PR_FP64, pr.PR_MIXED):
+                def solve():
+                    return pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, precision=prec)
+                solve()
+                ts, out = timed(solve, args.steps, "tau %.0e norm %d prec %d" % (tau, norm, prec))
+                res[prec] = (float(np.mean(ts)), out)
+                total[prec] += float(np.mean(ts))
+            f, m = res[pr.PR_FP64][1], res[pr.PR_MIXED][1]
+            rows.append({"tau": tau, "norm": norm, "fp64_iterations": f["iterations"],
+                         "fp64_ms": round(res[pr.PR_FP64][0] * 1e3, 3),
+                         "mixed_iterations": [m["fp32_iters"], m["fp64_iters"]],
+                         "mixed_ms": round(res[pr.PR_MIXED][0] * 1e3, 3),
+                         "mixed_vs_fp64_l1": pr.l1_distance(ctx, m["ranks"], f["ranks"]),
+                         "mixed_vs_fp64_linf": float((m["ranks"] - f["ranks"]).abs().max())})
+    # the single-vector updates, timed per launch over one float64 and one mixed solve
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    ref = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=pr.PR_L1, precision=pr.PR_FP64)
+    pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=pr.PR_LINF, precision=pr.PR_MIXED)
+    ctx.set_option("timing", 0)
+    n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+    n32, ms32 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F32)
+    t_ref = [r for r in rows if r["tau"] == 1e-10 and r["norm"] == pr.PR_L1][0]["fp64_ms"] * 1e-3
+    line = base_line("tau x norm readout (section 3): iterations and time to each stop, float64 vs mixed; GTEPS "
+                     "of the float64 solve to tau=1e-10 (L1)", round(E * ref["iterations"] / t_ref / 1e9, 3),
+                     "GTEPS", args, t_ref * 1e3, "f64 | f32+f64",
+                     {"workload": "R-MAT scale %d, edge factor 16, (.57,.19,.19,.05), seed %d, alpha=0.85, "
+                                  "tau=1e-3..1e-10 x {L1,L2,Linf}, max_iter 500" % (scale, seed), "N": N, "E": E})
+    line["roofline"] = roofline("k_update<double>", single_update_bytes(N, E, 8), ms64 / n64 * 1e-3, n64, None)
+    line["fp32_update"] = roofline("k_update<float>", single_update_bytes(N, E, 4), ms32 / n32 * 1e-3, n32, None)
+    line["readout"] = rows
+    line["sum_ms"] = {"fp64": round(total[pr.PR_FP64] * 1e3, 2), "mixed": round(total[pr.PR_MIXED] * 1e3, 2)}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")
+    ctx.close()
+    return line
+
+
+# ------------------------------------------------------------------ many graphs, one launch
+
+def run_multi(args, pr, gg, np, torch):
+    specs = gg.many_graph_specs()
+    log("generating %d graphs" % len(specs))
+    hosts = [gg.make_spec_graph(s) for s in specs]
+    ctx = pr.Context(0)
+    graphs = [pr.DeviceGraph.from_host(h, 0) for h in hosts]
+    probs = [dict(alpha=s["alpha"], tau=s["tau"], norm=s["norm"], max_iter=500) for s in specs]
+    t = time.time()
+    for dg in graphs:
+        dg.prepare(ctx)
+    torch.cuda.synchronize()
+    prep_ms = (time.time() - t) * 1e3
+    t = time.time()
+    tuned = [dg.autotune(ctx) for dg in graphs]
+    tune_s = time.time() - t
+    log("autotuned %d graphs in %.1f s" % (len(graphs), tune_s))
+    ws = torch.empty(ctx.lib.pr_multi_workspace_bytes(len(graphs), pr.multi_problems(ctx, graphs, probs)[0]),
+                     dtype=torch.uint8, device="cuda")
+
+    def one_launch():
+        return pr.pull_multi(ctx, graphs, probs, workspace=ws)
+
+    def sequential():
+        return [pr.pull(ctx, dg, **p) for dg, p in zip(graphs, probs)]
+
+    sequential()
+    seq_ts, seq_res = timed(sequential, max(1, args.seq_reps), "64 sequential solves")
+    for i in range(args.warmup):
+        one_launch()
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    ts, res = timed(one_launch, args.steps, "one persistent launch")
+    ctx.set_option("timing", 0)
+    nk, msk = ctx.stats(pr._lib.PR_KERNEL_MULTI)
+    step_s = float(np.mean(ts))
+    edges = sum(h.E * r["iterations"] for h, r in zip(hosts, res))
+    alg = sum(single_update_bytes(h.N, h.E, 8) * r["iterations"] for h, r in zip(hosts, res))
+    line = base_line("uneven batch of 64 graphs: aggregate GTEPS of one persistent launch vs 64 sequential solves",
+                     round(edges / step_s / 1e9, 3), "GTEPS", args, step_s * 1e3, "f64",
+                     {"workload": "64 seeded graphs (seed 1000): N log-uniform in [1e3,1e6], even R-MAT / odd "
+                                  "Erdos-Renyi, degree {4,8,16,32}, alpha {.75,.85,.95}, tau {1e-6,1e-8,1e-10}, "
+                                  "norm {L1,L2,Linf}; autotuned", "graphs": len(hosts),
+                      "sum_N": sum(h.N for h in hosts), "sum_E": sum(h.E for h in hosts)})
+    line["roofline"] = roofline("k_multi (whole solve)", alg, msk / nk * 1e-3, nk, None)
+    line["multi"] = {"sequential_ms": round(float(np.mean(seq_ts)) * 1e3, 3),
+                     "speedup_vs_sequential": round(float(np.mean(seq_ts)) / step_s, 3),
+                     "iterations": [r["iterations"] for r in res],
+                     "same_iterations_as_sequential": sum(int(a["iterations"] == b["iterations"])
+                                                          for a, b in zip(res, seq_res)),
+                     "max_l1_vs_sequential": max(pr.l1_distance(ctx, a["ranks"], b["ranks"])
+                                                 for a, b in zip(res, seq_res)),
+                     "prep_ms": round(prep_ms, 2), "autotune_s": round(tune_s, 2),
+                     "tuned_mid_deg": [t["mid_deg"] for t in tuned], "tuned_grid": [t["grid"] for t in tuned]}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(hosts, args.cpu_seconds, "all 64 graphs")
+    ctx.close()
+    return line
+
+
+# ------------------------------------------------------------------ learned warm start
+
+def run_warmstart(args, pr, gg, np, torch):
+    from paper_2108_02997_amd import warmstart as wsm
+    ctx = pr.Context(0)
+    model = wsm.WarmStart(ctx, seed=0)
+    train_alphas = [0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95, 0.99]
+    samples = []
+    t = time.time()
+    for s in range(20):
+        h = gg.rmat(20, edge_factor=16, seed=2000 + s)
+        dg = pr.DeviceGraph.from_host(h, 0)
+        samples += model.make_samples(dg, train_alphas)
+        del dg
+    label_s = time.time() - t
+    log("labelled %d samples in %.1f s" % (len(samples), label_s))
+    torch.cuda.synchronize()
+    t = time.time()
+    hist = model.train(samples, epochs=args.epochs, lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.time() - t
+    log("trained %d epochs in %.1f s, loss %.4f -> %.4f" % (args.epochs, train_s, hist[0], hist[-1]))
+    del samples
+    torch.cuda.empty_cache()
+
+    scale = args.scale or 24
+    seed = args.seed if args.seed is not None else 3000
+    g = gg.rmat(scale, edge_factor=16, seed=seed)
+    dg = pr.DeviceGraph.from_host(g, 0)
+    dg.prepare(ctx)
+    tau, norm = 1e-10, pr.PR_LINF
+    r85 = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm)
+    rows = []
+    for alpha in (0.90, 0.95, 0.99):
+        def uni():
+            return pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm)
+
+        def from85():
+            return pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, init=r85["ranks"])
+
+        def frommlp():
+            r0 = model.propose(dg, r85["ranks"], alpha)
+            return pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, init=r0)
+
+        def judged():
+            r0, name, _, steps, _ = model.start(dg, r85["ranks"], alpha, norm=norm)
+            out = pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, init=r0)
+            out["iterations_total"] = steps + out["iterations"]
+            out["choice"] = name
+            return out
+
+        row = {"alpha": alpha}
+        ref = None
+        for tag, fn in (("uniform", uni), ("r085", from85), ("mlp", frommlp), ("judged", judged)):
+            fn()
+            ts, out = timed(fn, args.steps, "alpha %.2f %s" % (alpha, tag))
+            row[tag + "_ms"] = round(float(np.mean(ts)) * 1e3, 3)
+            row[tag + "_iterations"] = out.get("iterations_total", out["iterations"])
+            if tag == "uniform":
+                ref = out["ranks"]
+            else:
+                row[tag + "_linf_vs_uniform"] = float((out["ranks"] - ref).abs().max())
+            if tag == "judged":
+                row["judged_choice"] = out["choice"]
+        rows.append(row)
+    t_uni = sum(r["uniform_ms"] for r in rows)
+    t_mlp = sum(r["mlp_ms"] for r in rows)
+    line = base_line("learned warm start: time to tau=1e-10 (Linf) from the network's start (features and inference "
+                     "included) against the uniform start, summed over alpha = 0.90, 0.95, 0.99",
+                     round(t_uni / t_mlp, 3), "x", args, t_mlp, "f64 solve; f32 weights, bf16 activations",
+                     {"workload": "train: 20 R-MAT scale-20 graphs (seeds 2000-2019), alpha in {.50..,.95,.99}, "
+                                  "labels at tau=1e-12 (L1); evaluate: unseen R-MAT scale %d seed %d" % (scale, seed),
+                      "N": g.N, "E": g.E, "tau": tau, "norm": "Linf"})
+    line["warm_start"] = {"rows": rows, "train_s": round(train_s, 2), "label_s": round(label_s, 2),
+                          "epochs": args.epochs, "loss_first_last": [hist[0], hist[-1]],
+                          "r085_iterations": r85["iterations"]}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the evaluation graph")
+    ctx.close()
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["sweep", "tau", "multi", "warmstart"], default="sweep")
+    ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default: 24, or 22 for --workload tau)")
+    ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--path", choices=["batch_mixed", "batch_fp64"], default="batch_mixed",
+                    help="the timed sweep: batched mixed precision (default) or batched float64")
+    ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 baseline")
+    ap.add_argument("--epochs", type=int, default=20, help="training epochs of the warm-start network")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2108_02997_amd as pr
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    run = {"sweep": run_sweep, "tau": run_tau, "multi": run_multi, "warmstart": run_warmstart}[args.workload]
+    line = run(args, pr, gg, np, torch)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

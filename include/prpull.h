@@ -108,7 +108,11 @@ enum {
   PR_KERNEL_BATCH_F64 = 2,  /* one float64 update of pr_pull_batch (all active columns) */
   PR_KERNEL_BATCH_F32 = 3,  /* one float32 update of pr_pull_batch */
   PR_KERNEL_MULTI = 4,      /* one whole pr_pull_multi launch (all rounds of all graphs) */
-  PR_KERNEL_KINDS = 8
+  /* pr_pull_batch updates again, split by the row width the update ran on: C columns per lane,
+   * rows of 4*C values (C = 1..4, kind = ..._C1 + C - 1) */
+  PR_KERNEL_BATCH_F64_C1 = 8,
+  PR_KERNEL_BATCH_F32_C1 = 12,
+  PR_KERNEL_KINDS = 16
 };
 
 /* With "timing" on: number of timed launches of `kind` that did work (launches that found the

@@ -232,11 +232,8 @@ def pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int = PR_FP64,
     return out
 
 
-def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, workspace=None) -> list:
-    """Many graphs, each with its own problem, in one persistent launch (pr_pull_multi, float64).
-
-    graphs: DeviceGraph list (prepared here if needed); problems: dicts with alpha, tau, norm,
-    max_iter.  Returns one dict per graph (ranks, iterations, converged, err, trace)."""
+def multi_problems(ctx: Context, graphs, problems, inits=None, trace: bool = False):
+    """The pr_graph_problem array of a many-graph call, with fresh rank (and trace) tensors."""
     G = len(graphs)
     if G != len(problems) or G < 1:
         raise ValueError("one problem per graph is required")
@@ -254,6 +251,16 @@ def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, 
                                   int(p["max_iter"]), _lib.ptr(ini), r.data_ptr(), _lib.ptr(tr))
         ranks.append(r)
         traces.append(tr)
+    return arr, ranks, traces
+
+
+def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, workspace=None) -> list:
+    """Many graphs, each with its own problem, in one persistent launch (pr_pull_multi, float64).
+
+    graphs: DeviceGraph list (prepared here if needed); problems: dicts with alpha, tau, norm,
+    max_iter.  Returns one dict per graph (ranks, iterations, converged, err, trace)."""
+    G = len(graphs)
+    arr, ranks, traces = multi_problems(ctx, graphs, problems, inits, trace)
     nbytes = ctx.lib.pr_multi_workspace_bytes(G, arr)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=graphs[0].off.device)

@@ -48,8 +48,8 @@ hipError_t launch_l1(hipStream_t s, const double *x, const double *y, int64_t N,
 int mlp_param_count();
 int mlp_backward_blocks(int64_t N);
 hipError_t launch_features(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
-                           const int4 *hubs, int32_t nhubs, const double *r, double alpha_t, float *feat,
-                           const double *r_target, float *target);
+                           const int4 *desc, int32_t ndesc, const int4 *hubs, int32_t nhubs, const double *r,
+                           double alpha_t, float *feat, const double *r_target, float *target);
 hipError_t launch_mlp_forward(hipStream_t s, const float *W, const float *feat, int64_t N, float *y, uint16_t *act);
 hipError_t launch_mlp_backward(hipStream_t s, const float *W, const float *feat, const uint16_t *act, const float *y,
                                const float *target, int64_t N, float *part, double *loss_part, float *dW,
@@ -72,6 +72,7 @@ struct GraphEntry {
 // k-th.  `key` identifies the captured graph (kernel, parameters, buffers).
 struct ChunkSpec {
   int kind;
+  int sub_kind = -1;  // also counted under this kind (the batch kernels by columns per lane)
   int count;
   std::vector<unsigned char> key;
   std::function<hipError_t(hipStream_t, int)> launch;
@@ -331,6 +332,10 @@ int run_until_stop(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const LoopHea
         PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
         ctx->stat_ms[c.kind] += ms;
         ctx->stat_launches[c.kind] += 1;
+        if (c.sub_kind >= 0) {
+          ctx->stat_ms[c.sub_kind] += ms;
+          ctx->stat_launches[c.sub_kind] += 1;
+        }
       }
     }
     before = h->phase_iter;
@@ -405,6 +410,7 @@ BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t preci
 ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int C, unsigned grid, const BatchParams &p, void *b0, void *b1) {
   ChunkSpec c;
   c.kind = fp32 ? PR_KERNEL_BATCH_F32 : PR_KERNEL_BATCH_F64;
+  c.sub_kind = (fp32 ? PR_KERNEL_BATCH_F32_C1 : PR_KERNEL_BATCH_F64_C1) + C - 1;
   c.count = (int)ctx->chunk;
   BatchParams q = p;
   q.y_in = b0;
@@ -874,13 +880,15 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     PR_HIP(hipStreamSynchronize(s));
     return PR_OK;
   };
-  auto stat_chunk = [&](int kind, const std::vector<hipEvent_t> *ev, int did, int count) -> int {
+  auto stat_chunk = [&](const ChunkSpec &cs, const std::vector<hipEvent_t> *ev, int did) -> int {
     if (!ev || did <= 0) return PR_OK;
     float ms = 0.f;
-    for (int k = 0; k < did && k < count; ++k) {
+    for (int k = 0; k < did && k < cs.count; ++k) {
       PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
-      ctx->stat_ms[kind] += ms;
-      ctx->stat_launches[kind] += 1;
+      ctx->stat_ms[cs.kind] += ms;
+      ctx->stat_launches[cs.kind] += 1;
+      ctx->stat_ms[cs.sub_kind] += ms;
+      ctx->stat_launches[cs.sub_kind] += 1;
     }
     return PR_OK;
   };
@@ -911,7 +919,7 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
     PR_HIP(hipStreamSynchronize(s));
     BatchState &hs = *ctx->hbstate;
-    rc = stat_chunk(cs.kind, ev, hs.head.phase_iter - before, cs.count);
+    rc = stat_chunk(cs, ev, hs.head.phase_iter - before);
     if (rc != PR_OK) return rc;
     before = hs.head.phase_iter;
     for (int i = 0; i < Kc; ++i) master[orig[i]] = hs.col[i];
@@ -1339,8 +1347,10 @@ int pr_features(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
   const int rc = get_prep(ctx, s, prep, N, E, &h);
   if (rc != PR_OK) return rc;
   const PrepPart &part = h.part[0];
-  PR_HIP(launch_features(s, in_offsets, in_indices, outdeg, (int32_t)N, (const int4 *)((const char *)prep + part.hub_off),
-                         part.nhubs, r085, alpha_target, feat, r_target, target));
+  PR_HIP(launch_features(s, in_offsets, in_indices, outdeg, (int32_t)N,
+                         (const int4 *)((const char *)prep + part.desc_off), part.ndesc,
+                         (const int4 *)((const char *)prep + part.hub_off), part.nhubs, r085, alpha_target, feat,
+                         r_target, target));
   return PR_OK;
 }
 

@@ -29,47 +29,116 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) { return (uint16_t)(__flo
 __device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ------------------------------------------------------------------ features
-// Rows of at most kSeg entries: eight lanes per row.  Longer rows (the hub table): one block each.
+// The mean in-neighbour rank is a pull gather like the rank update, so it walks the same tile
+// partition (prep.hip, partition A): a tile of short rows stages its index stream with coalesced
+// loads and the gathered ranks in LDS, then one lane sums each row of at most kFeatLane entries
+// (in entry order) and one wave each longer row; a long row that is one segment is summed by the
+// block; rows of several segments (the hub table) are left to k_features_hubs, one block each.
+constexpr int kFeatLane = 32;
+
+__device__ __forceinline__ void write_features(int64_t v, int32_t deg, double s, int32_t N,
+                                               const int32_t *__restrict__ outdeg, const double *__restrict__ r,
+                                               double alpha_t, float *__restrict__ feat,
+                                               const double *__restrict__ r_target, float *__restrict__ target) {
+  const double Nd = (double)N;
+  float *f = feat + v * kF;
+  f[0] = (float)log1p((double)deg);
+  f[1] = (float)log1p((double)outdeg[v]);
+  f[2] = (float)log(Nd * r[v]);
+  f[3] = deg > 0 ? (float)log(Nd * (s / (double)deg)) : 0.0f;
+  f[4] = (float)alpha_t;
+  if (target) target[v] = (float)log(r_target[v] / r[v]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_features(const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
                                                      const int32_t *__restrict__ outdeg, int32_t N,
+                                                     const int4 *__restrict__ desc, int32_t ndesc,
                                                      const double *__restrict__ r, double alpha_t,
                                                      float *__restrict__ feat, const double *__restrict__ r_target,
                                                      float *__restrict__ target) {
-  const int sub = threadIdx.x & 7;
-  const int64_t groups = (int64_t)gridDim.x * (kBlock / 8);
-  for (int64_t v = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 3; v < N; v += groups) {
-    const int32_t a = off[v], b = off[v + 1];
-    const int32_t deg = b - a;
-    double s = 0.0;
-    if (deg <= kSeg)
-      for (int32_t j = a + sub; j < b; j += 8) s += r[idx[j]];
-    s += __shfl_xor(s, 1, 8);
-    s += __shfl_xor(s, 2, 8);
-    s += __shfl_xor(s, 4, 8);
-    if (sub == 0) {
-      const double Nd = (double)N;
-      float *f = feat + v * kF;
-      f[0] = (float)log1p((double)deg);
-      f[1] = (float)log1p((double)outdeg[v]);
-      f[2] = (float)log(Nd * r[v]);
-      if (deg <= kSeg) f[3] = deg > 0 ? (float)log(Nd * (s / (double)deg)) : 0.0f;
-      f[4] = (float)alpha_t;
-      if (target) target[v] = (float)log(r_target[v] / r[v]);
+  __shared__ double vals[kSpan];
+  __shared__ double red[kWaves];
+  constexpr int kPer = kSpan / kBlock;
+  const int t = threadIdx.x, lane = t & 63;
+  for (int32_t i = blockIdx.x; i < ndesc; i += gridDim.x) {
+    const int4 d = desc[i];
+    const int4 dn = desc[i + 1];
+    const int32_t e0 = d.y, e1 = dn.y;
+    if (d.z < 0) {
+      const int32_t v0 = d.x, v1 = dn.x, n = e1 - e0;
+      int32_t u[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int j = t + k * kBlock;
+        u[k] = j < n ? __builtin_nontemporal_load(idx + e0 + j) : -1;
+      }
+      int32_t ra[kRowsPerLane], rb[kRowsPerLane];
+#pragma unroll
+      for (int q = 0; q < kRowsPerLane; ++q) {
+        const int32_t v = v0 + t + q * kBlock;
+        ra[q] = rb[q] = 0;
+        if (v < v1) {
+          ra[q] = off[v] - e0;
+          rb[q] = off[v + 1] - e0;
+        }
+      }
+      double x[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? r[u[k]] : 0.0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int j = t + k * kBlock;
+        if (j < n) vals[j] = x[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kRowsPerLane; ++q) {
+        const int32_t v = v0 + t + q * kBlock;
+        const bool mine = v < v1;
+        const int32_t deg = rb[q] - ra[q];
+        const bool mid = mine && deg > kFeatLane;
+        double s = 0.0;
+        if (mine && !mid)
+          for (int32_t j = ra[q]; j < rb[q]; ++j) s += vals[j];
+        unsigned long long m = __ballot(mid);
+        while (m) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const int32_t wa = __shfl(ra[q], src, 64), wb = __shfl(rb[q], src, 64);
+          double w = 0.0;
+          for (int32_t j = wa + lane; j < wb; j += 64) w += vals[j];
+          w = wave_sum(w);
+          if (lane == src) s = w;
+        }
+        if (mine) write_features(v, deg, s, N, outdeg, r, alpha_t, feat, r_target, target);
+      }
+      __syncthreads();
+    } else if (d.w < 0) {
+      // a long row that is a single segment [e0, e1)
+      const int32_t v = d.x;
+      double s = 0.0;
+      for (int32_t j = e0 + t; j < e1; j += kBlock) s += r[idx[j]];
+      s = block_sum(s, red);
+      if (t == 0) write_features(v, e1 - e0, s, N, outdeg, r, alpha_t, feat, r_target, target);
     }
   }
 }
 
+// Rows of several segments: one block per row of the hub table.
 __global__ __launch_bounds__(kBlock) void k_features_hubs(const int32_t *__restrict__ off,
-                                                          const int32_t *__restrict__ idx, const int4 *hubs,
-                                                          int32_t N, const double *__restrict__ r,
-                                                          float *__restrict__ feat) {
+                                                          const int32_t *__restrict__ idx,
+                                                          const int32_t *__restrict__ outdeg, const int4 *hubs,
+                                                          int32_t N, const double *__restrict__ r, double alpha_t,
+                                                          float *__restrict__ feat,
+                                                          const double *__restrict__ r_target,
+                                                          float *__restrict__ target) {
   __shared__ double red[kWaves];
   const int4 hb = hubs[blockIdx.x];
   const int32_t v = hb.x, a = off[v], b = off[v + 1];
   double s = 0.0;
   for (int32_t j = a + threadIdx.x; j < b; j += kBlock) s += r[idx[j]];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) feat[(int64_t)v * kF + 3] = (float)log((double)N * (s / (double)(b - a)));
+  if (threadIdx.x == 0) write_features(v, b - a, s, N, outdeg, r, alpha_t, feat, r_target, target);
 }
 
 // ------------------------------------------------------------------ forward
@@ -209,19 +278,35 @@ __global__ __launch_bounds__(kBlock, 2) void k_mlp_backward(const float *__restr
   if (t == 0) loss_part[blockIdx.x] = l;
 }
 
+// Block partials [nb][kParams] -> dW.  Block x owns parameters 64x .. 64x+63; its four waves sum
+// the partials of blocks b = w, w+4, w+8, ... in ascending b (float64), then the four wave sums
+// are added in wave order.  Block 0 also reduces the loss partials.
+constexpr int kReduceParams = 64;
+
 __global__ __launch_bounds__(kBlock) void k_mlp_grad_reduce(const float *__restrict__ part, int32_t nb,
                                                             const double *__restrict__ loss_part, double inv_n,
                                                             float *__restrict__ dW, double *__restrict__ loss) {
-  __shared__ double red[kWaves];
-  for (int p = threadIdx.x; p < kParams; p += kBlock) {
-    float s = 0.f;
-    for (int32_t b = 0; b < nb; ++b) s += part[(int64_t)b * kParams + p];
-    dW[p] = s;
+  __shared__ double red[kWaves][kReduceParams];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int p = blockIdx.x * kReduceParams + lane;
+  double s = 0.0;
+  if (p < kParams)
+    for (int32_t b = wave; b < nb; b += kWaves) s += (double)part[(int64_t)b * kParams + p];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && p < kParams) {
+    double x = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) x += red[w][lane];
+    dW[p] = (float)x;
   }
-  double l = 0.0;
-  for (int32_t b = threadIdx.x; b < nb; b += kBlock) l += loss_part[b];
-  l = block_sum(l, red);
-  if (threadIdx.x == 0) *loss = l * inv_n;
+  if (blockIdx.x == 0) {
+    __shared__ double lred[kWaves];
+    double l = 0.0;
+    for (int32_t b = t; b < nb; b += kBlock) l += loss_part[b];
+    l = block_sum(l, lred);
+    if (t == 0) *loss = l * inv_n;
+  }
 }
 
 // ------------------------------------------------------------------ Adam (Kingma and Ba, Algorithm 1)
@@ -284,11 +369,14 @@ int mlp_backward_blocks(int64_t N) {
 }
 
 hipError_t launch_features(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
-                           const int4 *hubs, int32_t nhubs, const double *r, double alpha_t, float *feat,
-                           const double *r_target, float *target) {
-  hipLaunchKernelGGL(k_features, dim3(blocks_for((int64_t)N * 8, 8192)), dim3(kBlock), 0, s, off, idx, outdeg, N, r,
-                     alpha_t, feat, r_target, target);
-  if (nhubs > 0) hipLaunchKernelGGL(k_features_hubs, dim3(nhubs), dim3(kBlock), 0, s, off, idx, hubs, N, r, feat);
+                           const int4 *desc, int32_t ndesc, const int4 *hubs, int32_t nhubs, const double *r,
+                           double alpha_t, float *feat, const double *r_target, float *target) {
+  const unsigned grid = (unsigned)std::min<int64_t>(std::max<int32_t>(ndesc, 1), 4 * 2048);
+  hipLaunchKernelGGL(k_features, dim3(grid), dim3(kBlock), 0, s, off, idx, outdeg, N, desc, ndesc, r, alpha_t, feat,
+                     r_target, target);
+  if (nhubs > 0)
+    hipLaunchKernelGGL(k_features_hubs, dim3(nhubs), dim3(kBlock), 0, s, off, idx, outdeg, hubs, N, r, alpha_t, feat,
+                       r_target, target);
   return hipGetLastError();
 }
 
@@ -304,7 +392,8 @@ hipError_t launch_mlp_backward(hipStream_t s, const float *W, const float *feat,
   const double inv_n = 1.0 / (double)N;
   hipLaunchKernelGGL(k_mlp_backward, dim3(nb), dim3(kBlock), 0, s, W, feat, act, y, target, N, inv_n, part,
                      loss_part);
-  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3(1), dim3(kBlock), 0, s, (const float *)part, nb,
+  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kParams + kReduceParams - 1) / kReduceParams), dim3(kBlock), 0, s,
+                     (const float *)part, nb,
                      (const double *)loss_part, inv_n, dW, loss);
   return hipGetLastError();
 }

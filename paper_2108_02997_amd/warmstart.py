@@ -3,9 +3,13 @@
 A per-vertex perceptron (5 -> 32 -> 32 -> 1, ReLU, float32 weights, bfloat16 activations) trained
 on ranks the solver itself produces proposes the start vector of a solve at a new alpha from the
 alpha = 0.85 ranks.  The power iteration then corrects it; a judge runs the candidate starts
-(network, alpha = 0.85 ranks, uniform) as columns of one batched update and keeps the one with
-the smallest first-update change in the norm the solve stops on, so the uniform start of the
-paper's method remains the fallback.  Every numerical step runs in libprpull.so (pr_features, pr_mlp_forward,
+(network, alpha = 0.85 ranks, uniform) as columns of one batched solve for a few updates and
+keeps the column whose last change, in the norm the solve stops on, is smallest; the solve
+continues from that column's iterate, so the judging updates are not lost and the uniform start
+of the paper's method remains the fallback.  A look-ahead of a few updates rather than one:
+the network's errors are local and die out within two or three updates, while the alpha = 0.85
+ranks differ from the target along slowly contracting directions, so a one-update comparison
+tends to prefer the latter even where it needs more updates in total.  Every numerical step runs in libprpull.so (pr_features, pr_mlp_forward,
 pr_mlp_backward, pr_adam_step, pr_warm_start_vector, pr_pull_batch); this module only sequences
 the calls and owns the tensors.
 """
@@ -136,21 +140,23 @@ class WarmStart:
         y, _ = forward(self.ctx, self.W, feat)
         return start_vector(self.ctx, feat, y)
 
-    def judge(self, g: DeviceGraph, alpha: float, candidates, norm: int = PR_L1):
-        """One batched update from every candidate start; the smallest change in `norm` wins."""
-        probs = [dict(alpha=alpha, tau=0.0, norm=norm, max_iter=1)] * len(candidates)
+    def judge(self, g: DeviceGraph, alpha: float, candidates, norm: int = PR_L1, steps: int = 3):
+        """`steps` float64 updates from every candidate start as columns of one batch; the smallest
+        last change in `norm` wins.  Returns (winner, last changes, iterates after `steps`)."""
+        probs = [dict(alpha=alpha, tau=0.0, norm=norm, max_iter=steps)] * len(candidates)
         res = pull_batch(self.ctx, g, probs, precision=PR_FP64, inits=list(candidates))
         e = [r["err"][norm - 1] for r in res]
         best = int(np.argmin(e))
-        return best, e
+        return best, e, [r["ranks"] for r in res]
 
-    def start(self, g: DeviceGraph, r085: torch.Tensor, alpha: float, norm: int = PR_L1):
-        """Judged start for a solve at alpha stopping on `norm`: (vector, chosen name, first-update
-        changes of the candidates, seconds spent on features, inference and judging)."""
+    def start(self, g: DeviceGraph, r085: torch.Tensor, alpha: float, norm: int = PR_L1, steps: int = 3):
+        """Judged start for a solve at alpha stopping on `norm`.  Returns (iterate of the winning
+        column after `steps` updates, its name, the candidates' last changes, `steps`, seconds spent
+        on features, inference and judging).  A solve continued from the iterate has done `steps`
+        updates more than its own count says."""
         t0 = time.perf_counter()
         mlp = self.propose(g, r085, alpha)
         uniform = torch.full((g.N,), 1.0 / g.N, dtype=torch.float64, device=g.off.device)
-        cands = [mlp, r085, uniform]
-        best, e = self.judge(g, alpha, cands, norm)
+        best, e, iterates = self.judge(g, alpha, [mlp, r085, uniform], norm, steps)
         torch.cuda.synchronize()
-        return cands[best], ("mlp", "r085", "uniform")[best], e, time.perf_counter() - t0
+        return iterates[best], ("mlp", "r085", "uniform")[best], e, steps, time.perf_counter() - t0
