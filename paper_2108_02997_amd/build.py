@@ -1,7 +1,8 @@
 """Build libprpull.so (HIP, gfx950) in-tree with hipcc.
 
 Every .hip file under csrc/ is compiled to an object, then all are linked into
-paper_2108_02997_amd/libprpull.so next to this file.
+paper_2108_02997_amd/libprpull.so next to this file.  The measurement kernels of microbench/
+are built into microbench/libgather_ceiling.so (not part of the solver).
 """
 from __future__ import annotations
 
@@ -56,7 +57,20 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, OUT)
+    build_microbench()
     return OUT
+
+
+def build_microbench() -> str:
+    src = os.path.join(HERE, "microbench", "gather_ceiling.hip")
+    out = os.path.join(HERE, "microbench", "libgather_ceiling.so")
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
