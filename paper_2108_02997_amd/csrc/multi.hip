@@ -3,10 +3,11 @@
 // functions, applied to every graph of the batch).
 //
 // All graphs iterate in lockstep global rounds; a graph that stops stays untouched.  A round is
-//   phase 1: every workgroup walks the global tile list (tile gi of graph g, in graph order, at
-//            stride gridDim.x) with the single-vector tile code; row epilogues accumulate per
-//            workgroup into the accumulator of the current graph, flushed to part[block][g]
-//            whenever the graph changes; hub segment sums go to the graph's slot array;
+//   phase 1: the graphs' tiles are numbered globally in graph order and global tile gi belongs
+//            to workgroup gi % gridDim.x; every workgroup takes, graph by graph, its tiles of the
+//            active graphs with the single-vector tile code; row epilogues accumulate per
+//            workgroup and graph and are flushed to part[block][g]; hub segment sums go to the
+//            graph's slot array;
 //   grid barrier;
 //   phase 2: graph g is finished by workgroup g % gridDim.x: hub rows (segments in order), the
 //            partials of the workgroups that touched g in block order, then its teleport term,
@@ -37,37 +38,36 @@ __device__ __forceinline__ void flush_acc(const MultiParams &p, int g, Acc &a, d
   a = Acc{0.0, 0.0, 0.0, 0.0};
 }
 
-// Graph owning global tile gi (binary search over the graphs' first tiles).
-__device__ __forceinline__ int graph_of(const int32_t *__restrict__ base, int G, int32_t gi) {
-  int lo = 0, hi = G - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (base[mid] <= gi) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
   __shared__ double vals[kSpan];
   __shared__ double red[kFinBlock / 64];
-  __shared__ int s_any;
+  __shared__ int32_t s_act[kBlock], s_base[kBlock + 1];
   cg::grid_group grid = cg::this_grid();
   const int t = threadIdx.x;
+  const int32_t nblk = (int32_t)gridDim.x, blk = (int32_t)blockIdx.x;
   for (int32_t round = 0; round < p.max_rounds; ++round) {
-    // ---- phase 1: tiles of all active graphs
-    int cur = -1;
-    Acc a = {0.0, 0.0, 0.0, 0.0};
-    TileCtx<double> c{};
-    for (int32_t gi = blockIdx.x; gi < p.total_tiles; gi += gridDim.x) {
-      const int g = graph_of(p.tile_base, p.G, gi);
-      const MultiGraph &mg = p.graphs[g];
-      MultiGraphState &gs = p.states[g];
-      if (!gs.active) continue;
-      if (g != cur) {
-        if (cur >= 0) flush_acc(p, cur, a, red);
-        cur = g;
+    // ---- phase 1: this workgroup's tiles of every active graph.  Global tile gi belongs to
+    // workgroup gi % gridDim.x; the graphs' activity flags and first tiles are staged in LDS,
+    // kBlock graphs at a time, so a stopped graph costs one LDS read.
+    for (int32_t g0 = 0; g0 < p.G; g0 += kBlock) {
+      const int32_t ng = min(kBlock, p.G - g0);
+      __syncthreads();
+      if (t < ng) {
+        s_act[t] = p.states[g0 + t].active;
+        s_base[t] = p.tile_base[g0 + t];
+      }
+      if (t == 0) s_base[ng] = p.tile_base[g0 + ng];
+      __syncthreads();
+      for (int32_t k = 0; k < ng; ++k) {
+        if (!s_act[k]) continue;
+        const int32_t base = s_base[k], end = s_base[k + 1];
+        const int32_t first = base + ((blk - base) % nblk + nblk) % nblk;
+        if (first >= end) continue;
+        const int32_t g = g0 + k;
+        const MultiGraph &mg = p.graphs[g];
+        const MultiGraphState &gs = p.states[g];
         const int par = gs.iters & 1;
+        TileCtx<double> c{};
         c.off = mg.off;
         c.idx = mg.idx;
         c.outdeg = mg.outdeg;
@@ -77,11 +77,11 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
         c.c0 = gs.c0;
         c.alpha = mg.alpha;
         c.mid_deg = mg.mid_deg;
+        Acc a = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t gi = first; gi < end; gi += nblk) update_tile<double>(c, mg.desc[gi - base], mg.desc[gi - base + 1], a, vals, red);
+        flush_acc(p, g, a, red);
       }
-      const int32_t li = gi - p.tile_base[g];
-      update_tile<double>(c, mg.desc[li], mg.desc[li + 1], a, vals, red);
     }
-    if (cur >= 0) flush_acc(p, cur, a, red);
     grid.sync();
 
     // ---- phase 2: one workgroup per graph
@@ -141,13 +141,10 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
       __syncthreads();
     }
     grid.sync();
-    if (t == 0) {
-      int any = 0;
-      for (int g = 0; g < p.G; ++g) any |= p.states[g].active;
-      s_any = any;
-    }
-    __syncthreads();
-    if (!s_any) break;
+    // every lane reads a strided share of the flags; the block ORs them
+    int any = 0;
+    for (int g = t; g < p.G; g += kBlock) any |= p.states[g].active;
+    if (!__syncthreads_or(any)) break;
   }
 }
 
