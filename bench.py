@@ -25,6 +25,9 @@ Other workloads (one JSON line each, same keys):
   --workload multi      64 seeded graphs of uneven size (log-uniform 1e3 .. 1e6 vertices) with
                         their own alpha/tau/norm, autotuned, in one persistent launch, against
                         the sum of 64 sequential solves
+  --workload norms      sections 3 and 4 on the same 64 graphs at alpha = 0.85: iterations and
+                        times of L1/L2/Linf at tau = 1e-6 with the six composite ratios (tables
+                        3.1/3.2), and the 21-tolerance sweep read off one traced launch
   --workload warmstart  the learned warm start: a network trained on 20 R-MAT scale-20 graphs
                         proposes start vectors for alpha = 0.90/0.95/0.99 on an unseen scale-24
                         graph; iterations and time from the uniform, alpha=0.85 and learned starts
@@ -389,6 +392,82 @@ def run_multi(args, pr, gg, np, torch):
     return line
 
 
+# ------------------------------------------------------------------ sections 3 and 4 over many graphs
+
+def run_norms(args, pr, gg, np, torch):
+    from paper_2108_02997_amd import report
+    specs = gg.many_graph_specs()
+    log("generating %d graphs" % len(specs))
+    hosts = [gg.make_spec_graph(s) for s in specs]
+    ctx = pr.Context(0)
+    graphs = [pr.DeviceGraph.from_host(h, 0) for h in hosts]
+    for dg in graphs:
+        dg.prepare(ctx)
+        dg.autotune(ctx)
+    alpha = 0.85
+    # section 3: alpha = 0.85, tau = 1e-6, each error function; per graph the mean of `steps`
+    # timed solves after one untimed one (the paper times 5 runs and takes the AM)
+    it3 = np.zeros((len(graphs), 3))
+    ms3 = np.zeros((len(graphs), 3))
+    for n in (1, 2, 3):
+        for i, dg in enumerate(graphs):
+            def solve():
+                return pr.pull(ctx, dg, alpha=alpha, tau=1e-6, norm=n)
+            solve()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                out = solve()
+            torch.cuda.synchronize()
+            ms3[i, n - 1] = (time.perf_counter() - t0) / args.steps * 1e3
+            it3[i, n - 1] = out["iterations"]
+        log("section 3, norm %d: %d iterations over the graphs" % (n, int(it3[:, n - 1].sum())))
+    # the same 64 solves as one persistent launch per error function
+    batch_ms, same = [], 0
+    for n in (1, 2, 3):
+        probs = [dict(alpha=alpha, tau=1e-6, norm=n, max_iter=500)] * len(graphs)
+        pr.pull_multi(ctx, graphs, probs)
+        ts, res = timed(lambda: pr.pull_multi(ctx, graphs, probs), args.steps, "one launch, norm %d" % n)
+        batch_ms.append(round(float(np.mean(ts)) * 1e3, 3))
+        same += sum(int(r["iterations"] == k) for r, k in zip(res, it3[:, n - 1].astype(int)))
+    # section 4: one traced solve per graph to the smallest tolerance in L1 (the largest of the
+    # three errors, so every (tau, norm) stop lies on the trace), all graphs in one launch
+    taus = gg.tau_sweep_21()
+    probs = [dict(alpha=alpha, tau=min(taus), norm=1, max_iter=500)] * len(graphs)
+    t0 = time.perf_counter()
+    res = pr.pull_multi(ctx, graphs, probs, trace=True)
+    torch.cuda.synchronize()
+    sweep_ms = (time.perf_counter() - t0) * 1e3
+    Y = np.stack([report.stops(r["trace"].cpu().numpy(), taus) for r in res], axis=1)  # [tau][graph][norm]
+    assert np.all(Y > 0), "a stop was not reached"
+    edges = float(sum(h.E * r["iterations"] for h, r in zip(hosts, res)))
+    line = base_line("sections 3-4 over 64 graphs: GM-RATIO of iterations, Linf vs L1 (alpha=0.85, tau=1e-6)",
+                     round(report.composite(it3, 0)["GM-RATIO"][2], 4), "ratio", args, float(np.sum(ms3[:, 0])),
+                     "f64", {"workload": "64 seeded graphs (seed 1000) as in --workload multi, every graph at "
+                                         "alpha=0.85; section 3 at tau=1e-6 for L1/L2/Linf; section 4 over the 21 "
+                                         "tolerances 1 ... 1e-10 read off one traced solve per graph",
+                             "graphs": len(hosts), "sum_E": sum(h.E for h in hosts)}, higher=False)
+    line["section3"] = {
+        "iterations_mean": [round(x, 3) for x in it3.mean(axis=0)],
+        "time_ms_sum_sequential": [round(x, 3) for x in ms3.sum(axis=0)],
+        "time_ms_one_launch": batch_ms,
+        "one_launch_same_iterations": "%d of %d" % (same, 3 * len(graphs)),
+        "table_3_1_times": {"baseline_L1": report.composite(ms3, 0), "baseline_Linf": report.composite(ms3, 2)},
+        "table_3_2_iterations": {"baseline_L1": report.composite(it3, 0), "baseline_Linf": report.composite(it3, 2)},
+    }
+    line["section4"] = {
+        "taus": list(taus),
+        "mean_iterations_per_tau": [[round(float(x), 3) for x in Y[i].mean(axis=0)] for i in range(len(taus))],
+        "nested_AM_vs_L1": report.nested(Y, 0, "AM"), "nested_GM_vs_L1": report.nested(Y, 0, "GM"),
+        "single_iteration_stops": [[int(x) for x in (Y[i] == 1).sum(axis=0)] for i in range(len(taus))],
+        "traced_launch_ms": round(sweep_ms, 3), "traced_launch_GTEPS": round(edges / sweep_ms / 1e6, 2),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(hosts, args.cpu_seconds, "all 64 graphs")
+    ctx.close()
+    return line
+
+
 # ------------------------------------------------------------------ learned warm start
 
 def run_warmstart(args, pr, gg, np, torch):
@@ -476,7 +555,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sweep", "tau", "multi", "warmstart"], default="sweep")
+    ap.add_argument("--workload", choices=["sweep", "tau", "multi", "norms", "warmstart"], default="sweep")
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default: 24, or 22 for --workload tau)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -502,7 +581,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
-    run = {"sweep": run_sweep, "tau": run_tau, "multi": run_multi, "warmstart": run_warmstart}[args.workload]
+    run = {"sweep": run_sweep, "tau": run_tau, "multi": run_multi, "norms": run_norms,
+           "warmstart": run_warmstart}[args.workload]
     line = run(args, pr, gg, np, torch)
     print(json.dumps(line), flush=True)
 

@@ -89,3 +89,25 @@ def test_multi_errors(pr, ctx):
     g = pr.DeviceGraph.from_host(gg.cycle(4))
     with pytest.raises(pr.PrError):
         pr.pull_multi(ctx, [g], [dict(alpha=0.85, tau=-1.0, norm=1, max_iter=10)])
+
+
+def test_tau_norm_stops_from_one_launch(pr, ctx):
+    # section 4 readout: every (tau, norm) stop of the 21-tolerance sweep read off the traces of
+    # one many-graph launch equals the stop read off the oracle's traces (tie rule of the module)
+    from paper_2108_02997_amd import report
+    specs = small_specs(12, 77)
+    hosts = [gg.make_spec_graph(s) for s in specs]
+    graphs = [pr.DeviceGraph.from_host(h) for h in hosts]
+    taus = gg.tau_sweep_21()
+    probs = [dict(alpha=0.85, tau=1e-10, norm=1, max_iter=500)] * len(hosts)
+    res = pr.pull_multi(ctx, graphs, probs, trace=True)
+    for r, h in zip(res, hosts):
+        ref = oracle.pagerank_graph(h, alpha=0.85, tau=1e-10, norm=1, trace=True)
+        got = report.stops(r["trace"].cpu().numpy(), taus)
+        want = report.stops(ref["trace"], taus)
+        for i, tau in enumerate(taus):
+            for n in range(3):
+                if got[i, n] != want[i, n]:
+                    col = ref["trace"][:, n]
+                    k = min(got[i, n], want[i, n])
+                    assert abs(got[i, n] - want[i, n]) == 1 and abs(col[k - 1] - tau) <= 1e-4 * tau, (tau, n)
