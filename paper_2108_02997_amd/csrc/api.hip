@@ -375,6 +375,7 @@ struct BatchLayout {
   BatchCols *cols;
   double *bpart;
   double *hpart;
+  double *hacc;
   float *y32[2];
   double *y64[2];
   void *prep;
@@ -396,6 +397,7 @@ BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t preci
   L.cols = (BatchCols *)c.take(sizeof(BatchCols));
   L.bpart = (double *)c.take(sizeof(double) * 4 * kMaxCols * (size_t)kMaxGrid);
   L.hpart = (double *)c.take(sizeof(double) * kMaxCols * (size_t)max_slots(N, E));
+  L.hacc = (double *)c.take(sizeof(double) * 4 * kMaxCols * (size_t)hub_blocks(max_hubs(N, E)));
   if (precision == PR_MIXED) {
     L.y32[0] = (float *)c.take(sizeof(float) * (size_t)(N * kp32));
     L.y32[1] = (float *)c.take(sizeof(float) * (size_t)(N * kp32));
@@ -844,6 +846,7 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   p.hubs = (const int4 *)((const char *)pp + part.hub_off);
   p.bpart = L.bpart;
   p.hpart = L.hpart;
+  p.hacc = L.hacc;
   p.st = L.st;
   p.cols = L.cols;
   int cus = 0;

@@ -56,6 +56,7 @@ struct BatchParams {
   const int4 *hubs;
   double *bpart;   // [grid][Kp][4]
   double *hpart;   // [slots][Kp]
+  double *hacc;    // [hub blocks][Kp][4]: the hub rows' error and dangling partials
   BatchState *st;
   const BatchCols *cols;
 };
@@ -102,6 +103,10 @@ __device__ __forceinline__ void batch_finalize_column(const BatchParams &p, int 
     }
   }
 }
+
+// Hub rows (several segments) are finished kHubsPerBlock to a workgroup, one lane per (row, column).
+constexpr int kHubsPerBlock = kBlock / 16;
+__host__ __device__ inline int64_t hub_blocks(int64_t nhubs) { return (nhubs + kHubsPerBlock - 1) / kHubsPerBlock; }
 
 hipError_t launch_batch_update(hipStream_t s, bool fp32, int C, unsigned grid, const BatchParams &p);
 int batch_blocks_per_cu(bool fp32, int C);

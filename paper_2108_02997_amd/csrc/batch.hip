@@ -12,8 +12,9 @@
 //   per-column segment partials for k_batch_finish.
 // Every column has its own c0, alpha, tau, norm, iteration count and stop decision; a column
 // that stops is masked (no writes) and keeps its last iterate in the buffer given by its own
-// update parity.  k_batch_finish (one block) combines hubs, reduces the block partials per
-// column in block order and finalizes every active column.
+// update parity.  k_batch_hubs finishes the rows of several segments (16 rows per workgroup);
+// k_batch_finish (one block) reduces the update and hub partials per column in block order and
+// finalizes every active column.
 #include "batch.h"
 
 namespace prpull {
@@ -292,7 +293,49 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
   }
 }
 
-// One block of kFinBlock lanes: lane t works on column t % 16 (columns >= Kp idle).
+// Hub rows: lane t of workgroup b finishes column t % 16 of hub row 16*b + t/16 (its segment
+// sums in segment order, then the epilogue); the workgroup's per-column partials are combined over
+// its 16 rows in row order and stored to hacc[b].
+template <typename VT, int C>
+__global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
+  constexpr int KP = 4 * C;
+  __shared__ double sacc[kHubsPerBlock][16][4];
+  const BatchState *st = p.st;
+  if (st->head.stop) return;
+  const int t = threadIdx.x, k = t & 15, j = t >> 4;
+  const int32_t h = (int32_t)blockIdx.x * kHubsPerBlock + j;
+  BAcc a = {0.0, 0.0, 0.0, 0.0};
+  if (h < p.nhubs && k < p.K && k < KP && st->col[k].active) {
+    const VT *__restrict__ yin = (const VT *)p.y_in;
+    VT *__restrict__ yout = (VT *)p.y_out;
+    const double c0 = st->col[k].c0, alpha = p.cols->alpha[k];
+    const int4 hb = p.hubs[h];
+    double s = 0.0;
+#pragma unroll 1
+    for (int32_t q = 0; q < hb.y; ++q) s += p.hpart[(int64_t)(hb.z + q) * KP + k];
+    double sv[1] = {s};
+    bool act[1] = {true};
+    BAcc aa[1] = {a};
+    // the epilogue addresses column k of row hb.x
+    batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, &c0, &alpha, act, aa);
+    a = aa[0];
+  }
+  sacc[j][k][0] = a.l1;
+  sacc[j][k][1] = a.sq;
+  sacc[j][k][2] = a.mx;
+  sacc[j][k][3] = a.dang;
+  __syncthreads();
+  if (t < KP * 4) {
+    const int col = t >> 2, f = t & 3;
+    double x = sacc[0][col][f];
+#pragma unroll 1
+    for (int r = 1; r < kHubsPerBlock; ++r) x = f == 2 ? fmax(x, sacc[r][col][f]) : x + sacc[r][col][f];
+    p.hacc[((int64_t)blockIdx.x * KP + col) * 4 + f] = x;
+  }
+}
+
+// One block of kFinBlock lanes: lane t works on column t % 16 (columns >= Kp idle) and adds the
+// partials of the update workgroups, then those of the hub workgroups, each in block order.
 template <typename VT, int C>
 __global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
   constexpr int KP = 4 * C;
@@ -301,26 +344,19 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
   BatchState *st = p.st;
   if (st->head.stop) return;
   const int t = threadIdx.x, k = t & 15, g = t >> 4;
-  const VT *__restrict__ yin = (const VT *)p.y_in;
-  VT *__restrict__ yout = (VT *)p.y_out;
   BAcc a = {0.0, 0.0, 0.0, 0.0};
   const bool col = k < p.K && k < KP && st->col[k].active;
   if (col) {
-    const double c0 = st->col[k].c0, alpha = p.cols->alpha[k];
-    for (int32_t h = g; h < p.nhubs; h += kGroups) {
-      const int4 hb = p.hubs[h];
-      double s = 0.0;
-#pragma unroll 1
-      for (int32_t q = 0; q < hb.y; ++q) s += p.hpart[(int64_t)(hb.z + q) * KP + k];
-      double sv[1] = {s};
-      bool act[1] = {true};
-      BAcc aa[1] = {a};
-      // the epilogue addresses column k of row hb.x
-      batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, &c0, &alpha, act, aa);
-      a = aa[0];
-    }
     for (int32_t b = g; b < p.grid; b += kGroups) {
       const double *bp = p.bpart + ((int64_t)b * KP + k) * 4;
+      a.l1 += bp[0];
+      a.sq += bp[1];
+      a.mx = fmax(a.mx, bp[2]);
+      a.dang += bp[3];
+    }
+    const int32_t nhb = (int32_t)hub_blocks(p.nhubs);
+    for (int32_t b = g; b < nhb; b += kGroups) {
+      const double *bp = p.hacc + ((int64_t)b * KP + k) * 4;
       a.l1 += bp[0];
       a.sq += bp[1];
       a.mx = fmax(a.mx, bp[2]);
@@ -514,18 +550,22 @@ static hipError_t batch_update_c(hipStream_t s, int C, unsigned grid, const Batc
   switch (C) {
     case 1:
       hipLaunchKernelGGL((k_batch_update<VT, 1>), dim3(grid), dim3(kBlock), 0, s, p);
+      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 1>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
       hipLaunchKernelGGL((k_batch_finish<VT, 1>), dim3(1), dim3(kFinBlock), 0, s, p);
       break;
     case 2:
       hipLaunchKernelGGL((k_batch_update<VT, 2>), dim3(grid), dim3(kBlock), 0, s, p);
+      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 2>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
       hipLaunchKernelGGL((k_batch_finish<VT, 2>), dim3(1), dim3(kFinBlock), 0, s, p);
       break;
     case 3:
       hipLaunchKernelGGL((k_batch_update<VT, 3>), dim3(grid), dim3(kBlock), 0, s, p);
+      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 3>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
       hipLaunchKernelGGL((k_batch_finish<VT, 3>), dim3(1), dim3(kFinBlock), 0, s, p);
       break;
     default:
       hipLaunchKernelGGL((k_batch_update<VT, 4>), dim3(grid), dim3(kBlock), 0, s, p);
+      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 4>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
       hipLaunchKernelGGL((k_batch_finish<VT, 4>), dim3(1), dim3(kFinBlock), 0, s, p);
       break;
   }

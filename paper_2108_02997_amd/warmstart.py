@@ -121,7 +121,9 @@ class WarmStart:
     def train(self, samples, epochs: int = 30, lr: float = 3e-3, seed: int = 0):
         """Adam over whole (graph, alpha) samples, one sample per step, epochs in a seeded order."""
         rng = np.random.default_rng(seed)
-        ws = None
+        n_max = max(feat.shape[0] for feat, _ in samples)
+        ws = torch.empty(self.ctx.lib.pr_mlp_backward_workspace_bytes(n_max), dtype=torch.uint8,
+                         device=samples[0][0].device)
         for ep in range(epochs):
             losses = []
             for k in rng.permutation(len(samples)):
