@@ -43,3 +43,12 @@ def test_null_arguments_rejected_on_host():
     assert lib.pr_pull(None, None, None, None, None, 10, 10, None, 0.85, 1e-6, 1, 10, 0, None, None, None, None,
                        0, None) == _lib.PR_EINVAL
     assert lib.pr_set_option(None, b"grid", 3) == _lib.PR_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
