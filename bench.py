@@ -20,6 +20,8 @@ Reported:
   cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
 
 Other workloads (one JSON line each, same keys):
+  --workload small      Erdos-Renyi N=10,000 (average out-degree 8, 5% dangling), one float64 solve
+                        to tau=1e-6 (L1): solve and update times, oracle on one and on all cores
   --workload tau        R-MAT scale 22: every (tau, norm) stop for tau = 1e-3 .. 1e-10 and the
                         three norms, float64 against mixed precision (iterations, time, distance)
   --workload multi      64 seeded graphs of uneven size (log-uniform 1e3 .. 1e6 vertices) with
@@ -122,6 +124,24 @@ def roofline(kernel, alg_bytes, avg_s, launches, traffic):
             "launches_timed": launches}
 
 
+def stream_gbps(torch):
+    """Achievable streaming bandwidth: a 1 GiB device-to-device copy (read + write bytes / time)."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(graphs, seconds, what):
     """The oracle (FP64, OpenMP gather) timed on a bounded number of updates over `graphs`."""
     import oracle
@@ -179,21 +199,9 @@ def run_sweep(args, pr, gg, np, torch):
         return [pr.pull(ctx, dg, alpha=p["alpha"], tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64,
                         ranks=r) for p, r in zip(problems, ranks_s)]
 
-    if args.calibrate:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(5):
-            dst.copy_(src)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(10):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 10 * 2 * src.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-        log("device copy 1 GiB: %.0f GB/s (read+write)" % copy_gbs)
-        del src, dst
+    # achievable streaming bandwidth (also the copy kernel that calibrates the memory counters)
+    copy_gbs = stream_gbps(torch)
+    log("device copy 1 GiB: %.0f GB/s (read+write)" % copy_gbs)
 
     # the plain FP64 reference: 11 sequential solves.  The first (untimed) pass runs with per-launch
     # event timing to measure the single-vector float64 update; the timed passes replay graphs.
@@ -254,10 +262,13 @@ def run_sweep(args, pr, gg, np, torch):
                                          if batch_prec == pr.PR_MIXED else "float64"),
                          "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path})
     line["roofline"] = roofline(kname, alg_per_launch, avg_launch_s, n_dom, traffic)
+    line["roofline"]["frac_of_stream"] = round(line["roofline"]["achieved"] / copy_gbs, 4)
     if n64:
         b64 = single_update_bytes(N, E, 8)
         line["plain_fp64_gather"] = roofline("k_update<double>", b64, ms64 / n64 * 1e-3, n64, traffic64)
         line["plain_fp64_gather"]["gteps_per_update"] = round(E / (ms64 / n64 * 1e-3) / 1e9, 2)
+        line["plain_fp64_gather"]["frac_of_stream"] = round(line["plain_fp64_gather"]["achieved"] / copy_gbs, 4)
+    line["stream_copy_GBps"] = round(copy_gbs, 1)
     line["sweep"] = {
         "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],
         "fp64_iters": [r["fp64_iters"] for r in results], "converged": [r["converged"] for r in results],
@@ -268,11 +279,62 @@ def run_sweep(args, pr, gg, np, torch):
         "l1_vs_alpha_085": [round(x, 6) for x in l1_vs_085],
         "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
         "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
+        "step_ms_min_median": [round(min(times) * 1e3, 3), round(float(np.median(times)) * 1e3, 3)],
+        "graph_passes_per_s": round((n_all / args.steps + max(r["fp64_iters"] for r in results)) / step_s, 2)
+        if n_all else None,
         "first_phase_updates_per_step": round(n_all / args.steps, 2) if n_all else None,
         "first_phase_update_us_all_widths": round(1e3 * ms_all / n_all, 2) if n_all else None,
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")
+    ctx.close()
+    return line
+
+
+# ------------------------------------------------------------------ the small configuration
+
+def run_small(args, pr, gg, np, torch):
+    g = gg.workload_c1()
+    N, E = g.N, g.E
+    ctx = pr.Context(0)
+    dg = pr.DeviceGraph.from_host(g, 0)
+    dg.prepare(ctx)
+
+    def solve():
+        return pr.pull(ctx, dg, alpha=0.85, tau=1e-6, norm=pr.PR_L1, max_iter=500)
+
+    for _ in range(args.warmup):
+        solve()
+    ts, res = timed(solve, args.steps, "solve")
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    solve()
+    ctx.set_option("timing", 0)
+    n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+    step_s = float(np.mean(ts))
+    line = base_line("small configuration: float64 solve time (alpha=0.85, tau=1e-6, L1) on Erdos-Renyi N=10,000",
+                     round(step_s * 1e6, 2), "us", args, step_s * 1e3, "f64",
+                     {"workload": "Erdos-Renyi N=10,000, average out-degree 8, 5% forced dangling, no self-loops, "
+                                  "seed 1; alpha=0.85, tau=1e-6, L1, uniform start, max_iter 500", "N": N, "E": E},
+                     higher=False)
+    line["small"] = {"iterations": res["iterations"], "us_per_update": round(step_s * 1e6 / res["iterations"], 2),
+                     "update_kernel_us": round(1e3 * ms64 / n64, 2) if n64 else None,
+                     "solve_us_min_median": [round(min(ts) * 1e6, 2), round(float(np.median(ts)) * 1e6, 2)],
+                     "note": "launch- and latency-bound (working set < 1 MB): no roofline claim"}
+    if not args.no_cpu:
+        import oracle
+        nt = oracle.max_threads()
+        out = {}
+        for threads in (nt, 1):
+            tt = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                oracle.pagerank_graph(g, alpha=0.85, tau=1e-6, norm=oracle.L1, max_iter=500, threads=threads)
+                tt.append(time.perf_counter() - t0)
+            out[threads] = float(np.mean(tt))
+        line["cpu_baseline"] = {"value": round(out[nt] * 1e6, 2), "unit": "us", "cores": nt,
+                                "kind": "oracle", "sample": "the whole solve, mean of 5 runs on %d threads; "
+                                "one thread: %.2f us; host CPU %s" % (nt, out[1] * 1e6, cpu_model())}
     ctx.close()
     return line
 
@@ -555,12 +617,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["sweep", "tau", "multi", "norms", "warmstart"], default="sweep")
+    ap.add_argument("--workload", choices=["sweep", "small", "tau", "multi", "norms", "warmstart"], default="sweep")
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default: 24, or 22 for --workload tau)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--calibrate", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--calibrate", action="store_true", help="accepted for older command lines; the 1 GiB copy "
+                    "that calibrates the memory counters now always runs")
     ap.add_argument("--path", choices=["batch_mixed", "batch_fp64"], default="batch_mixed",
                     help="the timed sweep: batched mixed precision (default) or batched float64")
     ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 baseline")
@@ -581,7 +644,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
-    run = {"sweep": run_sweep, "tau": run_tau, "multi": run_multi, "norms": run_norms,
+    run = {"sweep": run_sweep, "small": run_small, "tau": run_tau, "multi": run_multi, "norms": run_norms,
            "warmstart": run_warmstart}[args.workload]
     line = run(args, pr, gg, np, torch)
     print(json.dumps(line), flush=True)

@@ -73,14 +73,26 @@ def features(N, off, idx, outdeg, r085, alpha_target):
     return Fm
 
 
-def forward(W, X):
-    """y[N] and the cache for backward.  X is [N][5]."""
+def round_bf16(a):
+    """Round to bfloat16 (the upper 16 bits of a float32: 8-bit significand), nearest, ties to
+    even, returned as float64.  The value is first held as a float32, the precision in which the
+    network's activations are produced before they are stored as bfloat16."""
+    a32 = np.asarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(W, X, activations="fp64"):
+    """y[N] and the cache for backward.  X is [N][5].  activations="bf16" stores both hidden
+    layers rounded to bfloat16, as the warm start's network specifies; "fp64" keeps them exact."""
     p = unpack(W)
     X = np.asarray(X, dtype=np.float64)
+    q = round_bf16 if activations == "bf16" else (lambda a: a)
     z1 = X @ p["W1"].T + p["b1"]
-    h1 = np.maximum(z1, 0.0)
+    h1 = q(np.maximum(z1, 0.0))
     z2 = h1 @ p["W2"].T + p["b2"]
-    h2 = np.maximum(z2, 0.0)
+    h2 = q(np.maximum(z2, 0.0))
     y = h2 @ p["W3"] + p["b3"][0]
     return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
 

@@ -5,18 +5,12 @@
   section 3 taken from both traces; mixed precision per norm against the oracle.
 * R-MAT scale 24 (16,777,216 vertices, ~263 M edges): the eleven-column damping sweep,
   tau = 1e-10 in L-infinity, float32 gather with float64 norms and refinement (the benchmark's
-  step).  Every column: one oracle update applied to the returned ranks stays within the bound
-  that the reported last change implies, vertex by vertex.  alpha = 0.85, 0.95 and 1.00 are also
-  solved in full by the oracle and compared.
+  step, default launch settings).  Every column against its own full oracle solve: within the L1
+  fixed-point bound alpha/(1-alpha) * (e_gpu + e_oracle) for alpha < 1 (section 2 map, an
+  alpha-contraction in L1), within 10 tau per vertex at alpha = 1; the same column solved alone in
+  float64 (the benchmark's baseline) within 1e-12 in L1 with the same iteration count.
 * The uneven batch of 64 graphs (vertex counts log-uniform in [1e3, 1e6]) in one persistent
   launch, every graph against its own oracle solve.
-
-Per-vertex bound (section 2 map G, last change e = ||r_k - r_{k-1}||_inf):
-  |G(r_k)_v - r_k_v| = |G(r_k)_v - G(r_{k-1})_v| + rounding
-                     <= alpha * e * (sum over in-edges u->v of 1/d_u + n_dangling / N) + rounding,
-because c0 moves by alpha/N times the change of the dangling sum and every gathered term by
-alpha * |delta r_u| / d_u.  Rounding: both sides sum (in-degree + a few) float64 terms of one sign,
-so (indeg_v + 8) * 2^-51 * (r_v + G_v) covers it.
 """
 import numpy as np
 import pytest
@@ -46,26 +40,6 @@ def ctx(pr):
     c = pr.Context(0)
     yield c
     c.close()
-
-
-def in_weight(g):
-    """w_v = sum over in-edges u->v of 1/d_u."""
-    inv = np.zeros(g.N)
-    nz = g.outdeg > 0
-    inv[nz] = 1.0 / g.outdeg[nz]
-    dst = np.repeat(np.arange(g.N, dtype=np.int64), np.diff(g.off.astype(np.int64)))
-    return np.bincount(dst, weights=inv[g.idx], minlength=g.N)
-
-
-def check_fixed_point_step(g, w, n_dang, r, alpha, e_inf):
-    """One oracle update from r against the per-vertex bound of the module docstring."""
-    step = oracle.pagerank_graph(g, alpha=alpha, tau=0.0, norm=oracle.L1, max_iter=1, init=r)["ranks"]
-    indeg = np.diff(g.off.astype(np.int64))
-    bound = alpha * e_inf * (w + n_dang / g.N) + (indeg + 8) * 2.0 ** -51 * (np.abs(r) + np.abs(step))
-    gap = np.abs(step - r)
-    worst = int(np.argmax(gap / bound))
-    assert np.all(gap <= bound), (alpha, worst, gap[worst], bound[worst])
-    return float(gap.max())
 
 
 # ------------------------------------------------------------------ scale 22: traces and readout
@@ -129,13 +103,12 @@ def test_scale22_mixed_against_oracle(pr, ctx, rmat22, norm):
 
 @pytest.fixture(scope="module")
 def rmat24():
-    g = gg.rmat(24, edge_factor=16, seed=24)
-    return g, in_weight(g), int((g.outdeg == 0).sum())
+    return gg.rmat(24, edge_factor=16, seed=24)
 
 
 @pytest.fixture(scope="module")
 def dev24(pr, ctx, rmat24):
-    dg = pr.DeviceGraph.from_host(rmat24[0])
+    dg = pr.DeviceGraph.from_host(rmat24)
     dg.prepare(ctx)
     yield dg
     del dg
@@ -152,8 +125,7 @@ def sweep24(pr, ctx, dev24):
     return probs, res
 
 
-def test_scale24_sweep_as_benchmarked(rmat24, sweep24):
-    g, w, n_dang = rmat24
+def test_scale24_sweep_as_benchmarked(sweep24):
     probs, res = sweep24
     report = []
     for r, p in zip(res, probs):
@@ -164,14 +136,13 @@ def test_scale24_sweep_as_benchmarked(rmat24, sweep24):
         # float32 phase left, a drift of float32 rounding (bounded here by 2^-16)
         m = abs(r["ranks"].sum() - 1.0)
         assert m <= (a / (1 - a) * r["err"][0] + 1e-12 if a < 1 else 2.0 ** -16), (a, m)
-        gap = check_fixed_point_step(g, w, n_dang, r["ranks"], a, r["err"][2])
-        report.append((a, r["iterations"], r["fp32_iters"], r["fp64_iters"], "%.2e" % m, "%.2e" % gap))
-    print("scale-24 sweep (alpha, iterations, fp32, fp64, |sum-1|, max |G(r)-r|):", report)
+        report.append((a, r["iterations"], r["fp32_iters"], r["fp64_iters"], "%.2e" % m))
+    print("scale-24 sweep (alpha, iterations, fp32, fp64, |sum-1|):", report)
 
 
-@pytest.mark.parametrize("alpha", [0.85, 0.95, 1.0])
+@pytest.mark.parametrize("alpha", gg.ALPHA_SWEEP)
 def test_scale24_columns_against_full_oracle(pr, ctx, rmat24, dev24, sweep24, alpha):
-    g = rmat24[0]
+    g = rmat24
     p = dict(alpha=alpha, tau=1e-10, norm=3, max_iter=500)
     ref = oracle.pagerank_graph(g, trace=True, **p)
     # the sequential float64 solve of the benchmark's baseline

@@ -85,3 +85,27 @@ def test_start_vector_zero_output_is_r085():
     Fm = np.zeros((4, 5))
     Fm[:, 2] = np.log(4 * r)
     np.testing.assert_allclose(mlp.start_vector(Fm, np.zeros(4)), r, rtol=1e-14)
+
+
+def test_bf16_rounding_from_the_format():
+    # bfloat16 keeps 8 significand bits: between 1 and 2 the spacing is 2^-7
+    cases = [(1.0, 1.0), (1.0 + 2.0 ** -8, 1.0),                       # halfway, ties to the even 1.0
+             (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),                     # halfway, ties to the even 1+2^-6
+             (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),            # just above halfway: up
+             (1.0 + 2.0 ** -8 - 2.0 ** -20, 1.0),                         # just below halfway: down
+             (-3.0, -3.0), (0.0, 0.0), (2.0 ** 100, 2.0 ** 100),
+             (1.0 / 3.0, 171.0 / 512.0)]      # 1.0101010|1010..b x 2^-2: the dropped bits exceed half -> up
+    got = mlp.round_bf16(np.array([c[0] for c in cases]))
+    np.testing.assert_array_equal(got, [c[1] for c in cases])
+
+
+def test_bf16_forward_stays_close_to_exact():
+    W = mlp.init_params(5)
+    X = np.random.default_rng(5).normal(size=(200, 5))
+    y, c = mlp.forward(W, X)
+    yb, cb = mlp.forward(W, X, activations="bf16")
+    # every stored activation is a bfloat16 value, within half a bfloat16 ulp of its own float32 input
+    for h in (cb["h1"], cb["h2"]):
+        np.testing.assert_array_equal(h, mlp.round_bf16(h))
+    np.testing.assert_allclose(cb["h1"], c["h1"], rtol=2.0 ** -8, atol=0)
+    assert np.max(np.abs(yb - y)) <= 2.0 ** -7 * (np.abs(y).max() + 1.0)
