@@ -262,7 +262,8 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
 int pr_mlp_param_count(void);
 
 /* Features from the ranks r085 (device, N float64, e.g. the alpha = 0.85 solution) into feat
- * (device, float32 [N][5]).  prep: pr_prepare output of the graph (its hub table).  For training,
+ * (device, float32 [N][5]).  prep: pr_prepare output of the graph (its tile partition and hub
+ * table: the mean in-neighbour rank is gathered tile by tile like an update).  For training,
  * r_target (device, N float64, the ranks at alpha_target) and target (device, N float32) may be
  * given together: target_v = log(r_target_v / r085_v), the value the network's output should take.
  * Async. */
