@@ -23,7 +23,8 @@ Other workloads (one JSON line each, same keys):
   --workload small      Erdos-Renyi N=10,000 (average out-degree 8, 5% dangling), one float64 solve
                         to tau=1e-6 (L1): solve and update times, oracle on one and on all cores
   --workload tau        R-MAT scale 22: every (tau, norm) stop for tau = 1e-3 .. 1e-10 and the
-                        three norms, float64 against mixed precision (iterations, time, distance)
+                        three norms, float64 against mixed precision (iterations, time, distance),
+                        with a float32-only ablation beside them
   --workload multi      64 seeded graphs of uneven size (log-uniform 1e3 .. 1e6 vertices) with
                         their own alpha/tau/norm, autotuned, in one persistent launch, against
                         the sum of 64 sequential solves
@@ -363,7 +364,10 @@ def run_tau(args, pr, gg, np, torch):
                 res[prec] = (float(np.mean(ts)), out)
                 total[prec] += float(np.mean(ts))
             f, m = res[pr.PR_FP64][1], res[pr.PR_MIXED][1]
+            # ablation: the float32 phase alone, to tau or max_iter (the paper's sensitivity limits)
+            a = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, precision=pr.PR_FP32)
             rows.append({"tau": tau, "norm": norm, "fp64_iterations": f["iterations"],
+                         "fp32_only_iterations": a["iterations"], "fp32_only_converged": bool(a["converged"]),
                          "fp64_ms": round(res[pr.PR_FP64][0] * 1e3, 3),
                          "mixed_iterations": [m["fp32_iters"], m["fp64_iters"]],
                          "mixed_ms": round(res[pr.PR_MIXED][0] * 1e3, 3),

@@ -189,6 +189,20 @@ def complete(N: int) -> Graph:
     return from_edges(N, u[m], v[m], name="complete(%d)" % N)
 
 
+def grid2d(rows: int, cols: int) -> Graph:
+    """Road-like graph: a rows x cols lattice, each cell linked both ways to its 4 neighbours
+    (out-degree 2..4, no dangling vertices, diameter rows + cols - 2).  A stand-in for the paper's
+    road networks: large, low-degree, with every rank near 1/N."""
+    i, j = np.meshgrid(np.arange(rows, dtype=np.int64), np.arange(cols, dtype=np.int64), indexing="ij")
+    v = (i * cols + j).ravel()
+    src, dst = [], []
+    for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        ok = ((i + di >= 0) & (i + di < rows) & (j + dj >= 0) & (j + dj < cols)).ravel()
+        src.append(v[ok])
+        dst.append(((i + di) * cols + (j + dj)).ravel()[ok])
+    return from_edges(rows * cols, np.concatenate(src), np.concatenate(dst), name="grid(%dx%d)" % (rows, cols))
+
+
 def edgeless(N: int) -> Graph:
     return from_edges(N, np.zeros(0, np.int32), np.zeros(0, np.int32), name="edgeless(%d)" % N)
 

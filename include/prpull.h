@@ -51,11 +51,14 @@ enum { PR_L1 = 1, PR_L2 = 2, PR_LINF = 3 };
 /* Arithmetic of the solve.
  * PR_FP64:  contributions, gather, ranks, reductions all in float64.
  * PR_MIXED: a float32 phase (float32 contributions and gather with float32 accumulation;
- *           dangling sum, teleport term and norms in float64) runs until it meets tau or its L1
- *           change stops decreasing; then float64 iterations continue from the float32 iterate
- *           until a float64 update meets tau.  The convergence decision is always taken on a
- *           float64 update. */
-enum { PR_FP64 = 0, PR_MIXED = 1 };
+ *           dangling sum, teleport term and norms in float64) runs until it meets tau, its L1
+ *           change stops decreasing or, for the L1 norm, that change is below 2^-17; then
+ *           float64 iterations continue from the float32 iterate until a float64 update meets
+ *           tau.  The convergence decision is always taken on a float64 update.
+ * PR_FP32:  pr_pull only, an ablation: the float32 phase alone, run until it meets tau or
+ *           max_iter, with no float64 update; it shows where float32 iterates stop converging
+ *           (the paper's sensitivity limits of section 4) and is not meant for results. */
+enum { PR_FP64 = 0, PR_MIXED = 1, PR_FP32 = 2 };
 
 enum {
   PR_OK = 0,
@@ -69,7 +72,7 @@ enum {
 typedef struct {
   int32_t iterations; /* updates performed, including the one that met tau (1..max_iter) */
   int32_t converged;  /* 1 if an update met tau (always a float64 update) */
-  int32_t fp32_iters; /* updates of the float32 phase (PR_MIXED), else 0 */
+  int32_t fp32_iters; /* updates of the float32 phase (PR_MIXED, PR_FP32), else 0 */
   int32_t fp64_iters; /* float64 updates */
   double final_err[3]; /* L1, L2, Linf of r' - r at the last update */
 } pr_result;
@@ -153,7 +156,7 @@ size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_
  *   tau       : tolerance >= 0 (tau = 0 never converges; the solve then runs max_iter updates)
  *   norm      : PR_L1, PR_L2 or PR_LINF
  *   max_iter  : >= 1
- *   precision : PR_FP64 or PR_MIXED
+ *   precision : PR_FP64, PR_MIXED or PR_FP32
  *   init      : device, N values, the start vector (any non-negative vector), or NULL for 1/N
  *   ranks     : device, N values, out: the newest iterate (may alias init)
  *   norm_trace: device, max_iter x 3 values, or NULL

@@ -15,10 +15,11 @@ from dataclasses import dataclass, field
 import torch
 
 from . import _lib
-from ._lib import (MAX_COLS, PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK,  # noqa: F401
+from ._lib import (MAX_COLS, PR_FP32, PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK,  # noqa: F401
                    PrError, pr_graph_problem, pr_problem, pr_result)
 
-__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "pull_multi", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64", "PR_MIXED", "PrError"]
+__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "pull_multi", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64",
+           "PR_MIXED", "PR_FP32", "PrError"]
 
 
 def _require_gpu():

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libprpull.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
-PR_FP64, PR_MIXED = 0, 1
+PR_FP64, PR_MIXED, PR_FP32 = 0, 1, 2
 PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32, PR_KERNEL_MULTI = 0, 1, 2, 3, 4
 PR_KERNEL_BATCH_F64_C1, PR_KERNEL_BATCH_F32_C1, PR_KERNEL_KINDS = 8, 12, 16
 MAX_COLS = 16

@@ -169,7 +169,7 @@ Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep) 
   L.hpart = (double *)c.take(sizeof(double) * (size_t)slots);
   L.y64[0] = (double *)c.take(sizeof(double) * (size_t)N);
   L.y64[1] = (double *)c.take(sizeof(double) * (size_t)N);
-  if (precision == PR_MIXED) {
+  if (precision == PR_MIXED || precision == PR_FP32) {
     L.y32[0] = (float *)c.take(sizeof(float) * (size_t)N);
     L.y32[1] = (float *)c.take(sizeof(float) * (size_t)N);
   }
@@ -666,7 +666,7 @@ int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, cons
 }
 
 size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep) {
-  if (N < 1 || E < 0 || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
+  if (N < 1 || E < 0 || (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32)) return 0;
   return carve(nullptr, N, E, precision, with_prep != 0).total;
 }
 
@@ -695,8 +695,8 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
     set_error("max_iter must be >= 1, got %d", max_iter);
     return PR_EINVAL;
   }
-  if (precision != PR_FP64 && precision != PR_MIXED) {
-    set_error("precision must be PR_FP64 or PR_MIXED, got %d", precision);
+  if (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32) {
+    set_error("precision must be PR_FP64, PR_MIXED or PR_FP32, got %d", precision);
     return PR_EINVAL;
   }
   const Layout L = carve(workspace, N, E, precision, prep == nullptr);
@@ -719,7 +719,7 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
 
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
   const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
-  const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_MIXED ? 1 : 0];
+  const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_FP64 ? 0 : 1];
   const PrepPart &part = h.part[0];
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
 
@@ -763,6 +763,15 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
       if (rc != PR_OK) return rc;
       final_y = L.y64[fbuf];
     }
+  } else if (precision == PR_FP32) {
+    // the float32 phase alone, stopping like a float64 solve (tau met or max_iter)
+    PR_HIP(launch_init(s, true, outdeg, (int32_t)N, init, L.y32[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 0;
+    rc = run_until_stop(ctx, s, update_chunk(ctx, true, grid, p, L.y32[0], L.y32[1]), &L.st->head, max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    fp32_iters = ((LoopHead *)ctx->hstate)->iter;
+    final_y = L.y32[fbuf];
+    final_fp32 = true;
   } else {
     PR_HIP(launch_init(s, false, outdeg, (int32_t)N, init, L.y64[0], alpha, L.st, L.bpart, kMaxGrid));
     p.phase = 0;
@@ -776,7 +785,7 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   const SolveState &hs = *ctx->hstate;
   out->iterations = hs.head.iter;
   out->converged = hs.converged;
-  out->fp32_iters = precision == PR_MIXED ? fp32_iters : 0;
+  out->fp32_iters = precision == PR_FP64 ? 0 : fp32_iters;
   out->fp64_iters = hs.head.iter - out->fp32_iters;
   out->final_err[0] = hs.err[0];
   out->final_err[1] = hs.err[1];

@@ -282,3 +282,33 @@ def test_row_threshold_extremes(pr, ctx, mid):
         check_fp64(pr, ctx, g, tau=1e-10, norm=3)
     finally:
         ctx.set_option("mid_deg", 32)
+
+
+def test_road_like_lattice_single_iteration(pr, ctx):
+    # 1000 x 1000 lattice: the first update changes no rank by more than alpha/(3N) = 2.8e-7, so
+    # L-infinity at tau = 1e-6 stops after one update (the paper's road networks); L1 and L2 run on
+    g = gg.grid2d(1000, 1000)
+    dg = dev(pr, g)
+    res, ref = check_fp64(pr, ctx, g, alpha=0.85, tau=1e-6, norm=3, dg=dg)
+    assert res["iterations"] == 1 == ref["iterations"]
+    for norm in (1, 2):
+        res, ref = check_fp64(pr, ctx, g, alpha=0.85, tau=1e-6, norm=norm, dg=dg)
+        assert res["iterations"] > 1
+
+
+def test_fp32_only_ablation(pr, ctx):
+    # float32 iterate with no float64 update: its stops are its own; where it converges, the
+    # ranks sit within the L1 fixed-point bound of the oracle's plus float32 rounding of the
+    # iterate (2^-24 relative per vertex, amplified at most 1/(1-alpha) by the map)
+    g = gg.rmat(15, seed=41)
+    dg = dev(pr, g)
+    for norm, tau in ((3, 1e-9), (2, 1e-8), (1, 1e-6)):
+        res = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, precision=pr.PR_FP32)
+        ref = oracle.pagerank_graph(g, alpha=0.85, tau=tau, norm=norm)
+        assert res["fp64_iters"] == 0 and res["fp32_iters"] == res["iterations"]
+        assert res["converged"] and res["err"][norm - 1] < tau
+        d = np.abs(res["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert d <= 0.85 / 0.15 * (res["err"][0] + ref["err"][0]) + 2.0 ** -24 / 0.15 * 4, d
+    # the batch and many-graph paths refuse it
+    with pytest.raises(pr.PrError):
+        pr.pull_batch(ctx, dg, [dict(alpha=0.85, tau=1e-6, norm=1, max_iter=10)], precision=pr.PR_FP32)

@@ -64,6 +64,24 @@ def test_large_dangling_sum_is_exact_to_rounding():
     assert res["err"][0] <= 1e-15 and res["err"][2] <= 8 * 2.0 ** -52 / N
 
 
+@pytest.mark.parametrize("rows,cols", [(3, 3), (20, 30), (50, 40)])
+def test_lattice_first_update_by_hand(rows, cols):
+    # Road-like lattice (every cell linked both ways to its 4 neighbours), uniform start, no
+    # dangling vertices.  A corner has two in-neighbours of out-degree 3, so its first update is
+    # (1-alpha)/N + alpha*(2/3)/N: it falls by alpha/(3N), the largest change of any vertex (an
+    # edge cell changes by alpha/(12N), interior cells by at most that).  Hence L-infinity meets
+    # any tau above alpha/(3N) in a single update -- the paper's observation on road networks.
+    g = gg.grid2d(rows, cols)
+    N = rows * cols
+    alpha = 0.85
+    res = run(g, alpha=alpha, tau=0.0, norm=LINF, max_iter=1, trace=True)
+    assert abs(res["trace"][0, 2] - alpha / (3 * N)) <= 1e-15 / N
+    corner = res["ranks"][0]
+    assert abs(corner - ((1 - alpha) / N + alpha * (2.0 / 3.0) / N)) <= 4e-16 / N * 4
+    assert run(g, alpha=alpha, tau=1.01 * alpha / (3 * N), norm=LINF)["iterations"] == 1
+    assert run(g, alpha=alpha, tau=0.99 * alpha / (3 * N), norm=LINF)["iterations"] > 1
+
+
 def in_star_closed_form(L, alpha, k):
     """In-star (leaves -> hub, hub dangling), uniform start: leaves l_k and the three errors at step k."""
     N = L + 1
