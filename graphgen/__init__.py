@@ -203,6 +203,39 @@ def grid2d(rows: int, cols: int) -> Graph:
     return from_edges(rows * cols, np.concatenate(src), np.concatenate(dst), name="grid(%dx%d)" % (rows, cols))
 
 
+def load_mtx(path: str, dedupe: bool = True, drop_self_loops: bool = True) -> Graph:
+    """A graph from a MatrixMarket coordinate file (the format of the paper's SuiteSparse inputs):
+    entry (i, j) is the edge i -> j (1-based in the file); `symmetric` files list each undirected
+    edge once and get both directions; values, if any, are ignored (pattern graph).  Array-format
+    files are refused."""
+    with open(path) as fh:
+        head = fh.readline().split()
+        if len(head) < 5 or head[0] != "%%MatrixMarket" or head[1].lower() != "matrix":
+            raise ValueError("%s: not a MatrixMarket matrix file" % path)
+        fmt, sym = head[2].lower(), head[4].lower()
+        if fmt != "coordinate":
+            raise ValueError("%s: only coordinate (sparse) files hold graphs" % path)
+        if sym not in ("general", "symmetric", "skew-symmetric", "hermitian"):
+            raise ValueError("%s: unknown symmetry %r" % (path, sym))
+        line = fh.readline()
+        while line.startswith("%") or not line.strip():
+            line = fh.readline()
+        rows, cols, nnz = (int(x) for x in line.split()[:3])
+        data = np.loadtxt(fh, dtype=np.float64, ndmin=2, max_rows=nnz, comments="%")
+    if data.shape[0] != nnz or (nnz and data.shape[1] < 2):
+        raise ValueError("%s: expected %d entries, found %d" % (path, nnz, data.shape[0]))
+    N = max(rows, cols)
+    src = data[:, 0].astype(np.int64) - 1 if nnz else np.zeros(0, np.int64)
+    dst = data[:, 1].astype(np.int64) - 1 if nnz else np.zeros(0, np.int64)
+    if nnz and (src.min() < 0 or dst.min() < 0 or src.max() >= N or dst.max() >= N):
+        raise ValueError("%s: an entry lies outside the %d x %d matrix" % (path, rows, cols))
+    if sym != "general":
+        off = src != dst
+        src, dst = np.concatenate([src, dst[off]]), np.concatenate([dst, src[off]])
+    return from_edges(N, src, dst, dedupe=dedupe, drop_self_loops=drop_self_loops,
+                      name=os.path.basename(path))
+
+
 def edgeless(N: int) -> Graph:
     return from_edges(N, np.zeros(0, np.int32), np.zeros(0, np.int32), name="edgeless(%d)" % N)
 

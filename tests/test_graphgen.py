@@ -73,3 +73,27 @@ def test_specs_cover_the_ranges():
     assert {s["norm"] for s in specs} == {1, 2, 3}
     assert gg.ALPHA_SWEEP[0] == 0.5 and gg.ALPHA_SWEEP[7] == 0.85 and gg.ALPHA_SWEEP[-1] == 1.0
     assert len(gg.tau_sweep_21()) == 21
+
+
+def test_load_mtx_general_and_symmetric(tmp_path):
+    gen = tmp_path / "g.mtx"
+    gen.write_text("%%MatrixMarket matrix coordinate pattern general\n% a comment\n4 4 5\n"
+                   "1 2\n2 3\n3 1\n3 4\n3 4\n")          # one duplicate entry
+    g = gg.load_mtx(str(gen))
+    assert g.N == 4 and g.E == 4
+    src, dst = g.edges()
+    assert sorted(zip(src.tolist(), dst.tolist())) == [(0, 1), (1, 2), (2, 0), (2, 3)]
+    assert g.outdeg.tolist() == [1, 1, 2, 0]
+    sym = tmp_path / "s.mtx"
+    sym.write_text("%%MatrixMarket matrix coordinate real symmetric\n3 3 3\n2 1 1.5\n3 2 -1\n3 3 7\n")
+    h = gg.load_mtx(str(sym))                             # both directions; the diagonal is a self-loop
+    src, dst = h.edges()
+    assert sorted(zip(src.tolist(), dst.tolist())) == [(0, 1), (1, 0), (1, 2), (2, 1)]
+    bad = tmp_path / "b.mtx"
+    bad.write_text("%%MatrixMarket matrix array real general\n2 2\n1\n2\n3\n4\n")
+    with pytest.raises(ValueError):
+        gg.load_mtx(str(bad))
+    out = tmp_path / "o.mtx"
+    out.write_text("%%MatrixMarket matrix coordinate pattern general\n2 2 1\n3 1\n")
+    with pytest.raises(ValueError):
+        gg.load_mtx(str(out))
