@@ -127,7 +127,8 @@ int pr_reset_stats(pr_ctx *ctx);
 
 /* --------------------------------------------------------------- graph prep (once per graph) */
 
-/* Bytes of the prep buffer for a graph with N vertices and E CSR entries (an upper bound). */
+/* Bytes of the prep buffer for a graph with N vertices and E CSR entries (an upper bound); 0 when
+ * N is outside [1, 2^31-2] or E outside [0, 2^31-1] (the int32 CSR's range, as in every call). */
 size_t pr_prep_bytes(int64_t N, int64_t E);
 
 /* Partition the rows of the in-edge CSR into work tiles by in-degree: runs of consecutive
@@ -146,7 +147,8 @@ int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, cons
 
 /* ------------------------------------------------------------------ single solve */
 
-/* Device workspace bytes needed by pr_pull (prep == NULL adds room to prepare inside it). */
+/* Device workspace bytes needed by pr_pull (prep == NULL adds room to prepare inside it); 0 for
+ * out-of-range sizes or an unknown precision. */
 size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep);
 
 /* One PageRank solve (sections 2 and 3).
@@ -178,7 +180,7 @@ typedef struct {
   int32_t max_iter; /* >= 1 */
 } pr_problem;
 
-/* Device workspace bytes of pr_pull_batch for K problems (1..16). */
+/* Device workspace bytes of pr_pull_batch for K problems (1..16); 0 for out-of-range arguments. */
 size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep);
 
 /* K problems on one graph in one pass per update over its edges: the damping-factor sweep of

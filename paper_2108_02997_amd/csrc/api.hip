@@ -619,7 +619,7 @@ int pr_reset_stats(pr_ctx *ctx) {
 }
 
 size_t pr_prep_bytes(int64_t N, int64_t E) {
-  if (N < 1 || E < 0) return 0;
+  if (bad_graph_sizes(N, E)) return 0;
   return prep_bytes(N, E);
 }
 
@@ -666,7 +666,7 @@ int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, cons
 }
 
 size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep) {
-  if (N < 1 || E < 0 || (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32)) return 0;
+  if (bad_graph_sizes(N, E) || (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32)) return 0;
   return carve(nullptr, N, E, precision, with_prep != 0).total;
 }
 
@@ -794,7 +794,7 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
 }
 
 size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep) {
-  if (N < 1 || E < 0 || K < 1 || K > kMaxCols || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
+  if (bad_graph_sizes(N, E) || K < 1 || K > kMaxCols || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
   return carve_batch(nullptr, N, E, K, precision, with_prep != 0).total;
 }
 
@@ -1101,7 +1101,7 @@ static size_t multi_layout(int32_t G, const pr_graph_problem *probs, void *ws, M
 size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs) {
   if (G < 1 || G > kMaxGraphs || !probs) return 0;
   for (int g = 0; g < G; ++g)
-    if (probs[g].N < 1 || probs[g].E < 0) return 0;
+    if (bad_graph_sizes(probs[g].N, probs[g].E)) return 0;
   MultiGraph *a;
   MultiGraphState *b;
   int32_t *c;
@@ -1382,7 +1382,7 @@ int pr_mlp_forward(pr_ctx *ctx, void *stream, const float *W, const float *feat,
 }
 
 size_t pr_mlp_backward_workspace_bytes(int64_t N) {
-  if (N < 1) return 0;
+  if (N < 1 || N > 2147483646LL) return 0;
   const int nb = mlp_backward_blocks(N);
   return align_up(sizeof(float) * (size_t)nb * (size_t)mlp_param_count(), 256) +
          align_up(sizeof(double) * (size_t)(nb + 1), 256);

@@ -52,3 +52,19 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_size_limits_of_the_int32_csr():
+    # the largest graph the ABI takes: N = 2^31 - 2 vertices, E = 2^31 - 1 entries (int32 offsets)
+    lib = _lib.load()
+    n_max, e_max = (1 << 31) - 2, (1 << 31) - 1
+    for prec in (0, 1, 2):
+        b = lib.pr_workspace_bytes(n_max, e_max, prec, 1)
+        assert b >= 2 * 8 * n_max and b < 1 << 40
+        assert lib.pr_workspace_bytes(n_max + 1, e_max, prec, 1) == 0
+        assert lib.pr_workspace_bytes(n_max, e_max + 1, prec, 1) == 0
+    assert lib.pr_prep_bytes(n_max, e_max) > 0 and lib.pr_prep_bytes(n_max, e_max + 1) == 0
+    assert lib.pr_batch_workspace_bytes(n_max, e_max, 16, 1, 1) > 0
+    assert lib.pr_batch_workspace_bytes(n_max, e_max, 17, 1, 1) == 0
+    assert lib.pr_batch_workspace_bytes(n_max, e_max, 4, 2, 1) == 0   # no float32-only batches
+    assert lib.pr_mlp_backward_workspace_bytes(n_max) > 0 and lib.pr_mlp_backward_workspace_bytes(0) == 0

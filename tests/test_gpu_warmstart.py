@@ -164,3 +164,14 @@ def test_trained_network_gains_over_uniform_start(pr, ws, ctx):
     print("warm start iterations (alpha, uniform, r085, mlp, judged choice, judged):", report)
     assert sum(r[3] for r in report) < sum(r[1] for r in report)
     assert sum(r[5] for r in report) <= sum(r[1] for r in report)
+
+
+@pytest.mark.parametrize("make", [lambda: gg.edgeless(5), lambda: gg.cycle(7), lambda: gg.in_star(40),
+                                  lambda: gg.out_star(9), gg.two_triangles, lambda: gg.complete(1)])
+def test_features_on_tiny_and_degenerate_graphs(pr, ws, ctx, make):
+    g = make()
+    r85 = oracle.pagerank_graph(g, alpha=0.85, tau=1e-12)["ranks"]
+    dg = pr.DeviceGraph.from_host(g)
+    feat, _ = ws.features(ctx, dg, torch.from_numpy(r85).cuda(), 0.9)
+    ref = omlp.features(g.N, g.off, g.idx, g.outdeg, r85, 0.9)
+    np.testing.assert_allclose(feat.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
