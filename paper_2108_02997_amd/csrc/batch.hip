@@ -478,27 +478,39 @@ __global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restric
                                                           int32_t kp32, double *__restrict__ y64, int32_t kp64,
                                                           int32_t N, int32_t K, const BatchState *st,
                                                           const BatchCols *cols) {
-  int par[kMaxCols], dst[kMaxCols];
-  for (int c = 0; c < kMaxCols; ++c) {
-    par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
-    dst[c] = c < K ? cols->map[c] : -1;
+  // one lane per float32 element, in memory order (coalesced reads); per-column buffer parity
+  // and destination column from LDS
+  __shared__ int s_par[kMaxCols], s_dst[kMaxCols];
+  if (threadIdx.x < kMaxCols) {
+    const int c = threadIdx.x;
+    s_par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
+    s_dst[c] = c < K ? cols->map[c] : -1;
   }
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    for (int c = 0; c < K; ++c) {
-      if (dst[c] >= 0) y64[v * kp64 + dst[c]] = (double)(par[c] ? y32b : y32a)[v * kp32 + c];
-    }
+  __syncthreads();
+  const int64_t total = (int64_t)N * kp32;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int c = (int)(e % kp32);
+    if (c >= K) continue;
+    const int d = s_dst[c];
+    if (d < 0) continue;
+    y64[(e / kp32) * kp64 + d] = (double)(s_par[c] ? y32b : y32a)[e];
   }
 }
 
-// Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.
+// Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.  One lane per
+// destination element, in memory order.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_batch_compact(const VT *__restrict__ src, int32_t kp_src,
                                                           VT *__restrict__ dst, int32_t kp_dst, int32_t N, int32_t K,
                                                           const BatchCols *cols) {
-  int m[kMaxCols];
-  for (int c = 0; c < kMaxCols; ++c) m[c] = c < K ? cols->map[c] : -1;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    for (int c = 0; c < kp_dst; ++c) dst[v * kp_dst + c] = (c < K && m[c] >= 0) ? src[v * kp_src + m[c]] : (VT)0;
+  __shared__ int s_map[kMaxCols];
+  if (threadIdx.x < kMaxCols) s_map[threadIdx.x] = (int)threadIdx.x < K ? cols->map[threadIdx.x] : -1;
+  __syncthreads();
+  const int64_t total = (int64_t)N * kp_dst;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    const int c = (int)(e % kp_dst);
+    const int m = c < kMaxCols ? s_map[c] : -1;
+    dst[e] = m >= 0 ? src[(e / kp_dst) * kp_src + m] : (VT)0;
   }
 }
 
@@ -607,8 +619,8 @@ hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, in
 
 hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
                                 int32_t kp64, int32_t N, int32_t K, const BatchState *st, const BatchCols *cols) {
-  hipLaunchKernelGGL(k_batch_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32a, y32b, kp32, y64, kp64, N,
-                     K, st, cols);
+  hipLaunchKernelGGL(k_batch_convert, dim3(grid_for((int64_t)N * kp32, 8192)), dim3(kBlock), 0, s, y32a, y32b, kp32,
+                     y64, kp64, N, K, st, cols);
   return hipGetLastError();
 }
 
@@ -620,11 +632,11 @@ hipError_t launch_batch_rearm(hipStream_t s, BatchState *st, int32_t K) {
 hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32_t kp_src, void *dst, int32_t kp_dst,
                                 int32_t N, int32_t K, const BatchCols *cols) {
   if (fp32)
-    hipLaunchKernelGGL(k_batch_compact<float>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, (const float *)src, kp_src,
-                       (float *)dst, kp_dst, N, K, cols);
+    hipLaunchKernelGGL(k_batch_compact<float>, dim3(grid_for((int64_t)N * kp_dst, 8192)), dim3(kBlock), 0, s,
+                       (const float *)src, kp_src, (float *)dst, kp_dst, N, K, cols);
   else
-    hipLaunchKernelGGL(k_batch_compact<double>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, (const double *)src,
-                       kp_src, (double *)dst, kp_dst, N, K, cols);
+    hipLaunchKernelGGL(k_batch_compact<double>, dim3(grid_for((int64_t)N * kp_dst, 8192)), dim3(kBlock), 0, s,
+                       (const double *)src, kp_src, (double *)dst, kp_dst, N, K, cols);
   return hipGetLastError();
 }
 
