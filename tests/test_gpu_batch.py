@@ -197,3 +197,24 @@ def test_compaction_with_traces_and_max_iter(pr, ctx):
         if r["iterations"] == ref["iterations"]:
             atol = TRACE_ATOL
             np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=atol)
+
+
+@pytest.mark.parametrize("make", [lambda: gg.edgeless(1), lambda: gg.cycle(2), lambda: gg.in_star(1),
+                                  lambda: gg.out_star(5), gg.two_triangles])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_on_tiny_graphs(pr, ctx, make, precision):
+    g = make()
+    dg = pr.DeviceGraph.from_host(g)
+    probs = [dict(alpha=0.85, tau=1e-12, norm=1, max_iter=500), dict(alpha=0.5, tau=1e-10, norm=3, max_iter=500),
+             dict(alpha=1.0, tau=1e-12, norm=2, max_iter=50)]
+    res = pr.pull_batch(ctx, dg, probs, precision=precision)
+    for r, p in zip(res, probs):
+        ref = oracle.pagerank_graph(g, trace=True, **p)
+        d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        if precision == 0:
+            assert iterations_ok(r["iterations"], ref, p["tau"], p["norm"]), (p, r["iterations"], ref["iterations"])
+            assert d <= 1e-12, (p, d)
+        else:
+            assert r["err"][p["norm"] - 1] < p["tau"] or not r["converged"]
+            bound = p["alpha"] / (1 - p["alpha"]) * (r["err"][0] + ref["err"][0]) + 1e-13 if p["alpha"] < 1 else 1e-6
+            assert d <= bound, (p, d)
