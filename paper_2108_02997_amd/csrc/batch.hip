@@ -394,44 +394,67 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
   }
 }
 
+// Grid-stride lanes over a row-major [N][kp] array in which every lane keeps one column: the
+// stride is the largest multiple of kp within the grid's lane count, so consecutive lanes touch
+// consecutive elements and no lane divides inside its loop.
+struct ColLane {
+  int64_t v;      // first row
+  int64_t vstep;  // rows per grid sweep
+  int c;          // the lane's column
+  bool on;        // lanes past the last whole row of a sweep idle
+};
+
+__device__ __forceinline__ ColLane col_lane(int kp) {
+  const int32_t lanes = (int32_t)(gridDim.x * blockDim.x);
+  const int32_t per = lanes / kp;
+  const int32_t tid = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  ColLane r;
+  r.on = tid < per * kp;
+  r.v = tid / kp;
+  r.c = tid % kp;
+  r.vstep = per;
+  return r;
+}
+
 // Start vectors: column k from init[k] (or 1/N); per-block, per-column dangling sums.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_batch_init(const int32_t *__restrict__ outdeg, int32_t N, int32_t K,
                                                        int32_t kp, BatchParams p, VT *__restrict__ y,
                                                        double *bpart) {
 #pragma clang fp contract(off)
-  __shared__ double red[kWaves][16];
-  double dang[16];
-  for (int c = 0; c < 16; ++c) dang[c] = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    const int32_t dv = outdeg[v];
-    for (int c = 0; c < kp; ++c) {
+  __shared__ double s[kBlock];
+  const ColLane cl = col_lane(kp);
+  double dang = 0.0;
+  if (cl.on) {
+    const int c = cl.c;
+    const double *ini = c < K ? p.cols->init[c] : nullptr;
+    const double r1 = 1.0 / (double)N;
+    for (int64_t v = cl.v; v < N; v += cl.vstep) {
       VT yy = (VT)0;
       if (c < K) {
-        const double *ini = p.cols->init[c];
-        const double r0 = ini ? ini[v] : 1.0 / (double)N;
+        const int32_t dv = outdeg[v];
+        const double r0 = ini ? ini[v] : r1;
         if (dv > 0) {
           yy = (VT)(r0 / (double)dv);
         } else {
           yy = (VT)r0;
-          dang[c] += (double)yy;
+          dang += (double)yy;
         }
       }
       y[v * kp + c] = yy;
     }
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c = 0; c < 16; ++c) {
-    double x = dang[c];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) red[w][c] = x;
-  }
+  s[threadIdx.x] = dang;
   __syncthreads();
+  // per column: the block's lanes of that column in lane order
   if (threadIdx.x < 16) {
-    double x = red[0][threadIdx.x];
-    for (int i = 1; i < kWaves; ++i) x += red[i][threadIdx.x];
-    bpart[(int64_t)blockIdx.x * 16 + threadIdx.x] = x;
+    const int t = threadIdx.x;
+    double x = 0.0;
+    if (t < kp) {
+      const int base = (int)(((int64_t)blockIdx.x * kBlock) % kp);
+      for (int i = (t - base + kp) % kp; i < kBlock; i += kp) x += s[i];
+    }
+    bpart[(int64_t)blockIdx.x * 16 + t] = x;
   }
 }
 
@@ -473,45 +496,29 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_init_finish(const double *_
 }
 
 // Float32 columns -> float64 columns: column c (its newest buffer by its update parity) goes to
-// float64 column map[c] (skipped when map[c] < 0).
+// float64 column map[c] (skipped when map[c] < 0).  Lanes keep one column (coalesced reads).
 __global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restrict__ y32a, const float *__restrict__ y32b,
                                                           int32_t kp32, double *__restrict__ y64, int32_t kp64,
                                                           int32_t N, int32_t K, const BatchState *st,
                                                           const BatchCols *cols) {
-  // one lane per float32 element, in memory order (coalesced reads); per-column buffer parity
-  // and destination column from LDS
-  __shared__ int s_par[kMaxCols], s_dst[kMaxCols];
-  if (threadIdx.x < kMaxCols) {
-    const int c = threadIdx.x;
-    s_par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
-    s_dst[c] = c < K ? cols->map[c] : -1;
-  }
-  __syncthreads();
-  const int64_t total = (int64_t)N * kp32;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
-    const int c = (int)(e % kp32);
-    if (c >= K) continue;
-    const int d = s_dst[c];
-    if (d < 0) continue;
-    y64[(e / kp32) * kp64 + d] = (double)(s_par[c] ? y32b : y32a)[e];
-  }
+  const ColLane cl = col_lane(kp32);
+  if (!cl.on || cl.c >= K) return;
+  const int c = cl.c, d = cols->map[c];
+  if (d < 0) return;
+  const float *__restrict__ src = (st->col[c].phase_updates & 1) ? y32b : y32a;
+  for (int64_t v = cl.v; v < N; v += cl.vstep) y64[v * kp64 + d] = (double)src[v * kp32 + c];
 }
 
-// Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.  One lane per
-// destination element, in memory order.
+// Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.  Lanes keep
+// one destination column, in memory order.
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_batch_compact(const VT *__restrict__ src, int32_t kp_src,
                                                           VT *__restrict__ dst, int32_t kp_dst, int32_t N, int32_t K,
                                                           const BatchCols *cols) {
-  __shared__ int s_map[kMaxCols];
-  if (threadIdx.x < kMaxCols) s_map[threadIdx.x] = (int)threadIdx.x < K ? cols->map[threadIdx.x] : -1;
-  __syncthreads();
-  const int64_t total = (int64_t)N * kp_dst;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
-    const int c = (int)(e % kp_dst);
-    const int m = c < kMaxCols ? s_map[c] : -1;
-    dst[e] = m >= 0 ? src[(e / kp_dst) * kp_src + m] : (VT)0;
-  }
+  const ColLane cl = col_lane(kp_dst);
+  if (!cl.on) return;
+  const int c = cl.c, m = c < K ? cols->map[c] : -1;
+  for (int64_t v = cl.v; v < N; v += cl.vstep) dst[v * kp_dst + c] = m >= 0 ? src[v * kp_src + m] : (VT)0;
 }
 
 // Re-arm for the float64 phase: every column not done becomes active.
@@ -530,22 +537,37 @@ __global__ void k_batch_rearm(BatchState *st, int32_t K) {
   }
 }
 
-// ranks[k][v] from the buffer holding column k's newest iterate.
+// ranks[k][v] from the buffer holding column k's newest iterate.  A block moves tiles of
+// kOutRows rows through LDS: read in memory order (lanes keep one column), written one column
+// per wave, 64 consecutive vertices at a time.
+constexpr int kOutRows = 64;
+constexpr int kOutPitch = kMaxCols + 1;  // odd pitch in doubles: the column reads are conflict-free
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_batch_output(const int32_t *__restrict__ outdeg, const VT *__restrict__ ya,
                                                          const VT *__restrict__ yb, int32_t kp, int32_t N, int32_t K,
                                                          BatchParams p) {
+  __shared__ double tile[kOutRows * kOutPitch];
   const BatchState *st = p.st;
-  int par[16];
-  for (int c = 0; c < 16; ++c) par[c] = c < K ? (st->col[c].phase_updates & 1) : 0;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    const int32_t dv = outdeg[v];
-    for (int c = 0; c < K; ++c) {
-      double *out = p.cols->ranks[c];
-      if (!out) continue;
-      const double y = (double)(par[c] ? yb : ya)[v * kp + c];
-      out[v] = dv > 0 ? y * (double)dv : y;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int rc = t % kp, rr = t / kp, rstep = kBlock / kp;  // load phase: lane (row rr, column rc)
+  const bool ld = rr < rstep && rc < K;
+  const VT *__restrict__ src = ld && (st->col[rc].phase_updates & 1) ? yb : ya;
+  for (int64_t v0 = (int64_t)blockIdx.x * kOutRows; v0 < N; v0 += (int64_t)gridDim.x * kOutRows) {
+    const int rows = (int)(N - v0 < kOutRows ? N - v0 : kOutRows);
+    if (ld) {
+      for (int r = rr; r < rows; r += rstep) tile[r * kOutPitch + rc] = (double)src[(v0 + r) * kp + rc];
     }
+    __syncthreads();
+    if (lane < rows) {
+      const int32_t dv = outdeg[v0 + lane];
+      for (int c = wave; c < K; c += kWaves) {
+        double *out = p.cols->ranks[c];
+        if (!out) continue;
+        const double y = tile[lane * kOutPitch + c];
+        out[v0 + lane] = dv > 0 ? y * (double)dv : y;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -555,6 +577,11 @@ static unsigned grid_for(int64_t n, int64_t cap) {
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (unsigned)g;
+}
+
+static unsigned out_grid(int64_t N) {
+  const int64_t tiles = (N + kOutRows - 1) / kOutRows;
+  return (unsigned)(tiles < 1 ? 1 : tiles > 4096 ? 4096 : tiles);
 }
 
 template <typename VT>
@@ -607,7 +634,7 @@ int batch_blocks_per_cu(bool fp32, int C) {
 
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase) {
-  const unsigned g = grid_for(N, bpart_blocks < 1024 ? bpart_blocks : 1024);
+  const unsigned g = grid_for((int64_t)N * kp, bpart_blocks < 2048 ? bpart_blocks : 2048);
   if (fp32)
     hipLaunchKernelGGL(k_batch_init<float>, dim3(g), dim3(kBlock), 0, s, outdeg, N, K, kp, p, (float *)y, bpart);
   else
@@ -643,10 +670,10 @@ hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32
 hipError_t launch_batch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *ya, const void *yb,
                                int32_t kp, int32_t N, int32_t K, const BatchParams &p) {
   if (fp32)
-    hipLaunchKernelGGL(k_batch_output<float>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, outdeg,
+    hipLaunchKernelGGL(k_batch_output<float>, dim3(out_grid(N)), dim3(kBlock), 0, s, outdeg,
                        (const float *)ya, (const float *)yb, kp, N, K, p);
   else
-    hipLaunchKernelGGL(k_batch_output<double>, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, outdeg,
+    hipLaunchKernelGGL(k_batch_output<double>, dim3(out_grid(N)), dim3(kBlock), 0, s, outdeg,
                        (const double *)ya, (const double *)yb, kp, N, K, p);
   return hipGetLastError();
 }
