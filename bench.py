@@ -232,8 +232,9 @@ def run_sweep(args, pr, gg, np, torch):
     # + 4N (out-degrees) + 2*s*K_a*N (read and write of the active columns, s bytes each).
     fp32 = batch_prec == pr.PR_MIXED
     s_bytes = 4 if fp32 else 8
-    C0 = 4 if fp32 and K > 8 else (K + 3) // 4
-    dom_kind = (pr._lib.PR_KERNEL_BATCH_F32_C1 if fp32 else pr._lib.PR_KERNEL_BATCH_F64_C1) + C0 - 1
+    # the widest row width that ran: the one of the first launches
+    kp0 = max(w for w in pr._lib.BATCH_ROW_WIDTHS if ctx.stats(pr._lib.batch_kind(fp32, w))[0] > 0)
+    dom_kind = pr._lib.batch_kind(fp32, kp0)
     phase1 = [r["fp32_iters"] for r in results] if fp32 else iters
     n_dom, ms_dom = ctx.stats(dom_kind)
     per_step = max(1, round(n_dom / args.steps))
@@ -242,7 +243,7 @@ def run_sweep(args, pr, gg, np, torch):
     avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
     n_f64, ms_f64 = ctx.stats(pr._lib.PR_KERNEL_BATCH_F64)
     n_all, ms_all = ctx.stats(pr._lib.PR_KERNEL_BATCH_F32 if fp32 else pr._lib.PR_KERNEL_BATCH_F64)
-    kname = "k_batch_update<%s,%d>" % ("float" if fp32 else "double", C0)
+    kname = "k_batch_update<%s,%d>" % ("float" if fp32 else "double", kp0)
     digest = source_digest([CSRC + "batch.hip", CSRC + "batch.h", CSRC + "internal.h"])
     traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if s_bytes == 4 else "f64", scale), digest)
     d64 = source_digest([CSRC + "pull.hip", CSRC + "device.h", CSRC + "internal.h"])

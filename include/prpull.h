@@ -99,6 +99,9 @@ const char *pr_version(void);
  *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
+ *   "narrow": 1 (default) = one or two columns of pr_pull_batch run on rows of one or two values;
+ *             0 = rows hold at least four values (the row layouts keep every column's sums in
+ *             the same order, so with a pinned grid compaction then leaves results bitwise equal)
  *   "timing": 1 = launch updates one by one, each bracketed by HIP events on the solve stream,
  *             and accumulate their durations (pr_get_stats); graphs are not replayed meanwhile
  * Returns PR_OK or PR_EINVAL for an unknown key or a value out of range. */
@@ -111,11 +114,11 @@ enum {
   PR_KERNEL_BATCH_F64 = 2,  /* one float64 update of pr_pull_batch (all active columns) */
   PR_KERNEL_BATCH_F32 = 3,  /* one float32 update of pr_pull_batch */
   PR_KERNEL_MULTI = 4,      /* one whole pr_pull_multi launch (all rounds of all graphs) */
-  /* pr_pull_batch updates again, split by the row width the update ran on: C columns per lane,
-   * rows of 4*C values (C = 1..4, kind = ..._C1 + C - 1) */
-  PR_KERNEL_BATCH_F64_C1 = 8,
-  PR_KERNEL_BATCH_F32_C1 = 12,
-  PR_KERNEL_KINDS = 16
+  /* pr_pull_batch updates again, split by the row width (values per vertex) the update ran on:
+   * widths 1, 2, 4, 8, 12, 16 are kinds ..._W1 + 0 .. 5 */
+  PR_KERNEL_BATCH_F64_W1 = 8,
+  PR_KERNEL_BATCH_F32_W1 = 14,
+  PR_KERNEL_KINDS = 20
 };
 
 /* With "timing" on: number of timed launches of `kind` that did work (launches that found the

@@ -19,7 +19,13 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
 PR_FP64, PR_MIXED, PR_FP32 = 0, 1, 2
 PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32, PR_KERNEL_MULTI = 0, 1, 2, 3, 4
-PR_KERNEL_BATCH_F64_C1, PR_KERNEL_BATCH_F32_C1, PR_KERNEL_KINDS = 8, 12, 16
+PR_KERNEL_BATCH_F64_W1, PR_KERNEL_BATCH_F32_W1, PR_KERNEL_KINDS = 8, 14, 20
+BATCH_ROW_WIDTHS = (1, 2, 4, 8, 12, 16)
+
+
+def batch_kind(fp32: bool, width: int) -> int:
+    """Stats kind of pr_pull_batch updates that ran on rows of `width` values."""
+    return (PR_KERNEL_BATCH_F32_W1 if fp32 else PR_KERNEL_BATCH_F64_W1) + BATCH_ROW_WIDTHS.index(width)
 MAX_COLS = 16
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EGRAPH = 0, 1, -1, -2, -3, -4
 STATUS_NAMES = {0: "PR_OK", 1: "PR_NOT_CONVERGED", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE",

@@ -107,6 +107,7 @@ struct pr_ctx {
   std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;  // signature -> (mid_deg, grid)
   std::string tune_file;
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
+  int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
   double stat_ms[PR_KERNEL_KINDS] = {};
@@ -382,17 +383,23 @@ struct BatchLayout {
   size_t total;
 };
 
-// Columns per lane: rows of 4C values.  For float32 a 64-byte row (C = 4) is preferred over a
-// 48-byte one once K > 8: a row fetch then touches exactly one 64-byte line.
-int batch_cols_per_lane(int K, bool fp32) {
-  if (fp32 && K > 8) return 4;
-  return (K + 3) / 4;
+// Row width (values per vertex) of the batch state for K columns: 1 or 2 (narrow rows, one lane
+// per row fetch), else 4, 8, 12 or 16.  For float32 a 64-byte row is preferred over a 48-byte one
+// once K > 8: a row fetch then touches exactly one 64-byte line.
+int batch_row_width(int K, bool fp32, bool narrow) {
+  if (narrow && K <= 2) return K < 1 ? 1 : K;
+  if (fp32 && K > 8) return 16;
+  return 4 * ((K + 3) / 4);
 }
+
+// Index of a row width among the per-width stats kinds (widths 1, 2, 4, 8, 12, 16).
+static int width_index(int kp) { return kp == 1 ? 0 : kp == 2 ? 1 : kp / 4 + 1; }
 
 BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t precision, bool with_prep) {
   Carver c(ws);
   BatchLayout L{};
-  const int64_t kp32 = 4 * batch_cols_per_lane(K, true), kp64 = 4 * batch_cols_per_lane(K, false);
+  // sized for the widest layout of K columns (narrow rows only ever take less)
+  const int64_t kp32 = batch_row_width(K, true, false), kp64 = batch_row_width(K, false, false);
   L.st = (BatchState *)c.take(sizeof(BatchState));
   L.cols = (BatchCols *)c.take(sizeof(BatchCols));
   L.bpart = (double *)c.take(sizeof(double) * 4 * kMaxCols * (size_t)kMaxGrid);
@@ -409,23 +416,23 @@ BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t preci
   return L;
 }
 
-ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int C, unsigned grid, const BatchParams &p, void *b0, void *b1) {
+ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int kp, unsigned grid, const BatchParams &p, void *b0, void *b1) {
   ChunkSpec c;
   c.kind = fp32 ? PR_KERNEL_BATCH_F32 : PR_KERNEL_BATCH_F64;
-  c.sub_kind = (fp32 ? PR_KERNEL_BATCH_F32_C1 : PR_KERNEL_BATCH_F64_C1) + C - 1;
+  c.sub_kind = (fp32 ? PR_KERNEL_BATCH_F32_W1 : PR_KERNEL_BATCH_F64_W1) + width_index(kp);
   c.count = (int)ctx->chunk;
   BatchParams q = p;
   q.y_in = b0;
   q.y_out = b1;
-  const int64_t meta[2] = {grid, C};
+  const int64_t meta[2] = {grid, kp};
   c.key.resize(sizeof q + sizeof meta);
   memcpy(c.key.data(), &q, sizeof q);
   memcpy(c.key.data() + sizeof q, meta, sizeof meta);
-  c.launch = [fp32, C, grid, p, b0, b1](hipStream_t s, int k) {
+  c.launch = [fp32, kp, grid, p, b0, b1](hipStream_t s, int k) {
     BatchParams r = p;
     r.y_in = (k & 1) ? b1 : b0;
     r.y_out = (k & 1) ? b0 : b1;
-    return launch_batch_update(s, fp32, C, grid, r);
+    return launch_batch_update(s, fp32, kp, grid, r);
   };
   return c;
 }
@@ -577,6 +584,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->compact = value;
+  } else if (!strcmp(key, "narrow")) {
+    if (value != 0 && value != 1) {
+      set_error("narrow must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->narrow = value;
   } else if (!strcmp(key, "timing")) {
     if (value != 0 && value != 1) {
       set_error("timing must be 0 or 1");
@@ -860,8 +873,8 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   p.cols = L.cols;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
-  auto grid_of = [&](bool fp32, int C) {
-    const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, C);
+  auto grid_of = [&](bool fp32, int kpw) {
+    const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, kpw);
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, res, kMaxGrid}));
   };
 
@@ -907,23 +920,24 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
 
   const bool mixed = precision == PR_MIXED;
   const bool fp32 = mixed;  // first phase arithmetic
-  int C = batch_cols_per_lane(Kc, fp32), kp = 4 * C;
+  const bool narrow = ctx->narrow != 0;
+  int kp = batch_row_width(Kc, fp32, narrow);
   void *b0 = fp32 ? (void *)L.y32[0] : (void *)L.y64[0];
   void *b1 = fp32 ? (void *)L.y32[1] : (void *)L.y64[1];
-  const int C64 = batch_cols_per_lane(K, false), kp64 = 4 * C64;
+  const int kp64 = batch_row_width(K, false, narrow);
 
   rc = write_cols(Kc, orig, nullptr, false, nullptr);
   if (rc != PR_OK) return rc;
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(BatchState) / 4, 0u));
   p.K = Kc;
   p.phase = mixed ? 1 : 0;
-  p.grid = (int32_t)grid_of(fp32, C);
+  p.grid = (int32_t)grid_of(fp32, kp);
   PR_HIP(launch_batch_init(s, fp32, outdeg, (int32_t)N, Kc, kp, b0, L.bpart, kMaxGrid, p, p.phase));
 
   // ---- first phase, with compaction of the active columns into narrower rows
   int before = 0;
   for (int rounds = 0;; ++rounds) {
-    ChunkSpec cs = batch_chunk(ctx, fp32, C, (unsigned)p.grid, p, b0, b1);
+    ChunkSpec cs = batch_chunk(ctx, fp32, kp, (unsigned)p.grid, p, b0, b1);
     cs.count = (int)ctx->batch_chunk;
     const std::vector<hipEvent_t> *ev = nullptr;
     rc = run_chunk(ctx, s, cs, &ev);
@@ -946,8 +960,8 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
       leaving[i] = !hs.col[i].active;
       if (hs.col[i].active) act[nact++] = i;
     }
-    const int C2 = batch_cols_per_lane(nact, fp32);
-    if (ctx->compact == 0 || nact == Kc || 4 * C2 >= kp) continue;
+    const int kp2 = batch_row_width(nact, fp32, narrow);
+    if (ctx->compact == 0 || nact == Kc || kp2 >= kp) continue;
     // (a) columns leaving the layout: float32 -> their float64 columns (mixed), or final ranks
     if (mixed) {
       int map[kMaxCols];
@@ -969,7 +983,7 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     for (int i = 0; i < nact; ++i) norig[i] = orig[act[i]];
     rc = write_cols(nact, norig, act, false, nullptr);
     if (rc != PR_OK) return rc;
-    PR_HIP(launch_batch_compact(s, fp32, cur, kp, oth, 4 * C2, (int32_t)N, nact, L.cols));
+    PR_HIP(launch_batch_compact(s, fp32, cur, kp, oth, kp2, (int32_t)N, nact, L.cols));
     // (c) the slot states follow their columns; the repacked buffer becomes buffer 0
     BatchState ns = hs;
     for (int i = 0; i < kMaxCols; ++i) {
@@ -986,12 +1000,11 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     PR_HIP(hipStreamSynchronize(s));
     Kc = nact;
     for (int i = 0; i < nact; ++i) orig[i] = norig[i];
-    C = C2;
-    kp = 4 * C2;
+    kp = kp2;
     b0 = oth;
     b1 = cur;
     p.K = Kc;
-    p.grid = (int32_t)grid_of(fp32, C);
+    p.grid = (int32_t)grid_of(fp32, kp);
     before = 0;
     hs.head.phase_iter = 0;
     PR_HIP(launch_fill_u32(s, (uint32_t *)&L.st->head.phase_iter, 1, 0u));
@@ -1025,9 +1038,9 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     PR_HIP(launch_batch_rearm(s, L.st, K));
     p.K = K;
     p.phase = 2;
-    p.grid = (int32_t)grid_of(false, C64);
+    p.grid = (int32_t)grid_of(false, kp64);
     int fbuf = 0;
-    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, C64, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
+    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, kp64, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
                         max_iter, &fbuf);
     if (rc != PR_OK) return rc;
     PR_HIP(launch_batch_output(s, false, outdeg, L.y64[0], L.y64[1], kp64, (int32_t)N, K, p));

@@ -54,9 +54,9 @@ struct BatchParams {
   int32_t nhubs;
   int32_t phase;
   const int4 *hubs;
-  double *bpart;   // [grid][Kp][4]
-  double *hpart;   // [slots][Kp]
-  double *hacc;    // [hub blocks][Kp][4]: the hub rows' error and dangling partials
+  double *bpart;   // [grid][KP][4]
+  double *hpart;   // [slots][KP]
+  double *hacc;    // [hub blocks][KP][4]: the hub rows' error and dangling partials
   BatchState *st;
   const BatchCols *cols;
 };
@@ -108,8 +108,9 @@ __device__ __forceinline__ void batch_finalize_column(const BatchParams &p, int 
 constexpr int kHubsPerBlock = kBlock / 16;
 __host__ __device__ inline int64_t hub_blocks(int64_t nhubs) { return (nhubs + kHubsPerBlock - 1) / kHubsPerBlock; }
 
-hipError_t launch_batch_update(hipStream_t s, bool fp32, int C, unsigned grid, const BatchParams &p);
-int batch_blocks_per_cu(bool fp32, int C);
+// kp: row width, 1, 2, 4, 8, 12 or 16 values
+hipError_t launch_batch_update(hipStream_t s, bool fp32, int kp, unsigned grid, const BatchParams &p);
+int batch_blocks_per_cu(bool fp32, int kp);
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase);
 hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,

@@ -1,14 +1,15 @@
 // batch.hip -- K rank columns of one graph in one pass over its edges (paper, section 2
 // update, run for several damping factors / tolerances / error functions at once).
 //
-// State: Y[N][Kp] in the phase's type VT (Kp = 4*C, C = columns per lane, at most 16 columns),
-// row-major, so one in-edge u -> v costs one contiguous Kp*sizeof(VT)-byte row fetch that
-// serves every column: y[u][k] = r_k[u]/d_u (or r_k[u] for a dangling u), as in pull.hip.
-// A quad of four lanes owns one row fetch; lane (l & 3) handles columns (l & 3)*C .. +C-1.
-//   tiles of short rows (partition B: fewer than kSpanB entries): every quad fetches the rows
-//   of kPerQ entries into LDS, then one quad sums each row of in-degree <= kMidDeg in ascending
-//   entry order and one wave each longer row (entry j on quad j % 16, xor reduction);
-//   long-row segments: one block per segment, reduction across quads and waves; hubs leave
+// State: Y[N][KP] in the phase's type VT (row width KP = 1, 2, 4, 8, 12 or 16 values, at most
+// 16 columns), row-major, so one in-edge u -> v costs one contiguous KP*sizeof(VT)-byte row fetch
+// that serves every column: y[u][k] = r_k[u]/d_u (or r_k[u] for a dangling u), as in pull.hip.
+// A group of G = min(KP, 4) lanes owns one row fetch; lane (l % G) handles columns
+// (l % G)*C .. +C-1, C = KP/G.
+//   tiles of short rows (partition B: fewer than kSpanB entries): every group fetches the rows
+//   of kPerQ entries into LDS, then one group sums each row of in-degree <= kMidDeg in ascending
+//   entry order and one wave each longer row (entry j on group j % (64/G), xor reduction);
+//   long-row segments: one block per segment, reduction across groups and waves; hubs leave
 //   per-column segment partials for k_batch_finish.
 // Every column has its own c0, alpha, tau, norm, iteration count and stop decision; a column
 // that stops is masked (no writes) and keeps its last iterate in the buffer given by its own
@@ -19,23 +20,29 @@
 
 namespace prpull {
 
-template <typename T>
-__device__ __forceinline__ T xor_sum_quads(T v) {
-  // sum over the 16 quads of a wave; lanes with equal (lane & 3) end with equal bits
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+// Sum (max) over the 64/G groups of G lanes in a wave; lanes with equal (lane % G) end with
+// equal bits.
+template <int G, typename T>
+__device__ __forceinline__ T xor_sum_groups(T v) {
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__device__ __forceinline__ double xor_max_quads(double v) {
-  v = fmax(v, __shfl_xor(v, 4, 64));
-  v = fmax(v, __shfl_xor(v, 8, 64));
-  v = fmax(v, __shfl_xor(v, 16, 64));
-  v = fmax(v, __shfl_xor(v, 32, 64));
+template <int G>
+__device__ __forceinline__ double xor_max_groups(double v) {
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+
+// Lanes per row fetch and columns per lane of a row width.
+template <int KP>
+struct RowShape {
+  static_assert(KP == 1 || KP == 2 || KP == 4 || KP == 8 || KP == 12 || KP == 16, "row width");
+  static constexpr int G = KP < 4 ? KP : 4;
+  static constexpr int C = KP / G;
+};
 
 template <typename VT, int C>
 struct Row {
@@ -88,12 +95,13 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
   }
 }
 
-template <typename VT, int C>
-__global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k_batch_update(BatchParams p) {
-  constexpr int KP = 4 * C;
-  constexpr int kQuads = kBlock / 4;             // 64 quads per block
-  constexpr int kPerQ = kSpanB / kQuads;         // entries gathered per quad per tile (8)
-  constexpr int kRowsQ = kRowsB / kQuads;        // rows owned per quad per tile (2)
+template <typename VT, int KP>
+__global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && KP == 16) ? 4 : 1) void k_batch_update(BatchParams p) {
+  constexpr int G = RowShape<KP>::G, C = RowShape<KP>::C;
+  constexpr int kQuads = kBlock / G;                        // groups per block (64, 128, 256)
+  constexpr int kGW = 64 / G;                               // groups per wave
+  constexpr int kPerQ = kSpanB / kQuads;                    // entries gathered per group per tile (8, 4, 2)
+  constexpr int kRowsQ = (kRowsB + kQuads - 1) / kQuads;    // rows owned per group per tile (2, 1, 1)
   __shared__ VT vals[kSpanB * KP];
   __shared__ double sred[kWaves][KP];
   __shared__ double sacc[kWaves][KP][4];
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
   const BatchState *st = p.st;
   if (st->head.stop) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int qp = lane & 3, quad = t >> 2;  // quad 0..63 in the block
+  const int qp = lane % G, quad = t / G;  // lane within its group, group in the block
   const int col0 = qp * C;
   if (t < KP) {
     sc0[t] = st->col[t].c0;
@@ -196,19 +204,19 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
           VT s[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) s[c] = (VT)0;
-          for (int32_t j = wa + (lane >> 2); j < wb; j += 16) {
+          for (int32_t j = wa + lane / G; j < wb; j += kGW) {
 #pragma unroll
             for (int c = 0; c < C; ++c) s[c] += vals[j * KP + col0 + c];
           }
           double sd[C];
 #pragma unroll
-          for (int c = 0; c < C; ++c) sd[c] = (double)xor_sum_quads(s[c]);
-          if (lane < 4) batch_epilogue<VT, C>(wv, sd, wd, yin, yout, KP, col0, c0, alpha, act, a);
+          for (int c = 0; c < C; ++c) sd[c] = (double)xor_sum_groups<G>(s[c]);
+          if (lane < G) batch_epilogue<VT, C>(wv, sd, wd, yin, yout, KP, col0, c0, alpha, act, a);
         }
       }
       __syncthreads();
     } else {
-      // ---- one segment [e0, e1) of a long row: quads stride the entries, kPerQ in flight
+      // ---- one segment [e0, e1) of a long row: groups stride the entries, kPerQ in flight
       const int32_t v = d.x, slot = d.w;
       VT s[C];
 #pragma unroll
@@ -238,14 +246,14 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
       }
       double tot[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) tot[c] = xor_sum_quads((double)s[c]);
+      for (int c = 0; c < C; ++c) tot[c] = xor_sum_groups<G>((double)s[c]);
       __syncthreads();
-      if (lane < 4) {
+      if (lane < G) {
 #pragma unroll
         for (int c = 0; c < C; ++c) sred[wave][col0 + c] = tot[c];
       }
       __syncthreads();
-      if (t < 4) {
+      if (t < G) {
         double segd[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -266,15 +274,15 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
   }
   __syncthreads();
 
-  // ---- block partials per column: lanes with equal qp reduce across quads and waves
+  // ---- block partials per column: lanes with equal qp reduce across groups and waves
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    a[c].l1 = xor_sum_quads(a[c].l1);
-    a[c].sq = xor_sum_quads(a[c].sq);
-    a[c].mx = xor_max_quads(a[c].mx);
-    a[c].dang = xor_sum_quads(a[c].dang);
+    a[c].l1 = xor_sum_groups<G>(a[c].l1);
+    a[c].sq = xor_sum_groups<G>(a[c].sq);
+    a[c].mx = xor_max_groups<G>(a[c].mx);
+    a[c].dang = xor_sum_groups<G>(a[c].dang);
   }
-  if (lane < 4) {
+  if (lane < G) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       sacc[wave][col0 + c][0] = a[c].l1;
@@ -296,9 +304,8 @@ __global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && C == 4) ? 4 : 1) void k
 // Hub rows: lane t of workgroup b finishes column t % 16 of hub row 16*b + t/16 (its segment
 // sums in segment order, then the epilogue); the workgroup's per-column partials are combined over
 // its 16 rows in row order and stored to hacc[b].
-template <typename VT, int C>
+template <typename VT, int KP>
 __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
-  constexpr int KP = 4 * C;
   __shared__ double sacc[kHubsPerBlock][16][4];
   const BatchState *st = p.st;
   if (st->head.stop) return;
@@ -336,9 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
 
 // One block of kFinBlock lanes: lane t works on column t % 16 (columns >= Kp idle) and adds the
 // partials of the update workgroups, then those of the hub workgroups, each in block order.
-template <typename VT, int C>
+template <typename VT, int KP>
 __global__ __launch_bounds__(kFinBlock) void k_batch_finish(BatchParams p) {
-  constexpr int KP = 4 * C;
   constexpr int kGroups = kFinBlock / 16;
   __shared__ double sacc[kGroups][16][4];
   BatchState *st = p.st;
@@ -584,53 +590,47 @@ static unsigned out_grid(int64_t N) {
   return (unsigned)(tiles < 1 ? 1 : tiles > 4096 ? 4096 : tiles);
 }
 
+template <typename VT, int KP>
+static void batch_update_w(hipStream_t s, unsigned grid, const BatchParams &p) {
+  hipLaunchKernelGGL((k_batch_update<VT, KP>), dim3(grid), dim3(kBlock), 0, s, p);
+  if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, KP>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL((k_batch_finish<VT, KP>), dim3(1), dim3(kFinBlock), 0, s, p);
+}
+
 template <typename VT>
-static hipError_t batch_update_c(hipStream_t s, int C, unsigned grid, const BatchParams &p) {
-  switch (C) {
-    case 1:
-      hipLaunchKernelGGL((k_batch_update<VT, 1>), dim3(grid), dim3(kBlock), 0, s, p);
-      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 1>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
-      hipLaunchKernelGGL((k_batch_finish<VT, 1>), dim3(1), dim3(kFinBlock), 0, s, p);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_batch_update<VT, 2>), dim3(grid), dim3(kBlock), 0, s, p);
-      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 2>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
-      hipLaunchKernelGGL((k_batch_finish<VT, 2>), dim3(1), dim3(kFinBlock), 0, s, p);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_batch_update<VT, 3>), dim3(grid), dim3(kBlock), 0, s, p);
-      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 3>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
-      hipLaunchKernelGGL((k_batch_finish<VT, 3>), dim3(1), dim3(kFinBlock), 0, s, p);
-      break;
-    default:
-      hipLaunchKernelGGL((k_batch_update<VT, 4>), dim3(grid), dim3(kBlock), 0, s, p);
-      if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, 4>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
-      hipLaunchKernelGGL((k_batch_finish<VT, 4>), dim3(1), dim3(kFinBlock), 0, s, p);
-      break;
+static hipError_t batch_update_t(hipStream_t s, int kp, unsigned grid, const BatchParams &p) {
+  switch (kp) {
+    case 1: batch_update_w<VT, 1>(s, grid, p); break;
+    case 2: batch_update_w<VT, 2>(s, grid, p); break;
+    case 4: batch_update_w<VT, 4>(s, grid, p); break;
+    case 8: batch_update_w<VT, 8>(s, grid, p); break;
+    case 12: batch_update_w<VT, 12>(s, grid, p); break;
+    case 16: batch_update_w<VT, 16>(s, grid, p); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_batch_update(hipStream_t s, bool fp32, int C, unsigned grid, const BatchParams &p) {
-  return fp32 ? batch_update_c<float>(s, C, grid, p) : batch_update_c<double>(s, C, grid, p);
+hipError_t launch_batch_update(hipStream_t s, bool fp32, int kp, unsigned grid, const BatchParams &p) {
+  return fp32 ? batch_update_t<float>(s, kp, grid, p) : batch_update_t<double>(s, kp, grid, p);
 }
 
-int batch_blocks_per_cu(bool fp32, int C) {
+template <typename VT>
+static int blocks_per_cu_t(int kp) {
   int n = 0;
   hipError_t e;
-  if (fp32) {
-    e = C == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 1>, kBlock, 0)
-      : C == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 2>, kBlock, 0)
-      : C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 3>, kBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<float, 4>, kBlock, 0);
-  } else {
-    e = C == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 1>, kBlock, 0)
-      : C == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 2>, kBlock, 0)
-      : C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 3>, kBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 4>, kBlock, 0);
+  switch (kp) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 1>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 2>, kBlock, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 4>, kBlock, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 8>, kBlock, 0); break;
+    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 12>, kBlock, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<VT, 16>, kBlock, 0); break;
   }
   return e == hipSuccess && n > 0 ? n : 1;
 }
+
+int batch_blocks_per_cu(bool fp32, int kp) { return fp32 ? blocks_per_cu_t<float>(kp) : blocks_per_cu_t<double>(kp); }
 
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase) {

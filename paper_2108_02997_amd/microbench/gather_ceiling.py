@@ -86,15 +86,15 @@ def main():
         ctx.set_option("timing", 0)
         n, ms = ctx.stats(kind)
         kernels.append({"kernel": name, "us": round(1e3 * ms / n, 1)})
-    for K, C in ((4, 1), (8, 2), (11, 4)):
+    for K, W in ((1, 1), (2, 2), (4, 4), (8, 8), (11, 16)):
         probs = [dict(alpha=0.85, tau=1e-30, norm=3, max_iter=6)] * K
         pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
         ctx.reset_stats()
         ctx.set_option("timing", 1)
         pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
         ctx.set_option("timing", 0)
-        n, ms = ctx.stats(pr._lib.PR_KERNEL_BATCH_F32_C1 + C - 1)
-        kernels.append({"kernel": "k_batch_update<float,%d> (%d columns, %d-byte rows)" % (C, K, 16 * C),
+        n, ms = ctx.stats(pr._lib.batch_kind(True, W))
+        kernels.append({"kernel": "k_batch_update<float,%d> (%d columns, %d-byte rows)" % (W, K, 4 * W),
                         "us": round(1e3 * ms / n, 1)})
     ctx.close()
     print(json.dumps({"graph": "R-MAT scale %d seed %d" % (args.scale, args.seed), "N": N, "E": E,

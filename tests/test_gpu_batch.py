@@ -100,7 +100,8 @@ def test_per_column_starts(pr, ctx):
         check_column(r, g, p, init=s0)
 
 
-def test_hubs_in_batch(pr, ctx):
+@pytest.mark.parametrize("K", [1, 2, 7])
+def test_hubs_in_batch(pr, ctx, K):
     rng = np.random.default_rng(9)
     N = 40000
     src, dst = [], []
@@ -111,9 +112,13 @@ def test_hubs_in_batch(pr, ctx):
     dst.extend(rng.integers(0, N, 80000).tolist())
     g = gg.from_edges(N, src, dst)
     dg = pr.DeviceGraph.from_host(g)
-    probs = sweep_problems(tau=1e-11, norm=1)[:7]
+    probs = sweep_problems(tau=1e-11, norm=1)[:K]
     for r, p in zip(pr.pull_batch(ctx, dg, probs), probs):
         check_column(r, g, p)
+    for r, p in zip(pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED), probs):
+        ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"])
+        d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert r["converged"] and d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
 
 
 def test_batch_repeatable(pr, ctx):
@@ -170,15 +175,18 @@ def test_compaction_changes_nothing(pr, ctx, precision):
     g = gg.rmat(14, seed=21)
     dg = pr.DeviceGraph.from_host(g)
     probs = sweep_problems(tau=1e-10, norm=3)
+    # rows of one or two values (one lane per row fetch) sum in another order: kept out here
     out = {}
     try:
         ctx.set_option("grid", 300)
+        ctx.set_option("narrow", 0)
         for compact in (0, 1):
             ctx.set_option("compact", compact)
             out[compact] = pr.pull_batch(ctx, dg, probs, precision=precision)
             out[compact] = [(r["iterations"], r["fp32_iters"], r["ranks"].clone()) for r in out[compact]]
     finally:
         ctx.set_option("compact", 1)
+        ctx.set_option("narrow", 1)
         ctx.set_option("grid", 0)
     for (i0, f0, r0), (i1, f1, r1) in zip(out[0], out[1]):
         assert i0 == i1 and f0 == f1
@@ -218,3 +226,38 @@ def test_batch_on_tiny_graphs(pr, ctx, make, precision):
             assert r["err"][p["norm"] - 1] < p["tau"] or not r["converged"]
             bound = p["alpha"] / (1 - p["alpha"]) * (r["err"][0] + ref["err"][0]) + 1e-13 if p["alpha"] < 1 else 1e-6
             assert d <= bound, (p, d)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_narrow_rows_against_oracle(pr, ctx, precision):
+    # one and two columns run on rows of one and two values, from the start (K = 1, 2) and after
+    # compaction of a sweep; every update is counted under the width it ran on
+    g = gg.rmat(14, seed=31)
+    dg = pr.DeviceGraph.from_host(g)
+    fp32 = precision == pr.PR_MIXED
+    sweeps = [sweep_problems(tau=1e-10, norm=3)[7:8], sweep_problems(tau=1e-10, norm=1)[8:10],
+              sweep_problems(tau=1e-10, norm=3)[:-1]]
+    for probs in sweeps:
+        ctx.reset_stats()
+        ctx.set_option("timing", 1)
+        try:
+            res = pr.pull_batch(ctx, dg, probs, precision=precision)
+        finally:
+            ctx.set_option("timing", 0)
+        for r, p in zip(res, probs):
+            if precision == pr.PR_FP64:
+                check_column(r, g, p)
+            else:
+                ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"])
+                d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
+                assert r["converged"] and d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
+        first = ctx.stats(pr._lib.PR_KERNEL_BATCH_F32 if fp32 else pr._lib.PR_KERNEL_BATCH_F64)[0]
+        by_width = {w: ctx.stats(pr._lib.batch_kind(fp32, w))[0] for w in pr._lib.BATCH_ROW_WIDTHS}
+        assert first > 0 and sum(by_width.values()) == first, by_width
+        K = len(probs)
+        if K <= 2:
+            # starts at width K; a column that stops leaves the other on width 1
+            assert by_width[K] > 0 and all(n == 0 for w, n in by_width.items() if w > K), by_width
+        else:
+            # the sweep ends with its slowest one or two columns
+            assert by_width[1] + by_width[2] > 0, by_width
