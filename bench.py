@@ -15,7 +15,10 @@ Reported:
   sweep            per-column iterations, the same sweep as eleven sequential float64 solves
                    (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
   roofline         the dominant kernel's algorithmic bytes per launch over its average launch
-                   duration, timed with HIP events on the solve stream inside the timed steps
+                   duration, timed with HIP events on the solve stream inside the timed steps;
+                   beside it (after the timed steps) the bare gather of the same rows over the
+                   same index array (microbench/gather_ceiling.hip), and the kernel's time as a
+                   fraction of that bare time
   plain_fp64_gather  the same for the single-vector float64 update of the sequential solves
   cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
 
@@ -123,6 +126,27 @@ def roofline(kernel, alg_bytes, avg_s, launches, traffic):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": round(alg_bytes), "avg_launch_us": round(avg_s * 1e6, 2),
             "launches_timed": launches}
+
+
+def bare_gather_us(dg, row_bytes):
+    """Time of the bare gather of one `row_bytes` row per in-edge of `dg` (index stream plus row
+    fetches, nothing else; microbench/gather_ceiling.hip), in us; None when not measurable."""
+    try:
+        from paper_2108_02997_amd.microbench import gather_ceiling as gc
+        if row_bytes not in gc.ROW_KINDS:
+            return None
+        return 1e3 * gc.bare_gather_ms(gc.load(), dg.idx, dg.N, row_bytes)
+    except OSError as e:  # measurement library not built
+        log("bare gather not measured: %s" % e)
+        return None
+
+
+def add_ceiling(entry, dg, row_bytes):
+    """The kernel's launch time against the bare gather of its rows on the same graph."""
+    bare = bare_gather_us(dg, row_bytes)
+    if bare is not None:
+        entry["bare_gather_us"] = round(bare, 1)
+        entry["frac_of_bare_gather"] = round(bare / entry["avg_launch_us"], 4)
 
 
 def stream_gbps(torch):
@@ -270,6 +294,8 @@ def run_sweep(args, pr, gg, np, torch):
         line["plain_fp64_gather"] = roofline("k_update<double>", b64, ms64 / n64 * 1e-3, n64, traffic64)
         line["plain_fp64_gather"]["gteps_per_update"] = round(E / (ms64 / n64 * 1e-3) / 1e9, 2)
         line["plain_fp64_gather"]["frac_of_stream"] = round(line["plain_fp64_gather"]["achieved"] / copy_gbs, 4)
+        add_ceiling(line["plain_fp64_gather"], dg, 8)
+    add_ceiling(line["roofline"], dg, kp0 * s_bytes)
     line["stream_copy_GBps"] = round(copy_gbs, 1)
     line["sweep"] = {
         "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],

@@ -18,6 +18,44 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+# gc_run kinds by bytes fetched per entry (float32, float64, 16/32/64-byte rows)
+ROW_KINDS = {4: 1, 8: 0, 16: 3, 32: 4, 64: 5}
+
+
+def load():
+    """The measurement library (built by paper_2108_02997_amd/build.py)."""
+    lib = ctypes.CDLL(os.path.join(HERE, "libgather_ceiling.so"))
+    lib.gc_run.restype = ctypes.c_int
+    lib.gc_run.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_int, ctypes.c_void_p]
+    return lib
+
+
+def bare_gather_ms(lib, idx, N: int, row_bytes: int, reps: int = 5, grid: int = 4096) -> float:
+    """HIP-event average of the bare gather of one `row_bytes` row per entry of the device int32
+    index array `idx` (values < N) from a random table, on torch's current stream."""
+    import torch
+    kind = ROW_KINDS[row_bytes]
+    E = idx.numel()
+    table = torch.rand(N * max(row_bytes, 8) // 4, dtype=torch.float32, device=idx.device)
+    out = torch.empty(grid * 256, dtype=torch.float64, device=idx.device)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def once():
+        rc = lib.gc_run(kind, idx.data_ptr(), E, table.data_ptr(), out.data_ptr(), grid, stream)
+        if rc != 0:
+            raise RuntimeError("gc_run(%d) failed: %d" % (kind, rc))
+
+    once()
+    once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
