@@ -232,8 +232,10 @@ size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs);
  * all workgroups, then one workgroup per graph finishes its update); each graph stops on its own
  * rule, exactly as in pr_pull.  Graphs prepared beforehand (prep != NULL) use their tiles; the
  * tile window / lane-per-row threshold comes from the context ("mid_deg", or the autotuner).
- * probs and results are host arrays of G entries.  Returns PR_OK when every graph converged,
- * PR_NOT_CONVERGED otherwise (see results[g].converged), or a negative status. */
+ * probs and results are host arrays of G entries.  The rounds are separated by grid barriers
+ * whose waits have a time limit (about 5 s); a wait that passes it ends the launch with
+ * PR_EDEVICE.  Returns PR_OK when every graph converged, PR_NOT_CONVERGED otherwise (see
+ * results[g].converged), or a negative status. */
 int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
                   size_t workspace_bytes, pr_result *results);
 

@@ -1095,9 +1095,10 @@ int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, 
 }
 
 static size_t multi_layout(int32_t G, const pr_graph_problem *probs, void *ws, MultiGraph **graphs,
-                           MultiGraphState **states, int32_t **tile_base, double **part, double **hpart,
-                           double **y, void **preps) {
+                           MultiGraphState **states, int32_t **tile_base, double **part, GridBarrier **bar,
+                           double **hpart, double **y, void **preps) {
   Carver c(ws);
+  *bar = (GridBarrier *)c.take(sizeof(GridBarrier));
   *graphs = (MultiGraph *)c.take(sizeof(MultiGraph) * (size_t)G);
   *states = (MultiGraphState *)c.take(sizeof(MultiGraphState) * (size_t)G);
   *tile_base = (int32_t *)c.take(sizeof(int32_t) * (size_t)(G + 1));
@@ -1119,9 +1120,10 @@ size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs) {
   MultiGraphState *b;
   int32_t *c;
   double *d;
+  GridBarrier *e;
   std::vector<double *> hp(G), y(2 * G);
   std::vector<void *> pp(G);
-  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, hp.data(), y.data(), pp.data());
+  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, &e, hp.data(), y.data(), pp.data());
 }
 
 int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
@@ -1154,10 +1156,11 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   MultiGraphState *dstates;
   int32_t *dbase;
   double *dpart;
+  GridBarrier *dbar;
   std::vector<double *> hpart(G), ybuf(2 * G);
   std::vector<void *> ownprep(G);
-  const size_t need =
-      multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, hpart.data(), ybuf.data(), ownprep.data());
+  const size_t need = multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, &dbar, hpart.data(),
+                                   ybuf.data(), ownprep.data());
   if (workspace_bytes < need) {
     set_error("pr_pull_multi: workspace has %zu bytes, needs %zu", workspace_bytes, need);
     return PR_ENOMEM;
@@ -1226,6 +1229,7 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   p.states = dstates;
   p.tile_base = dbase;
   p.part = dpart;
+  p.bar = dbar;
   p.G = G;
   p.total_tiles = (int32_t)total_tiles;
   p.max_rounds = max_rounds;
@@ -1240,12 +1244,17 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     PR_HIP(hipEventCreate(&e1));
     PR_HIP(hipEventRecord(e0, s));
   }
+  PR_HIP(launch_fill_u32(s, (uint32_t *)dbar, sizeof(GridBarrier) / 4, 0u));
   PR_HIP(launch_multi(s, (unsigned)grid, p, 64));
   if (ctx->timing) PR_HIP(hipEventRecord(e1, s));
   std::vector<MultiGraphState> hs(G);
+  uint32_t timed_out = 0;
   PR_HIP(hipMemcpyAsync(ctx->hmulti, dstates, sizeof(MultiGraphState) * (size_t)G, hipMemcpyDeviceToHost, s));
+  PR_HIP(hipMemcpyAsync((char *)ctx->hmulti + sizeof(MultiGraphState) * (size_t)G, &dbar->timeout[0],
+                        sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PR_HIP(hipStreamSynchronize(s));
   memcpy(hs.data(), ctx->hmulti, sizeof(MultiGraphState) * (size_t)G);
+  memcpy(&timed_out, (char *)ctx->hmulti + sizeof(MultiGraphState) * (size_t)G, sizeof(uint32_t));
   if (ctx->timing) {
     float ms = 0.f;
     PR_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -1253,6 +1262,10 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     ctx->stat_launches[PR_KERNEL_MULTI] += 1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  }
+  if (timed_out) {
+    set_error("pr_pull_multi: a grid barrier wait of the launch passed its time limit");
+    return PR_EDEVICE;
   }
   int all = 1;
   for (int g = 0; g < G; ++g) {

@@ -35,11 +35,25 @@ struct MultiGraphState {
   int32_t pad;
 };
 
+// Grid barrier state of the cooperative launch (zeroed before it).  Counters only grow; the
+// words are 128 bytes apart.  XCC_ID, the workgroup's XCD, is a 4-bit hardware field.
+constexpr int kMaxXcd = 16;
+constexpr int kBarPad = 32;
+struct GridBarrier {
+  uint32_t members[kMaxXcd * kBarPad];  // workgroups of the launch on each XCD
+  uint32_t xcd[kMaxXcd * kBarPad];      // arrivals on each XCD, all barriers so far
+  uint32_t release[kMaxXcd * kBarPad];  // per XCD: the last barrier its workgroups may leave
+  uint32_t global[kBarPad];             // XCD arrivals, all barriers so far
+  uint32_t setup[kBarPad];              // workgroups counted into members
+  uint32_t timeout[kBarPad];            // nonzero: a wait passed its time limit (all workgroups quit)
+};
+
 struct MultiParams {
   const MultiGraph *graphs;
   MultiGraphState *states;
   const int32_t *tile_base;  // [G+1]: first global tile of each graph
   double *part;              // [grid][G][4] per-workgroup partials (also init scratch)
+  GridBarrier *bar;
   int32_t G;
   int32_t total_tiles;
   int32_t max_rounds;

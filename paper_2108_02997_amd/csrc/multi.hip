@@ -13,15 +13,94 @@
 //            partials of the workgroups that touched g in block order, then its teleport term,
 //            errors, stop decision and trace row;
 //   grid barrier; the loop ends when no graph is active.
-// A grid barrier costs one release/acquire per workgroup (an L2 write-back/invalidate on gfx950),
-// paid twice per round instead of once per tile.
-#include <hip/hip_cooperative_groups.h>
-
+//
+// Grid barrier.  A device-scope release is a write-back of the XCD's whole L2 on gfx950 and an
+// acquire an invalidate of it (and of the CU's L1); issued by every workgroup, as a generic grid
+// barrier does, they cost ~220 us per barrier at 2048 workgroups.  Here the release is paid once
+// per XCD: every lane waits until its stores have reached the XCD's L2, the last workgroup of
+// the XCD to arrive (per-XCD arrival count) writes that L2 back for all of them and arrives at
+// the global count; once every XCD has arrived it invalidates its L2 and releases the XCD's
+// workgroups, which each acquire (invalidate) before reading.  ~21 us at 2048 workgroups.  Every
+// wait has a time limit: past it the workgroup sets `timeout` and leaves, so does every other
+// one at its next wait, and the host reports the failure.
 #include "multi.h"
 
-namespace cg = cooperative_groups;
-
 namespace prpull {
+
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & (kMaxXcd - 1);
+}
+
+__device__ __forceinline__ uint32_t bar_load(uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t bar_add(uint32_t *p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p >= target; false after ~5 s of the 100 MHz wall clock or once another workgroup
+// has timed out.
+__device__ bool bar_wait(GridBarrier *b, uint32_t *p, uint32_t target) {
+  const uint64_t t0 = wall_clock64();
+  while (bar_load(p) < target) {
+    if (bar_load(&b->timeout[0]) || wall_clock64() - t0 > 500000000ull) {
+      __hip_atomic_store(&b->timeout[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+struct BarSlot {
+  uint32_t x;     // this workgroup's XCD
+  uint32_t nx;    // workgroups on it
+  uint32_t nxcd;  // XCDs with workgroups of the launch
+};
+
+// Count the launch's workgroups per XCD.  Block-uniform result; false on time-out.
+__device__ bool bar_setup(GridBarrier *b, BarSlot &slot) {
+  __shared__ uint32_t s_v[3];
+  int ok = 1;
+  if (threadIdx.x == 0) {
+    const uint32_t x = xcc_id();
+    bar_add(&b->members[x * kBarPad]);
+    bar_add(&b->setup[0]);
+    ok = bar_wait(b, &b->setup[0], gridDim.x);
+    uint32_t n = 0;
+    for (int i = 0; i < kMaxXcd; ++i) n += bar_load(&b->members[i * kBarPad]) > 0;
+    s_v[0] = x;
+    s_v[1] = bar_load(&b->members[x * kBarPad]);
+    s_v[2] = n;
+  }
+  if (__syncthreads_or(!ok)) return false;
+  slot = BarSlot{s_v[0], s_v[1], s_v[2]};
+  return true;
+}
+
+// Barrier number k (1, 2, ...) of the launch.  Block-uniform result; false on time-out.
+__device__ bool grid_barrier(GridBarrier *b, const BarSlot &slot, uint32_t k) {
+  __builtin_amdgcn_s_waitcnt(0);  // this lane's stores are in the XCD's L2
+  __syncthreads();
+  int ok = 1;
+  if (threadIdx.x == 0) {
+    if (bar_add(&b->xcd[slot.x * kBarPad]) + 1u == k * slot.nx) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the XCD's L2 to memory
+      bar_add(&b->global[0]);
+      ok = bar_wait(b, &b->global[0], k * slot.nxcd);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(&b->release[slot.x * kBarPad], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      ok = bar_wait(b, &b->release[slot.x * kBarPad], k);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  return !__syncthreads_or(!ok);
+}
 
 __device__ __forceinline__ void flush_acc(const MultiParams &p, int g, Acc &a, double *red) {
   const double l1 = block_sum_n<kBlock>(a.l1, red);
@@ -42,9 +121,11 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
   __shared__ double vals[kSpan];
   __shared__ double red[kFinBlock / 64];
   __shared__ int32_t s_act[kBlock], s_base[kBlock + 1];
-  cg::grid_group grid = cg::this_grid();
   const int t = threadIdx.x;
   const int32_t nblk = (int32_t)gridDim.x, blk = (int32_t)blockIdx.x;
+  BarSlot slot;
+  if (!bar_setup(p.bar, slot)) return;
+  uint32_t nbar = 0;
   for (int32_t round = 0; round < p.max_rounds; ++round) {
     // ---- phase 1: this workgroup's tiles of every active graph.  Global tile gi belongs to
     // workgroup gi % gridDim.x; the graphs' activity flags and first tiles are staged in LDS,
@@ -82,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
         flush_acc(p, g, a, red);
       }
     }
-    grid.sync();
+    if (!grid_barrier(p.bar, slot, ++nbar)) break;
 
     // ---- phase 2: one workgroup per graph
     for (int g = blockIdx.x; g < p.G; g += gridDim.x) {
@@ -140,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
       }
       __syncthreads();
     }
-    grid.sync();
+    if (!grid_barrier(p.bar, slot, ++nbar)) break;
     // every lane reads a strided share of the flags; the block ORs them
     int any = 0;
     for (int g = t; g < p.G; g += kBlock) any |= p.states[g].active;
