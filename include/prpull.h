@@ -99,6 +99,8 @@ const char *pr_version(void);
  *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
+ *   "barrier_ms": time limit of one grid-barrier wait of pr_pull_multi in milliseconds, 0..600000
+ *             (default 5000); a wait that passes it ends the launch with PR_EDEVICE
  *   "narrow": 1 (default) = one or two columns of pr_pull_batch run on rows of one or two values;
  *             0 = rows hold at least four values (the row layouts keep every column's sums in
  *             the same order, so with a pinned grid compaction then leaves results bitwise equal)
@@ -233,8 +235,8 @@ size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs);
  * rule, exactly as in pr_pull.  Graphs prepared beforehand (prep != NULL) use their tiles; the
  * tile window / lane-per-row threshold comes from the context ("mid_deg", or the autotuner).
  * probs and results are host arrays of G entries.  The rounds are separated by grid barriers
- * whose waits have a time limit (about 5 s); a wait that passes it ends the launch with
- * PR_EDEVICE.  Returns PR_OK when every graph converged, PR_NOT_CONVERGED otherwise (see
+ * whose waits have a time limit (option "barrier_ms"); a wait that passes it ends the launch
+ * with PR_EDEVICE.  Returns PR_OK when every graph converged, PR_NOT_CONVERGED otherwise (see
  * results[g].converged), or a negative status. */
 int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
                   size_t workspace_bytes, pr_result *results);

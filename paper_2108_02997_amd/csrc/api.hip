@@ -108,6 +108,7 @@ struct pr_ctx {
   std::string tune_file;
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
+  int64_t barrier_ms = 5000;  // time limit of a grid-barrier wait in pr_pull_multi
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
   double stat_ms[PR_KERNEL_KINDS] = {};
@@ -590,6 +591,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->narrow = value;
+  } else if (!strcmp(key, "barrier_ms")) {
+    if (value < 0 || value > 600000) {
+      set_error("barrier_ms must be in [0, 600000]");
+      return PR_EINVAL;
+    }
+    ctx->barrier_ms = value;
   } else if (!strcmp(key, "timing")) {
     if (value != 0 && value != 1) {
       set_error("timing must be 0 or 1");
@@ -1230,6 +1237,12 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   p.tile_base = dbase;
   p.part = dpart;
   p.bar = dbar;
+  {
+    int khz = 0;  // wall clock of the device (s_memrealtime), 100 MHz on this GPU family
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz < 1)
+      khz = 100000;
+    p.wait_ticks = (uint64_t)ctx->barrier_ms * (uint64_t)khz;
+  }
   p.G = G;
   p.total_tiles = (int32_t)total_tiles;
   p.max_rounds = max_rounds;

@@ -54,6 +54,7 @@ struct MultiParams {
   const int32_t *tile_base;  // [G+1]: first global tile of each graph
   double *part;              // [grid][G][4] per-workgroup partials (also init scratch)
   GridBarrier *bar;
+  uint64_t wait_ticks;       // time limit of a barrier wait, in wall-clock ticks
   int32_t G;
   int32_t total_tiles;
   int32_t max_rounds;

@@ -22,7 +22,8 @@
 // the global count; once every XCD has arrived it invalidates its L2 and releases the XCD's
 // workgroups, which each acquire (invalidate) before reading.  ~21 us at 2048 workgroups.  Every
 // wait has a time limit: past it the workgroup sets `timeout` and leaves, so does every other
-// one at its next wait, and the host reports the failure.
+// one at its next wait, and the host reports the failure.  The limit is the context's
+// "barrier_ms" (5 s by default).
 #include "multi.h"
 
 namespace prpull {
@@ -41,12 +42,12 @@ __device__ __forceinline__ uint32_t bar_add(uint32_t *p) {
   return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until *p >= target; false after ~5 s of the 100 MHz wall clock or once another workgroup
-// has timed out.
-__device__ bool bar_wait(GridBarrier *b, uint32_t *p, uint32_t target) {
+// Wait until *p >= target; false after `limit` wall-clock ticks or once another workgroup has
+// timed out.
+__device__ bool bar_wait(GridBarrier *b, uint32_t *p, uint32_t target, uint64_t limit) {
   const uint64_t t0 = wall_clock64();
   while (bar_load(p) < target) {
-    if (bar_load(&b->timeout[0]) || wall_clock64() - t0 > 500000000ull) {
+    if (bar_load(&b->timeout[0]) || wall_clock64() - t0 > limit) {
       __hip_atomic_store(&b->timeout[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -62,14 +63,14 @@ struct BarSlot {
 };
 
 // Count the launch's workgroups per XCD.  Block-uniform result; false on time-out.
-__device__ bool bar_setup(GridBarrier *b, BarSlot &slot) {
+__device__ bool bar_setup(GridBarrier *b, BarSlot &slot, uint64_t limit) {
   __shared__ uint32_t s_v[3];
   int ok = 1;
   if (threadIdx.x == 0) {
     const uint32_t x = xcc_id();
     bar_add(&b->members[x * kBarPad]);
     bar_add(&b->setup[0]);
-    ok = bar_wait(b, &b->setup[0], gridDim.x);
+    ok = bar_wait(b, &b->setup[0], gridDim.x, limit);
     uint32_t n = 0;
     for (int i = 0; i < kMaxXcd; ++i) n += bar_load(&b->members[i * kBarPad]) > 0;
     s_v[0] = x;
@@ -82,7 +83,7 @@ __device__ bool bar_setup(GridBarrier *b, BarSlot &slot) {
 }
 
 // Barrier number k (1, 2, ...) of the launch.  Block-uniform result; false on time-out.
-__device__ bool grid_barrier(GridBarrier *b, const BarSlot &slot, uint32_t k) {
+__device__ bool grid_barrier(GridBarrier *b, const BarSlot &slot, uint32_t k, uint64_t limit) {
   __builtin_amdgcn_s_waitcnt(0);  // this lane's stores are in the XCD's L2
   __syncthreads();
   int ok = 1;
@@ -90,11 +91,11 @@ __device__ bool grid_barrier(GridBarrier *b, const BarSlot &slot, uint32_t k) {
     if (bar_add(&b->xcd[slot.x * kBarPad]) + 1u == k * slot.nx) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the XCD's L2 to memory
       bar_add(&b->global[0]);
-      ok = bar_wait(b, &b->global[0], k * slot.nxcd);
+      ok = bar_wait(b, &b->global[0], k * slot.nxcd, limit);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&b->release[slot.x * kBarPad], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      ok = bar_wait(b, &b->release[slot.x * kBarPad], k);
+      ok = bar_wait(b, &b->release[slot.x * kBarPad], k, limit);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
   const int t = threadIdx.x;
   const int32_t nblk = (int32_t)gridDim.x, blk = (int32_t)blockIdx.x;
   BarSlot slot;
-  if (!bar_setup(p.bar, slot)) return;
+  if (!bar_setup(p.bar, slot, p.wait_ticks)) return;
   uint32_t nbar = 0;
   for (int32_t round = 0; round < p.max_rounds; ++round) {
     // ---- phase 1: this workgroup's tiles of every active graph.  Global tile gi belongs to
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
         flush_acc(p, g, a, red);
       }
     }
-    if (!grid_barrier(p.bar, slot, ++nbar)) break;
+    if (!grid_barrier(p.bar, slot, ++nbar, p.wait_ticks)) break;
 
     // ---- phase 2: one workgroup per graph
     for (int g = blockIdx.x; g < p.G; g += gridDim.x) {
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
       }
       __syncthreads();
     }
-    if (!grid_barrier(p.bar, slot, ++nbar)) break;
+    if (!grid_barrier(p.bar, slot, ++nbar, p.wait_ticks)) break;
     // every lane reads a strided share of the flags; the block ORs them
     int any = 0;
     for (int g = t; g < p.G; g += kBlock) any |= p.states[g].active;

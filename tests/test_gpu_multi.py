@@ -111,3 +111,25 @@ def test_tau_norm_stops_from_one_launch(pr, ctx):
                     col = ref["trace"][:, n]
                     k = min(got[i, n], want[i, n])
                     assert abs(got[i, n] - want[i, n]) == 1 and abs(col[k - 1] - tau) <= 1e-4 * tau, (tau, n)
+
+
+def test_barrier_time_limit_ends_the_launch(pr, ctx):
+    # With a zero wait limit every workgroup leaves at its first grid-barrier wait that is not
+    # already met, so the launch ends normally and the call reports PR_EDEVICE; the next solve
+    # (default limit) is unaffected.
+    specs = small_specs(8, 900)
+    hosts = [gg.make_spec_graph(s) for s in specs]
+    graphs = [pr.DeviceGraph.from_host(h) for h in hosts]
+    probs = [dict(alpha=s["alpha"], tau=s["tau"], norm=s["norm"], max_iter=500) for s in specs]
+    assert sum(h.E for h in hosts) > 100000  # many tiles, so the launch spans every XCD
+    try:
+        ctx.set_option("barrier_ms", 0)
+        with pytest.raises(pr.PrError) as ei:
+            pr.pull_multi(ctx, graphs, probs)
+        assert ei.value.status == pr._lib.PR_EDEVICE and "time limit" in str(ei.value)
+    finally:
+        ctx.set_option("barrier_ms", 5000)
+    with pytest.raises(pr.PrError):
+        ctx.set_option("barrier_ms", -1)
+    for r, h, p in zip(pr.pull_multi(ctx, graphs, probs), hosts, probs):
+        check_column(r, h, p)
