@@ -284,13 +284,14 @@ int pr_features(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
                 const double *r_target, float *target);
 
 /* y = MLP(feat) (device float32 [N]); act_save (device, bfloat16 bits [N][64]: the two hidden
- * layers after ReLU) is written for the backward pass unless NULL.  Async. */
+ * layers after ReLU, 8-byte aligned) is written for the backward pass unless NULL.  The hidden
+ * layers run on the matrix cores (float32 products, float32 accumulation).  Async. */
 int pr_mlp_forward(pr_ctx *ctx, void *stream, const float *W, const float *feat, int64_t N, float *y,
                    uint16_t *act_save);
 
 /* Gradient dW (device, 1281 floats) of the mean squared error mean_v (y_v - target_v)^2 from a
- * forward pass's y and act_save; loss (host) receives the error.  Block partials are reduced in
- * a fixed order (repeatable).  workspace: device, pr_mlp_backward_workspace_bytes(N).
+ * forward pass's y and act_save (8-byte aligned); loss (host) receives the error.  Block
+ * partials are reduced in a fixed order (repeatable).  workspace: device, pr_mlp_backward_workspace_bytes(N).
  * Synchronises the stream. */
 size_t pr_mlp_backward_workspace_bytes(int64_t N);
 int pr_mlp_backward(pr_ctx *ctx, void *stream, const float *W, const float *feat, const uint16_t *act_save,

@@ -1415,6 +1415,10 @@ int pr_mlp_forward(pr_ctx *ctx, void *stream, const float *W, const float *feat,
     set_error("pr_mlp_forward: N must be >= 1");
     return PR_EINVAL;
   }
+  if (((uintptr_t)act_save & 7) != 0) {
+    set_error("pr_mlp_forward: act_save must be 8-byte aligned");
+    return PR_EINVAL;
+  }
   DeviceGuard g(ctx->device);
   PR_HIP(launch_mlp_forward((hipStream_t)stream, W, feat, N, y, act_save));
   return PR_OK;
@@ -1436,6 +1440,10 @@ int pr_mlp_backward(pr_ctx *ctx, void *stream, const float *W, const float *feat
   }
   if (N < 1) {
     set_error("pr_mlp_backward: N must be >= 1");
+    return PR_EINVAL;
+  }
+  if (((uintptr_t)act_save & 7) != 0) {
+    set_error("pr_mlp_backward: act_save must be 8-byte aligned");
     return PR_EINVAL;
   }
   if (workspace_bytes < pr_mlp_backward_workspace_bytes(N)) {

@@ -16,7 +16,7 @@ namespace prpull {
 constexpr int kF = 5, kH = 32;
 constexpr int oW1 = 0, oB1 = oW1 + kH * kF, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH, oB3 = oW3 + kH;
 constexpr int kParams = oB3 + 1;  // 1281
-constexpr int kChunk = 128;       // vertices per backward step of a block
+constexpr int kChunk = 128;       // vertices per block step of forward and backward (a 32-vertex tile per wave)
 
 __device__ __forceinline__ float to_bf16_float(float x) {
   // round to nearest even on the upper 16 bits (inputs are finite)
@@ -141,170 +141,239 @@ __global__ __launch_bounds__(kBlock) void k_features_hubs(const int32_t *__restr
   if (threadIdx.x == 0) write_features(v, b - a, s, N, outdeg, r, alpha_t, feat, r_target, target);
 }
 
+// ------------------------------------------------------------------ dense layers on MFMA
+// The hidden layers are dense contractions over 32-vertex tiles, one tile per wave at a time, on
+// v_mfma_f32_32x32x2f32 (float32 in, float32 accumulate).  Its operand layout (one 32x32x2
+// block, lane l, h = l / 32): A[i][k] sits in lane i + 32k, B[k][j] in lane j + 32k, and item r
+// of the 16 accumulators of lane l is D[row(r, h)][l % 32] with row(r, h) = 8(r/4) + 4h + r%4.
+// A contraction over 32 values takes 16 steps; step s pairs the values row(s, 0) and row(s, 1),
+// so a 32 x 32 result held in the accumulator layout feeds the next contraction directly: lane l
+// of a "vertex column" tile holds vertex l%32 at hidden units row(r, h), which is the B operand of
+// a product with that tile transposed and, for the gradients, the K-major operand over vertices.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int mrow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Packs four bfloat16 values (already rounded) into 8 bytes, lowest unit first.
+__device__ __forceinline__ uint2 pack4_bf16(float a, float b, float c, float d) {
+  return make_uint2((uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16),
+                    (uint32_t)bf16_bits(c) | ((uint32_t)bf16_bits(d) << 16));
+}
+
 // ------------------------------------------------------------------ forward
+// Per tile: Z1^T = [W1 | b1] [X | 1]^T (3 steps, the bias as a sixth input), H1 = bf16(relu(Z1)),
+// Z2^T = W2 H1^T + b2 (16 steps), H2 = bf16(relu(Z2)), y = b3 + W3 . H2 (per lane over its 16
+// units, then the two halves).  act[v] = H1[v] | H2[v] as bfloat16 when kept for training.
 __global__ __launch_bounds__(kBlock) void k_mlp_forward(const float *__restrict__ W, const float *__restrict__ feat,
                                                         int64_t N, float *__restrict__ y, uint16_t *__restrict__ act) {
-  __shared__ float w[kParams];
-  __shared__ float sh1[kBlock][kH + 1];  // this lane's first hidden layer
-  for (int i = threadIdx.x; i < kParams; i += kBlock) w[i] = W[i];
-  __syncthreads();
-  float *h1 = sh1[threadIdx.x];
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
-    float f[kF];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, c = lane & 31;
+  float a1[3], a2[16], b2[16], w3[16];
 #pragma unroll
-    for (int i = 0; i < kF; ++i) f[i] = feat[v * kF + i];
-#pragma unroll 4
-    for (int j = 0; j < kH; ++j) {
-      float z = w[oB1 + j];
+  for (int s = 0; s < 3; ++s) {
+    const int f = 2 * s + h;  // input f of hidden unit c: weight, or the bias as input 5
+    a1[s] = f < kF ? W[oW1 + c * kF + f] : W[oB1 + c];
+  }
 #pragma unroll
-      for (int i = 0; i < kF; ++i) z = fmaf(w[oW1 + j * kF + i], f[i], z);
-      h1[j] = to_bf16_float(fmaxf(z, 0.0f));
+  for (int r = 0; r < 16; ++r) {
+    a2[r] = W[oW2 + c * kH + mrow(r, h)];  // A of step r: W2[c][row(r, h)]
+    b2[r] = W[oB2 + mrow(r, h)];
+    w3[r] = W[oW3 + mrow(r, h)];
+  }
+  const float b3 = W[oB3];
+  const int64_t ntiles = (N + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t v = tile * 32 + c;
+    const bool ok = v < N;
+    floatx16 z1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z1[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int f = 2 * s + h;
+      const float x = ok ? (f < kF ? feat[v * kF + f] : 1.0f) : 0.f;
+      z1 = mfma32(a1[s], x, z1);
     }
-    float z2[kH];
+    // lane l: vertex c, hidden units row(r, h)
+    float h1[16];
 #pragma unroll
-    for (int j = 0; j < kH; ++j) z2[j] = w[oB2 + j];
-#pragma unroll 1
-    for (int k = 0; k < kH; ++k) {
-      const float hk = h1[k];
+    for (int r = 0; r < 16; ++r) h1[r] = to_bf16_float(fmaxf(z1[r], 0.f));
+    floatx16 z2;
 #pragma unroll
-      for (int j = 0; j < kH; ++j) z2[j] = fmaf(w[oW2 + j * kH + k], hk, z2[j]);
+    for (int r = 0; r < 16; ++r) z2[r] = b2[r];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z2 = mfma32(a2[s], h1[s], z2);
+    float h2[16], p = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      h2[r] = to_bf16_float(fmaxf(z2[r], 0.f));
+      p = fmaf(w3[r], h2[r], p);
     }
-    float out = w[oB3];
+    const float out = b3 + (p + __shfl_xor(p, 32, 64));
+    if (ok) {
+      if (h == 0) y[v] = out;
+      if (act) {
+        uint2 *row = (uint2 *)(act + v * (2 * kH));
 #pragma unroll
-    for (int j = 0; j < kH; ++j) {
-      const float h2 = to_bf16_float(fmaxf(z2[j], 0.0f));
-      out = fmaf(w[oW3 + j], h2, out);
-      if (act) act[v * (2 * kH) + kH + j] = bf16_bits(h2);
-    }
-    y[v] = out;
-    if (act) {
-#pragma unroll 4
-      for (int j = 0; j < kH; ++j) act[v * (2 * kH) + j] = bf16_bits(h1[j]);
+        for (int q = 0; q < 4; ++q) {
+          row[2 * q + h] = pack4_bf16(h1[4 * q], h1[4 * q + 1], h1[4 * q + 2], h1[4 * q + 3]);
+          row[8 + 2 * q + h] = pack4_bf16(h2[4 * q], h2[4 * q + 1], h2[4 * q + 2], h2[4 * q + 3]);
+        }
+      }
     }
   }
 }
 
 // ------------------------------------------------------------------ backward (mean squared error)
-// Per block: chunks of kChunk vertices; lanes < kChunk compute one vertex's dL/dz terms into LDS,
-// then every lane accumulates the parameters it owns over the chunk in vertex order.  Block
-// partials are reduced in block order by k_mlp_grad_reduce.
-__global__ __launch_bounds__(kBlock, 2) void k_mlp_backward(const float *__restrict__ W, const float *__restrict__ feat,
+// Per tile, with dy_v = 2/n (y_v - t_v):
+//   vertex columns (lane: vertex c, units row(r, h)): dZ2 = [H2 > 0] dy W3;
+//   dZ1 = dZ2 W2 (16 steps) lands in unit columns (lane: unit c, vertices row(r, h)), masked by
+//   [H1 > 0] loaded in the same layout, beside H2 and dy of those vertices;
+//   dW2 += dZ2^T H1 and [dW1 | db1]^T += [X | 1]^T dZ1 (16 steps each, K over the tile's vertices);
+//   db2, dW3 per unit lane, db3 and the loss per vertex lane.
+// The four waves' sums are added in wave order into the block's partial row; k_mlp_grad_reduce
+// adds the blocks in block order.
+__global__ __launch_bounds__(kBlock) void k_mlp_backward(const float *__restrict__ W, const float *__restrict__ feat,
                                                          const uint16_t *__restrict__ act,
                                                          const float *__restrict__ y, const float *__restrict__ target,
                                                          int64_t N, double inv_n, float *__restrict__ part,
                                                          double *__restrict__ loss_part) {
-  __shared__ float w[kParams];
-  __shared__ float sh1[kChunk][kH + 1], sh2[kChunk][kH + 1], sdz1[kChunk][kH + 1], sdz2[kChunk][kH + 1];
-  __shared__ float sf[kChunk][kF], sdy[kChunk];
+  __shared__ float sg[kWaves][kParams];
   __shared__ double red[kWaves];
-  const int t = threadIdx.x;
-  for (int i = t; i < kParams; i += kBlock) w[i] = W[i];
-  float g2[4] = {0.f, 0.f, 0.f, 0.f};  // dW2 entries 4t .. 4t+3
-  float gx = 0.f;                       // lanes 0..159 dW1, 160..191 db1, 192..223 db2, 224..255 dW3
-  float gb3 = 0.f;                      // lane 0: db3
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, h = lane >> 5, c = lane & 31;
+  float w3v[16], bw2[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    w3v[r] = W[oW3 + mrow(r, h)];
+    bw2[r] = W[oW2 + mrow(r, h) * kH + c];  // B of step r: W2[row(r, h)][c]
+  }
+  const float w3c = W[oW3 + c];
+  const float two_n = (float)(2.0 * inv_n);
+  floatx16 g2, g1;  // dW2 rows row(r, h), column c; [dW1 | db1]^T rows (inputs) row(r, h), column c
+#pragma unroll
+  for (int r = 0; r < 16; ++r) g2[r] = g1[r] = 0.f;
+  float gb2 = 0.f, gw3 = 0.f, gb3 = 0.f;
   double loss = 0.0;
-  __syncthreads();
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < N; base += (int64_t)gridDim.x * kChunk) {
-    if (t < kChunk) {
-      const int64_t v = base + t;
-      if (v < N) {
-        const float d = y[v] - target[v];
+  const int64_t ntiles = (N + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t v0 = tile * 32, v = v0 + c;
+    const bool ok = v < N;
+    float dy = 0.f;
+    if (ok) {
+      const float d = y[v] - target[v];
+      dy = two_n * d;
+      if (h == 0) {
         loss += (double)d * (double)d;
-        const float dy = (float)(2.0 * inv_n) * d;
-        sdy[t] = dy;
-#pragma unroll
-        for (int i = 0; i < kF; ++i) sf[t][i] = feat[v * kF + i];
-#pragma unroll 4
-        for (int j = 0; j < kH; ++j) {
-          const float h1 = bf16_to_float(act[v * (2 * kH) + j]);
-          const float h2 = bf16_to_float(act[v * (2 * kH) + kH + j]);
-          sh1[t][j] = h1;
-          sh2[t][j] = h2;
-          sdz2[t][j] = h2 > 0.f ? dy * w[oW3 + j] : 0.f;
-        }
-#pragma unroll 1
-        for (int k = 0; k < kH; ++k) {
-          float s = 0.f;
-#pragma unroll
-          for (int j = 0; j < kH; ++j) s = fmaf(w[oW2 + j * kH + k], sdz2[t][j], s);
-          sdz1[t][k] = sh1[t][k] > 0.f ? s : 0.f;
-        }
-      } else {
-        sdy[t] = 0.f;
-#pragma unroll
-        for (int i = 0; i < kF; ++i) sf[t][i] = 0.f;
-#pragma unroll
-        for (int j = 0; j < kH; ++j) sh1[t][j] = sh2[t][j] = sdz1[t][j] = sdz2[t][j] = 0.f;
+        gb3 += dy;
       }
     }
-    __syncthreads();
+    // vertex columns: dZ2 of vertex c at units row(r, h)
+    float dz2v[16];
+    {
+      uint2 q4[4] = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
+      if (ok) {
+        const uint2 *row = (const uint2 *)(act + v * (2 * kH));
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = 4 * t + q, j = e / kH, k = e % kH;
-      float s = 0.f;
-#pragma unroll 4
-      for (int vv = 0; vv < kChunk; ++vv) s = fmaf(sdz2[vv][j], sh1[vv][k], s);
-      g2[q] += s;
+        for (int q = 0; q < 4; ++q) q4[q] = row[8 + 2 * q + h];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float e[4] = {bf16_to_float((uint16_t)(q4[q].x & 0xffffu)), bf16_to_float((uint16_t)(q4[q].x >> 16)),
+                            bf16_to_float((uint16_t)(q4[q].y & 0xffffu)), bf16_to_float((uint16_t)(q4[q].y >> 16))};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dz2v[4 * q + i] = e[i] > 0.f ? dy * w3v[4 * q + i] : 0.f;
+      }
     }
-    float s = 0.f;
-    if (t < kH * kF) {
-      const int j = t / kF, i = t % kF;
-      for (int vv = 0; vv < kChunk; ++vv) s = fmaf(sdz1[vv][j], sf[vv][i], s);
-    } else if (t < kH * kF + kH) {
-      for (int vv = 0; vv < kChunk; ++vv) s += sdz1[vv][t - kH * kF];
-    } else if (t < kH * kF + 2 * kH) {
-      for (int vv = 0; vv < kChunk; ++vv) s += sdz2[vv][t - kH * kF - kH];
-    } else if (t < kH * kF + 3 * kH) {
-      const int j = t - kH * kF - 2 * kH;
-      for (int vv = 0; vv < kChunk; ++vv) s = fmaf(sdy[vv], sh2[vv][j], s);
+    // unit columns: unit c of vertices row(r, h)
+    float h1u[16], dz2u[16], xu[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t u = v0 + mrow(r, h);
+      const bool uok = u < N;
+      const float dyu = __shfl(dy, mrow(r, h), 64);
+      const float h1 = uok ? bf16_to_float(act[u * (2 * kH) + c]) : 0.f;
+      const float h2 = uok ? bf16_to_float(act[u * (2 * kH) + kH + c]) : 0.f;
+      h1u[r] = h1;
+      dz2u[r] = h2 > 0.f ? dyu * w3c : 0.f;
+      gb2 += dz2u[r];
+      gw3 = fmaf(dyu, h2, gw3);
+      xu[r] = (uok && c <= kF) ? (c < kF ? feat[u * kF + c] : 1.0f) : 0.f;
     }
-    gx += s;
-    if (t == 0) {
-      float b3 = 0.f;
-      for (int vv = 0; vv < kChunk; ++vv) b3 += sdy[vv];
-      gb3 += b3;
+    floatx16 dz1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dz1[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) dz1 = mfma32(dz2v[s], bw2[s], dz1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dz1[r] = h1u[r] > 0.f ? dz1[r] : 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      g2 = mfma32(dz2u[s], h1u[s], g2);
+      g1 = mfma32(xu[s], dz1[s], g1);
     }
-    __syncthreads();
   }
-  float *pb = part + (int64_t)blockIdx.x * kParams;
+  // this wave's sums into sg[wave] in packed parameter order
+  float *pw = sg[wave];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) pb[oW2 + 4 * t + q] = g2[q];
-  if (t < kH * kF) pb[oW1 + t] = gx;
-  else if (t < kH * kF + kH) pb[oB1 + t - kH * kF] = gx;
-  else if (t < kH * kF + 2 * kH) pb[oB2 + t - kH * kF - kH] = gx;
-  else if (t < kH * kF + 3 * kH) pb[oW3 + t - kH * kF - 2 * kH] = gx;
-  if (t == 0) pb[oB3] = gb3;
+  for (int r = 0; r < 16; ++r) {
+    const int j = mrow(r, h);
+    pw[oW2 + j * kH + c] = g2[r];
+    if (j < kF) pw[oW1 + c * kF + j] = g1[r];
+    else if (j == kF) pw[oB1 + c] = g1[r];
+  }
+  gb2 += __shfl_xor(gb2, 32, 64);
+  gw3 += __shfl_xor(gw3, 32, 64);
+  if (h == 0) {
+    pw[oB2 + c] = gb2;
+    pw[oW3 + c] = gw3;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) gb3 += __shfl_xor(gb3, o, 64);
+  if (lane == 0) pw[oB3] = gb3;
+  __syncthreads();
+  float *pb = part + (int64_t)blockIdx.x * kParams;
+  for (int i = t; i < kParams; i += kBlock) {
+    float x = sg[0][i];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) x += sg[w][i];
+    pb[i] = x;
+  }
   const double l = block_sum(loss, red);
   if (t == 0) loss_part[blockIdx.x] = l;
 }
 
-// Block partials [nb][kParams] -> dW.  Block x owns parameters 64x .. 64x+63; its four waves sum
-// the partials of blocks b = w, w+4, w+8, ... in ascending b (float64), then the four wave sums
-// are added in wave order.  Block 0 also reduces the loss partials.
+// Block partials [nb][kParams] -> dW.  Block x owns parameters 64x .. 64x+63; its sixteen waves
+// sum the partials of blocks b = w, w+16, w+32, ... in ascending b (float64), then the sixteen
+// wave sums are added in wave order.  Block 0 also reduces the loss partials.
 constexpr int kReduceParams = 64;
+constexpr int kReduceWaves = 16;
 
-__global__ __launch_bounds__(kBlock) void k_mlp_grad_reduce(const float *__restrict__ part, int32_t nb,
-                                                            const double *__restrict__ loss_part, double inv_n,
-                                                            float *__restrict__ dW, double *__restrict__ loss) {
-  __shared__ double red[kWaves][kReduceParams];
+__global__ __launch_bounds__(64 * kReduceWaves) void k_mlp_grad_reduce(const float *__restrict__ part, int32_t nb,
+                                                                       const double *__restrict__ loss_part,
+                                                                       double inv_n, float *__restrict__ dW,
+                                                                       double *__restrict__ loss) {
+  __shared__ double red[kReduceWaves][kReduceParams];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int p = blockIdx.x * kReduceParams + lane;
   double s = 0.0;
   if (p < kParams)
-    for (int32_t b = wave; b < nb; b += kWaves) s += (double)part[(int64_t)b * kParams + p];
+    for (int32_t b = wave; b < nb; b += kReduceWaves) s += (double)part[(int64_t)b * kParams + p];
   red[wave][lane] = s;
   __syncthreads();
   if (wave == 0 && p < kParams) {
     double x = red[0][lane];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) x += red[w][lane];
+    for (int w = 1; w < kReduceWaves; ++w) x += red[w][lane];
     dW[p] = (float)x;
   }
   if (blockIdx.x == 0) {
-    __shared__ double lred[kWaves];
+    __shared__ double lred[kReduceWaves];
     double l = 0.0;
-    for (int32_t b = t; b < nb; b += kBlock) l += loss_part[b];
-    l = block_sum(l, lred);
+    for (int32_t b = t; b < nb; b += 64 * kReduceWaves) l += loss_part[b];
+    l = block_sum_n<64 * kReduceWaves>(l, lred);
     if (t == 0) *loss = l * inv_n;
   }
 }
@@ -381,7 +450,9 @@ hipError_t launch_features(hipStream_t s, const int32_t *off, const int32_t *idx
 }
 
 hipError_t launch_mlp_forward(hipStream_t s, const float *W, const float *feat, int64_t N, float *y, uint16_t *act) {
-  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks_for(N, 4096)), dim3(kBlock), 0, s, W, feat, N, y, act);
+  int64_t g = (N + kChunk - 1) / kChunk;
+  g = g < 1 ? 1 : g > 4096 ? 4096 : g;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)g), dim3(kBlock), 0, s, W, feat, N, y, act);
   return hipGetLastError();
 }
 
@@ -392,7 +463,7 @@ hipError_t launch_mlp_backward(hipStream_t s, const float *W, const float *feat,
   const double inv_n = 1.0 / (double)N;
   hipLaunchKernelGGL(k_mlp_backward, dim3(nb), dim3(kBlock), 0, s, W, feat, act, y, target, N, inv_n, part,
                      loss_part);
-  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kParams + kReduceParams - 1) / kReduceParams), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kParams + kReduceParams - 1) / kReduceParams), dim3(64 * kReduceWaves), 0, s,
                      (const float *)part, nb,
                      (const double *)loss_part, inv_n, dW, loss);
   return hipGetLastError();

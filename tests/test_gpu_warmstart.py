@@ -70,9 +70,10 @@ def forward_bound(W, cache):
     return 2.0 ** -8 * (t1 + t2) + 1e-5
 
 
-def test_forward_backward_adam_against_oracle(pr, ws, ctx):
+@pytest.mark.parametrize("n", [5000, 1, 33, 4096])
+def test_forward_backward_adam_against_oracle(pr, ws, ctx, n):
+    # 32-vertex tiles: a ragged last tile (5000, 33), a single vertex, whole tiles only (4096)
     rng = np.random.default_rng(1)
-    n = 5000
     X = np.column_stack([rng.uniform(0, 6, n), rng.uniform(0, 6, n), rng.normal(0, 2, n), rng.normal(0, 2, n),
                          np.full(n, 0.9)]).astype(np.float32)
     # seeded weights drawn here, given to both sides: He-uniform scales, small biases
