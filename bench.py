@@ -36,7 +36,9 @@ Other workloads (one JSON line each, same keys):
                         3.1/3.2), and the 21-tolerance sweep read off one traced launch
   --workload warmstart  the learned warm start: a network trained on 20 R-MAT scale-20 graphs
                         proposes start vectors for alpha = 0.90/0.95/0.99 on an unseen scale-24
-                        graph; iterations and time from the uniform, alpha=0.85 and learned starts
+                        graph; iterations and time from the uniform, alpha=0.85 and learned starts;
+                        roofline of the float64 update, and of the network's inference on the
+                        matrix cores (float32 MFMA peak)
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -54,6 +56,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "α-sweep time to τ=1e-10 vs plain FP64; GTEPS; HBM GB/s as % of peak"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense float32 matrix-core peak of the MI355X
 CSRC = "paper_2108_02997_amd/csrc/"
 
 
@@ -637,6 +640,30 @@ def run_warmstart(args, pr, gg, np, torch):
     line["warm_start"] = {"rows": rows, "train_s": round(train_s, 2), "label_s": round(label_s, 2),
                           "epochs": args.epochs, "loss_first_last": [hist[0], hist[-1]],
                           "r085_iterations": r85["iterations"]}
+    # dominant kernel of the timed solves: the float64 update, event-timed per launch
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    pr.pull(ctx, dg, alpha=0.95, tau=tau, norm=norm, init=model.propose(dg, r85["ranks"], 0.95))
+    ctx.set_option("timing", 0)
+    n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+    if n64:
+        line["roofline"] = roofline("k_update<double>", single_update_bytes(g.N, g.E, 8), ms64 / n64 * 1e-3, n64, None)
+    # the network's inference on the matrix cores: 2 (32*6 + 32*32) flops per vertex in the two
+    # hidden layers (the bias as a sixth input), priced against the dense float32 MFMA peak
+    feat, _ = wsm.features(ctx, dg, r85["ranks"], 0.95)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wsm.forward(ctx, model.W, feat)
+    e0.record()
+    for _ in range(5):
+        wsm.forward(ctx, model.W, feat)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 5 * 1e-3
+    flops = 2.0 * (32 * 6 + 32 * 32) * g.N
+    line["mlp_forward"] = {"kernel": "k_mlp_forward (inference, N=%d)" % g.N, "bound": "mfma",
+                           "achieved": round(flops / fwd_s / 1e12, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(flops / fwd_s / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
+                           "avg_launch_us": round(fwd_s * 1e6, 1), "flops_per_vertex": 2 * (32 * 6 + 32 * 32)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the evaluation graph")
     ctx.close()
