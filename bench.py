@@ -472,7 +472,9 @@ def run_multi(args, pr, gg, np, torch):
                                   "Erdos-Renyi, degree {4,8,16,32}, alpha {.75,.85,.95}, tau {1e-6,1e-8,1e-10}, "
                                   "norm {L1,L2,Linf}; autotuned", "graphs": len(hosts),
                       "sum_N": sum(h.N for h in hosts), "sum_E": sum(h.E for h in hosts)})
-    line["roofline"] = roofline("k_multi (whole solve)", alg, msk / nk * 1e-3, nk, None)
+    traffic = read_traffic("multi_64graphs", source_digest([CSRC + "multi.hip", CSRC + "multi.h", CSRC + "device.h",
+                                                           CSRC + "internal.h"]))
+    line["roofline"] = roofline("k_multi (whole solve)", alg, msk / nk * 1e-3, nk, traffic)
     line["multi"] = {"sequential_ms": round(float(np.mean(seq_ts)) * 1e3, 3),
                      "speedup_vs_sequential": round(float(np.mean(seq_ts)) / step_s, 3),
                      "iterations": [r["iterations"] for r in res],
