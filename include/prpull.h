@@ -140,7 +140,10 @@ size_t pr_prep_bytes(int64_t N, int64_t E);
  * low/mid in-degree rows holding about one LDS tile of entries, and high in-degree rows split
  * into fixed-size segments.  Reads only in_offsets.  Writes `prep` (device, caller-owned,
  * prep_bytes >= pr_prep_bytes(N, E)); synchronises `stream` once to read the tile count.
- * The result depends only on in_offsets and may be reused by every later solve on the graph. */
+ * The result depends only on in_offsets and may be reused by every later solve on the graph.
+ * A context remembers, by buffer address, the tile counts of the prep buffers it prepared; a buffer
+ * rewritten by other means (another context, a copy) must be prepared again in this context before
+ * a solve here uses it. */
 int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, int64_t E, void *prep,
                size_t prep_bytes);
 

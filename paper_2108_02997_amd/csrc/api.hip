@@ -116,6 +116,18 @@ struct pr_ctx {
 
 namespace {
 
+// Two HIP events owned by a scope.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair &) = delete;
+  EventPair &operator=(const EventPair &) = delete;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -298,8 +310,8 @@ int run_chunk(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const std::vector<
       set_error("graph capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e2));
       return PR_EDEVICE;
     }
-    constexpr size_t kMaxGraphs = 48;
-    if (ctx->graphs.size() >= kMaxGraphs) {
+    constexpr size_t kMaxCachedGraphs = 48;  // instantiated update chunks kept per context
+    if (ctx->graphs.size() >= kMaxCachedGraphs) {
       size_t lru = 0;
       for (size_t i = 1; i < ctx->graphs.size(); ++i)
         if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
@@ -1251,15 +1263,15 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   const int64_t resident = (int64_t)cus * multi_blocks_per_cu();
   int64_t grid = ctx->max_grid > 0 ? std::min<int64_t>(ctx->max_grid, resident) : resident;
   grid = std::max<int64_t>(1, std::min<int64_t>({grid, total_tiles > 0 ? total_tiles : 1, (int64_t)kMaxGrid}));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair ev;  // destroyed on every return
   if (ctx->timing) {
-    PR_HIP(hipEventCreate(&e0));
-    PR_HIP(hipEventCreate(&e1));
-    PR_HIP(hipEventRecord(e0, s));
+    PR_HIP(hipEventCreate(&ev.a));
+    PR_HIP(hipEventCreate(&ev.b));
+    PR_HIP(hipEventRecord(ev.a, s));
   }
   PR_HIP(launch_fill_u32(s, (uint32_t *)dbar, sizeof(GridBarrier) / 4, 0u));
   PR_HIP(launch_multi(s, (unsigned)grid, p, 64));
-  if (ctx->timing) PR_HIP(hipEventRecord(e1, s));
+  if (ctx->timing) PR_HIP(hipEventRecord(ev.b, s));
   std::vector<MultiGraphState> hs(G);
   uint32_t timed_out = 0;
   PR_HIP(hipMemcpyAsync(ctx->hmulti, dstates, sizeof(MultiGraphState) * (size_t)G, hipMemcpyDeviceToHost, s));
@@ -1270,11 +1282,9 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   memcpy(&timed_out, (char *)ctx->hmulti + sizeof(MultiGraphState) * (size_t)G, sizeof(uint32_t));
   if (ctx->timing) {
     float ms = 0.f;
-    PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    PR_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
     ctx->stat_ms[PR_KERNEL_MULTI] += ms;
     ctx->stat_launches[PR_KERNEL_MULTI] += 1;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
   }
   if (timed_out) {
     set_error("pr_pull_multi: a grid barrier wait of the launch passed its time limit");
