@@ -9,6 +9,10 @@
   ratio-first forms (RATIO-AM/GM/HM: per-case ratio to the baseline, then the mean).
 * `nested`: section 4's two-level mean -- over the graphs for each tolerance, then over the
   tolerances -- relative to a baseline approach.
+* `sensitivity` and `single_iteration`: the two iteration-count checks of sections 4 and 5. An
+  approach has a sensitivity issue from the first tolerance (taken in decreasing order) at which
+  it abruptly needs the maximum number of iterations while the tolerance before did not; and it
+  converges in a single iteration at the tolerances where one update already meets tau.
 """
 from __future__ import annotations
 
@@ -60,3 +64,34 @@ def nested(Y, baseline: int, kind: str) -> list:
     per_tau = _mean(Y, kind, axis=1)           # [tau][approach]
     total = _mean(per_tau, kind, axis=0)       # [approach]
     return (total / total[baseline]).tolist()
+
+
+def _per_approach(iterations):
+    a = np.asarray(iterations)
+    return a.reshape(-1, 1) if a.ndim == 1 else a
+
+
+def sensitivity(iterations, max_iter: int):
+    """iterations: [tau] or [tau][approach] iteration counts, tolerances in decreasing order (a
+    count >= max_iter means the solve halted at the limit; a stop read off a trace as 0 -- never
+    reached -- counts as halted too).  Returns, per approach, the index of the first tolerance at
+    which the count jumps to max_iter from below it (index 0 when the first one is already
+    there), or None if it never does; a scalar for a one-dimensional table."""
+    a = _per_approach(iterations)
+    halted = (a >= max_iter) | (a == 0)
+    out = []
+    for j in range(a.shape[1]):
+        onset = None
+        for i in range(a.shape[0]):
+            if halted[i, j] and (i == 0 or not halted[i - 1, j]):
+                onset = i
+                break
+        out.append(onset)
+    return out[0] if np.asarray(iterations).ndim == 1 else out
+
+
+def single_iteration(iterations):
+    """Per approach, the indices of the tolerances at which one iteration is enough."""
+    a = _per_approach(iterations)
+    out = [[int(i) for i in np.nonzero(a[:, j] == 1)[0]] for j in range(a.shape[1])]
+    return out[0] if np.asarray(iterations).ndim == 1 else out

@@ -1,4 +1,6 @@
 """Host-side reports (paper sections 3 and 4) of the package against the oracle's definitions."""
+import os
+
 import numpy as np
 import pytest
 
@@ -46,3 +48,47 @@ def test_stops_match_the_oracle_readout():
 def test_composite_rejects_non_positive_tables():
     with pytest.raises(ValueError):
         report.composite([[1.0, 0.0, 2.0]], 0)
+
+
+def _golden_fig41():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sensitivity_fig41.txt")
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.split()
+    return kv
+
+
+def test_sensitivity_and_single_iteration_on_the_figure_41_description():
+    kv = _golden_fig41()
+    taus = [float(x) for x in kv["taus"]]
+    max_iter = int(kv["max_iter"][0])
+    onset = {n: taus.index(float(kv["onset " + n][0])) for n in ("L1", "L2", "Linf")}
+    single = {n: taus.index(float(kv["single_iteration_down_to " + n][0])) for n in ("L2", "Linf")}
+    # an iteration table with exactly the stated behaviour: counts grow as tau falls, one update
+    # while the single-iteration range lasts, then the abrupt jump to the limit
+    table = np.zeros((len(taus), 3), dtype=np.int64)
+    for j, n in enumerate(("L1", "L2", "Linf")):
+        for i in range(len(taus)):
+            if i >= onset[n]:
+                table[i, j] = max_iter
+            elif n in single and i <= single[n]:
+                table[i, j] = 1
+            else:
+                table[i, j] = 2 + 3 * i
+    assert report.sensitivity(table, max_iter) == [onset["L1"], onset["L2"], onset["Linf"]]
+    got = report.single_iteration(table)
+    assert got[0] == [] and got[1] == list(range(single["L2"] + 1)) and got[2] == list(range(single["Linf"] + 1))
+    # L1 is the first to suffer (section 4)
+    assert taus[report.sensitivity(table[:, 0], max_iter)] > taus[report.sensitivity(table[:, 1], max_iter)]
+
+
+def test_sensitivity_edge_cases():
+    assert report.sensitivity([3, 5, 9, 14], 500) is None
+    assert report.sensitivity([500, 500], 500) == 0
+    assert report.sensitivity([4, 7, 0, 0], 500) == 2        # a stop read off a trace as 0: never reached
+    assert report.sensitivity([4, 7, 499, 500, 500], 500) == 3
+    assert report.single_iteration([1, 1, 2, 1]) == [0, 1, 3]
+    assert report.sensitivity(np.array([[1, 500], [2, 500]]), 500) == [None, 0]
