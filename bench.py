@@ -126,10 +126,15 @@ def single_update_bytes(N, E, s):
 
 def roofline(kernel, alg_bytes, avg_s, launches, traffic):
     achieved = alg_bytes / avg_s / 1e9
-    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": round(alg_bytes), "avg_launch_us": round(avg_s * 1e6, 2),
-            "launches_timed": launches}
+    out = {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": round(alg_bytes), "avg_launch_us": round(avg_s * 1e6, 2),
+           "launches_timed": launches}
+    if traffic:
+        # the measured HBM-side bytes (calibrated counters) over the same launch time
+        out["traffic_GBps"] = round(traffic / avg_s / 1e9, 1)
+        out["traffic_frac_of_peak"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def bare_gather_us(dg, row_bytes):
