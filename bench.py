@@ -27,8 +27,10 @@ Other workloads (one JSON line each, same keys):
                         to tau=1e-6 (L1): solve and update times, oracle on one and on all cores
   --workload tau        R-MAT scale 22: every (tau, norm) stop for tau = 1e-3 .. 1e-10 and the
                         three norms, float64 against mixed precision (iterations, time, distance),
-                        with a float32-only ablation beside them (continued to 1e-12), and the
-                        sensitivity-issue and single-iteration checks of sections 4-5
+                        with a float32-only ablation beside them (continued to 1e-12), the
+                        sensitivity-issue and single-iteration checks of sections 4-5, and the
+                        update times on the graph as generated, randomly relabelled (locality
+                        stress case) and in out-degree order
   --workload multi      64 seeded graphs of uneven size (log-uniform 1e3 .. 1e6 vertices) with
                         their own alpha/tau/norm, autotuned, in one persistent launch, against
                         the sum of 64 sequential solves
@@ -452,6 +454,31 @@ def run_tau(args, pr, gg, np, torch):
     line["readout"] = rows
     line["fp32_only_below_1e-10"] = extra
     line["iteration_checks"] = checks
+    # locality: the same graph as generated, under a seeded random relabelling (the stress case) and
+    # in out-degree order (hot sources contiguous); update times of one float64 (L1) and one mixed
+    # (Linf) solve each, and the float64 ranks mapped back to the generated ids
+    locality = {}
+    for name, perm in (("as_generated", None), ("random_relabel", gg.permutation(N, seed + 7)),
+                       ("degree_order", gg.degree_order(g))):
+        h = g if perm is None else gg.relabel(g, perm)
+        dh = dg if perm is None else pr.DeviceGraph.from_host(h, 0).prepare(ctx)
+        ctx.reset_stats()
+        ctx.set_option("timing", 1)
+        r64 = pr.pull(ctx, dh, alpha=0.85, tau=1e-10, norm=pr.PR_L1, precision=pr.PR_FP64)
+        pr.pull(ctx, dh, alpha=0.85, tau=1e-10, norm=pr.PR_LINF, precision=pr.PR_MIXED)
+        ctx.set_option("timing", 0)
+        a64, b64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+        a32, b32 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F32)
+        back = r64["ranks"] if perm is None else r64["ranks"][torch.from_numpy(perm.astype(np.int64)).cuda()]
+        locality[name] = {"f64_update_us": round(1e3 * b64 / a64, 1), "f32_update_us": round(1e3 * b32 / a32, 1),
+                          "f64_iterations": r64["iterations"],
+                          "f64_frac_of_peak": round(single_update_bytes(N, E, 8) / (b64 / a64 * 1e-3) / 1e9
+                                                    / HBM_PEAK_GBS, 4),
+                          "l1_vs_as_generated": pr.l1_distance(ctx, back, ref["ranks"])}
+        if perm is not None:
+            del dh
+            torch.cuda.empty_cache()
+    line["locality"] = locality
     line["sum_ms"] = {"fp64": round(total[pr.PR_FP64] * 1e3, 2), "mixed": round(total[pr.PR_MIXED] * 1e3, 2)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")

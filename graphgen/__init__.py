@@ -172,6 +172,15 @@ def relabel(g: Graph, perm: np.ndarray) -> Graph:
     return from_edges(g.N, perm[src], perm[dst], dedupe=False, drop_self_loops=False, name=g.name + "+relabel")
 
 
+def degree_order(g: Graph) -> np.ndarray:
+    """perm[v] = new id of v when vertices are ordered by decreasing out-degree, ties by id: the
+    most cited sources get consecutive ids (a locality ordering for the pull gather)."""
+    order = np.argsort(-np.asarray(g.outdeg, dtype=np.int64), kind="stable")
+    perm = np.empty(g.N, dtype=np.int32)
+    perm[order] = np.arange(g.N, dtype=np.int32)
+    return perm
+
+
 def hash3(seed: int, stream: int, counter: int) -> int:
     return int(_load().gg_hash3(seed, stream, counter))
 

@@ -97,3 +97,19 @@ def test_load_mtx_general_and_symmetric(tmp_path):
     out.write_text("%%MatrixMarket matrix coordinate pattern general\n2 2 1\n3 1\n")
     with pytest.raises(ValueError):
         gg.load_mtx(str(out))
+
+
+def test_degree_order_is_a_permutation_by_decreasing_out_degree():
+    g = gg.rmat(10, seed=4)
+    p = gg.degree_order(g)
+    assert sorted(p.tolist()) == list(range(g.N))
+    inv = np.empty(g.N, dtype=np.int64)
+    inv[p] = np.arange(g.N)
+    d = g.outdeg[inv]                      # out-degree of new id 0, 1, ...
+    assert np.all(np.diff(d.astype(np.int64)) <= 0)
+    # ties keep the original order
+    for k in range(g.N - 1):
+        if d[k] == d[k + 1]:
+            assert inv[k] < inv[k + 1]
+    h = gg.relabel(g, p)
+    assert np.array_equal(h.outdeg[p], g.outdeg)
