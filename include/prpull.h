@@ -147,6 +147,24 @@ size_t pr_prep_bytes(int64_t N, int64_t E);
 int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, int64_t E, void *prep,
                size_t prep_bytes);
 
+/* Degree ordering of the vertices, a locality preprocessing for the pull gather (the ranks of the
+ * relabelled graph are those of the original, renamed): perm[v] = new id of v, vertices by
+ * decreasing out-degree, ties by increasing id, so the most cited sources get consecutive ids.
+ * The relabelled in-CSR goes to out_offsets[N+1], out_indices[E], out_outdeg[N]: row perm[v]
+ * holds v's in-edges, each source u renamed perm[u], in ascending order.  All arrays are device
+ * memory owned by the caller; the outputs must not overlap the inputs.  workspace: device,
+ * pr_relabel_workspace_bytes(ctx, N, E) bytes (0 when N or E is out of range or the size query
+ * fails).  Synchronises the stream once.  Solve the relabelled graph, then pr_unpermute maps its
+ * ranks back. */
+size_t pr_relabel_workspace_bytes(pr_ctx *ctx, int64_t N, int64_t E);
+int pr_relabel(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+               int64_t N, int64_t E, int32_t *perm, int32_t *out_offsets, int32_t *out_indices, int32_t *out_outdeg,
+               void *workspace, size_t workspace_bytes);
+
+/* out[v] = in[perm[v]] for v < N (device float64 arrays, not overlapping): ranks of a graph
+ * relabelled by pr_relabel, back in the original ids.  Async. */
+int pr_unpermute(pr_ctx *ctx, void *stream, const int32_t *perm, int64_t N, const double *in, double *out);
+
 /* Structural check of a CSR (debugging/tests; O(N + E)): offsets monotone with off[0] = 0 and
  * off[N] = E, every index in [0, N), and outdeg[u] equal to u's number of CSR entries.
  * Needs a device workspace of at least 4*N + 256 bytes.  Returns PR_OK or PR_EGRAPH. */

@@ -18,8 +18,8 @@ from . import _lib
 from ._lib import (MAX_COLS, PR_FP32, PR_FP64, PR_L1, PR_L2, PR_LINF, PR_MIXED, PR_NOT_CONVERGED, PR_OK,  # noqa: F401
                    PrError, pr_graph_problem, pr_problem, pr_result)
 
-__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "pull_multi", "PR_L1", "PR_L2", "PR_LINF", "PR_FP64",
-           "PR_MIXED", "PR_FP32", "PrError"]
+__all__ = ["Context", "DeviceGraph", "pull", "pull_batch", "pull_multi", "unpermute", "PR_L1", "PR_L2", "PR_LINF",
+           "PR_FP64", "PR_MIXED", "PR_FP32", "PrError"]
 
 
 def _require_gpu():
@@ -96,6 +96,24 @@ class DeviceGraph:
                                                     self.prep.data_ptr(), nbytes))
         return self
 
+    def relabelled(self, ctx: Context):
+        """pr_relabel: the graph in out-degree order (most cited sources first) and perm, the new id
+        of every vertex.  Ranks solved on the returned graph map back with unpermute(ctx, perm, r)."""
+        dev = self.off.device
+        perm = torch.empty(self.N, dtype=torch.int32, device=dev)
+        off = torch.empty(self.N + 1, dtype=torch.int32, device=dev)
+        idx = torch.empty(max(self.E, 1), dtype=torch.int32, device=dev)[:self.E]
+        outdeg = torch.empty(self.N, dtype=torch.int32, device=dev)
+        nbytes = ctx.lib.pr_relabel_workspace_bytes(ctx.handle, self.N, self.E)
+        if nbytes == 0:
+            raise PrError("pr_relabel_workspace_bytes", _lib.PR_EINVAL, _lib.last_error())
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _lib.check("pr_relabel", ctx.lib.pr_relabel(
+            ctx.handle, ctx.stream, self.off.data_ptr(), _lib.ptr(self.idx) if self.E else None,
+            self.outdeg.data_ptr(), self.N, self.E, perm.data_ptr(), off.data_ptr(),
+            _lib.ptr(idx) if self.E else None, outdeg.data_ptr(), ws.data_ptr(), nbytes))
+        return DeviceGraph(self.N, self.E, off, idx, outdeg), perm
+
     def workspace(self, ctx: Context, precision: int, with_prep: bool, K: int = 0) -> torch.Tensor:
         key = (precision, with_prep, K)
         ws = self._ws.get(key)
@@ -148,6 +166,14 @@ def pr_pull(ctx: Context, g: DeviceGraph, alpha: float, tau: float, norm: int, m
                          workspace.data_ptr(), workspace.numel(), ctypes.byref(res))
     _lib.check("pr_pull", st)
     return st, res.as_dict()
+
+
+def unpermute(ctx: Context, perm: torch.Tensor, ranks: torch.Tensor) -> torch.Tensor:
+    """pr_unpermute: out[v] = ranks[perm[v]], ranks of a relabelled graph back in the original ids."""
+    out = torch.empty_like(ranks)
+    _lib.check("pr_unpermute", ctx.lib.pr_unpermute(ctx.handle, ctx.stream, perm.data_ptr(), ranks.numel(),
+                                                    ranks.data_ptr(), out.data_ptr()))
+    return out
 
 
 def pull(ctx: Context, g: DeviceGraph, alpha: float = 0.85, tau: float = 1e-6, norm: int = PR_L1,

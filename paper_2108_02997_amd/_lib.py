@@ -26,6 +26,8 @@ BATCH_ROW_WIDTHS = (1, 2, 4, 8, 12, 16)
 def batch_kind(fp32: bool, width: int) -> int:
     """Stats kind of pr_pull_batch updates that ran on rows of `width` values."""
     return (PR_KERNEL_BATCH_F32_W1 if fp32 else PR_KERNEL_BATCH_F64_W1) + BATCH_ROW_WIDTHS.index(width)
+
+
 MAX_COLS = 16
 PR_OK, PR_NOT_CONVERGED, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EGRAPH = 0, 1, -1, -2, -3, -4
 STATUS_NAMES = {0: "PR_OK", 1: "PR_NOT_CONVERGED", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE",
@@ -77,6 +79,9 @@ SIGNATURES = {
     "pr_prep_bytes": ([_i64, _i64], _sz),
     "pr_prepare": ([_vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),
     "pr_validate_graph": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),
+    "pr_relabel_workspace_bytes": ([_vp, _i64, _i64], _sz),
+    "pr_relabel": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _sz], ctypes.c_int),
+    "pr_unpermute": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "pr_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "pr_pull": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz,
                  ctypes.POINTER(pr_result)], ctypes.c_int),

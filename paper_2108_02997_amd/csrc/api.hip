@@ -697,6 +697,49 @@ int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, cons
   return PR_OK;
 }
 
+size_t pr_relabel_workspace_bytes(pr_ctx *ctx, int64_t N, int64_t E) {
+  if (!ctx || bad_graph_sizes(N, E)) return 0;
+  DeviceGuard g(ctx->device);
+  size_t b = 0;
+  return relabel_temp_bytes(N, E, &b) == hipSuccess ? b : 0;
+}
+
+int pr_relabel(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+               int64_t N, int64_t E, int32_t *perm, int32_t *out_offsets, int32_t *out_indices, int32_t *out_outdeg,
+               void *workspace, size_t workspace_bytes) {
+  if (!ctx || !in_offsets || !outdeg || !perm || !out_offsets || !out_outdeg || !workspace ||
+      (E > 0 && (!in_indices || !out_indices))) {
+    set_error("pr_relabel: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  DeviceGuard g(ctx->device);
+  size_t need = 0;
+  PR_HIP(relabel_temp_bytes(N, E, &need));
+  if (workspace_bytes < need) {
+    set_error("pr_relabel: workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return PR_ENOMEM;
+  }
+  PR_HIP(launch_relabel((hipStream_t)stream, in_offsets, in_indices, outdeg, (int32_t)N, (int32_t)E, perm,
+                        out_offsets, out_indices, out_outdeg, workspace, workspace_bytes,
+                        (uint32_t *)ctx->hscratch));
+  return PR_OK;
+}
+
+int pr_unpermute(pr_ctx *ctx, void *stream, const int32_t *perm, int64_t N, const double *in, double *out) {
+  if (!ctx || !perm || !in || !out) {
+    set_error("pr_unpermute: NULL argument");
+    return PR_EINVAL;
+  }
+  if (N < 1 || N > 2147483646LL) {
+    set_error("pr_unpermute: N must be in [1, 2^31-2], got %lld", (long long)N);
+    return PR_EINVAL;
+  }
+  DeviceGuard g(ctx->device);
+  PR_HIP(launch_unpermute((hipStream_t)stream, perm, (int32_t)N, in, out));
+  return PR_OK;
+}
+
 size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep) {
   if (bad_graph_sizes(N, E) || (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32)) return 0;
   return carve(nullptr, N, E, precision, with_prep != 0).total;

@@ -150,6 +150,29 @@ def test_relabelled_rmat(pr, ctx):
     check_fp64(pr, ctx, g, tau=1e-9, norm=2)
 
 
+@pytest.mark.parametrize("make", [lambda: gg.rmat(14, seed=5), gg.workload_c1, lambda: gg.edgeless(3),
+                                  lambda: gg.out_star(6), gg.two_triangles, lambda: gg.complete(100)])
+def test_degree_relabel_on_the_device(pr, ctx, make):
+    # pr_relabel: the permutation is the host's definition (decreasing out-degree, ties by id), the
+    # relabelled CSR the host's relabelling, and ranks solved on it map back to the oracle's on the
+    # original graph
+    g = make()
+    dg = dev(pr, g)
+    h, perm = dg.relabelled(ctx)
+    p_ref = gg.degree_order(g)
+    assert np.array_equal(perm.cpu().numpy(), p_ref)
+    ref = gg.relabel(g, p_ref)
+    assert np.array_equal(h.off.cpu().numpy(), ref.off) and np.array_equal(h.outdeg.cpu().numpy(), ref.outdeg)
+    # rows in ascending source order on both sides: the same arrays
+    assert np.array_equal(h.idx.cpu().numpy(), ref.idx)
+    res = pr.pull(ctx, h, alpha=0.85, tau=1e-10, norm=1)
+    back = pr.unpermute(ctx, perm, res["ranks"])
+    oref = oracle.pagerank_graph(g, alpha=0.85, tau=1e-10, norm=1, trace=True)
+    assert iterations_ok(res["iterations"], oref, 1e-10, 1)
+    if res["iterations"] == oref["iterations"]:
+        assert np.abs(back.cpu().numpy() - oref["ranks"]).sum() <= 1e-12
+
+
 def test_max_iter_halt(pr, ctx):
     g = gg.workload_c1()
     dg = dev(pr, g)
