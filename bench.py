@@ -20,6 +20,8 @@ Reported:
                    same index array (microbench/gather_ceiling.hip), and the kernel's time as a
                    fraction of that bare time
   plain_fp64_gather  the same for the single-vector float64 update of the sequential solves
+  degree_order     the same sweep and sequential solves on the graph relabelled by out-degree
+                   (pr_relabel, excluded from the timing like the prep), ranks mapped back
   cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
 
 Other workloads (one JSON line each, same keys):
@@ -324,10 +326,49 @@ def run_sweep(args, pr, gg, np, torch):
         "first_phase_updates_per_step": round(n_all / args.steps, 2) if n_all else None,
         "first_phase_update_us_all_widths": round(1e3 * ms_all / n_all, 2) if n_all else None,
     }
+    if not args.no_relabel:
+        line["degree_order"] = relabelled_sweep(args, pr, ctx, dg, problems, batch_prec, tau, norm, max_iter, N, E,
+                                                step_s, seq_s, ranks_b, torch, np)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")
     ctx.close()
     return line
+
+
+def relabelled_sweep(args, pr, ctx, dg, problems, batch_prec, tau, norm, max_iter, N, E, step_s, seq_s, ranks_b,
+                     torch, np):
+    """The same sweep and sequential solves on the graph in out-degree order (pr_relabel, timed on
+    its own; not part of the headline numbers), the ranks mapped back and compared."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dh, perm = dg.relabelled(ctx)
+    torch.cuda.synchronize()
+    relabel_ms = (time.perf_counter() - t0) * 1e3
+    dh.prepare(ctx)
+    log("relabelled by out-degree in %.1f ms" % relabel_ms)
+    sweep = lambda: pr.pull_batch(ctx, dh, problems, precision=batch_prec)  # noqa: E731
+    seq = lambda: [pr.pull(ctx, dh, alpha=p["alpha"], tau=tau, norm=norm, max_iter=max_iter,  # noqa: E731
+                           precision=pr.PR_FP64) for p in problems]
+    sweep()
+    ts, res = timed(sweep, min(args.steps, 3), "step (batched sweep, degree order)")
+    seq()
+    ts_seq, _ = timed(seq, 1, "sequential fp64 sweep, degree order")
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    pr.pull(ctx, dh, alpha=0.85, tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64)
+    ctx.set_option("timing", 0)
+    n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+    back = [pr.unpermute(ctx, perm, r["ranks"]) for r in res]
+    step = float(np.mean(ts))
+    return {"relabel_ms": round(relabel_ms, 2), "batched_sweep_ms": round(step * 1e3, 3),
+            "sequential_fp64_ms": round(float(np.mean(ts_seq)) * 1e3, 3),
+            "speedup_vs_sequential_fp64": round(float(np.mean(ts_seq)) / step, 3),
+            "vs_generated_labels": {"batched_sweep": round(step_s / step, 3),
+                                    "sequential_fp64": round(seq_s / float(np.mean(ts_seq)), 3)},
+            "iterations": [r["iterations"] for r in res],
+            "max_l1_vs_generated_labels": max(pr.l1_distance(ctx, a, b) for a, b in zip(back, ranks_b)),
+            "plain_fp64_update": roofline("k_update<double>", single_update_bytes(N, E, 8), ms64 / n64 * 1e-3, n64,
+                                          None) if n64 else None}
 
 
 # ------------------------------------------------------------------ the small configuration
@@ -759,6 +800,7 @@ def main():
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default: 24, or 22 for --workload tau)")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-relabel", action="store_true", help="skip the sweep on the out-degree-ordered graph")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--calibrate", action="store_true", help="accepted for older command lines; the 1 GiB copy "
                     "that calibrates the memory counters now always runs")

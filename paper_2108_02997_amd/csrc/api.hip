@@ -22,6 +22,7 @@
 #include "batch.h"
 #include "internal.h"
 #include "multi.h"
+#include "relabel.h"
 
 namespace prpull {
 

@@ -140,12 +140,5 @@ hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N
                           unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
-// relabel.hip: workspace bytes of launch_relabel (queries hipCUB; needs a current device)
-hipError_t relabel_temp_bytes(int64_t N, int64_t E, size_t *bytes);
-// host_count: pinned host word; the launch synchronises s once (to size the segmented sort)
-hipError_t launch_relabel(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
-                          int32_t E, int32_t *perm, int32_t *new_off, int32_t *new_idx, int32_t *new_outdeg,
-                          void *ws, size_t ws_bytes, uint32_t *host_count);
-hipError_t launch_unpermute(hipStream_t s, const int32_t *perm, int32_t N, const double *in, double *out);
 
 }  // namespace prpull

@@ -10,7 +10,7 @@
 // segmented radix sort (hipCUB) of the longer rows.
 #include <hipcub/hipcub.hpp>
 
-#include "internal.h"
+#include "relabel.h"
 
 namespace prpull {
 
