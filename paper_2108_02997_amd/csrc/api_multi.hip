@@ -1,0 +1,289 @@
+// api_multi.hip -- the C ABI of the many-graph persistent launch (pr_pull_multi) and of the
+// autotuner (pr_autotune).
+#include <string.h>
+
+#include <algorithm>
+
+#include "api_internal.h"
+
+extern "C" {
+
+static size_t multi_layout(int32_t G, const pr_graph_problem *probs, void *ws, MultiGraph **graphs,
+                           MultiGraphState **states, int32_t **tile_base, double **part, GridBarrier **bar,
+                           double **hpart, double **y, void **preps) {
+  Carver c(ws);
+  *bar = (GridBarrier *)c.take(sizeof(GridBarrier));
+  *graphs = (MultiGraph *)c.take(sizeof(MultiGraph) * (size_t)G);
+  *states = (MultiGraphState *)c.take(sizeof(MultiGraphState) * (size_t)G);
+  *tile_base = (int32_t *)c.take(sizeof(int32_t) * (size_t)(G + 1));
+  *part = (double *)c.take(sizeof(double) * 4 * (size_t)kMaxGrid * (size_t)G);
+  for (int g = 0; g < G; ++g) {
+    hpart[g] = (double *)c.take(sizeof(double) * (size_t)max_slots(probs[g].N, probs[g].E));
+    y[2 * g] = (double *)c.take(sizeof(double) * (size_t)probs[g].N);
+    y[2 * g + 1] = (double *)c.take(sizeof(double) * (size_t)probs[g].N);
+    preps[g] = probs[g].prep ? nullptr : c.take(prep_bytes(probs[g].N, probs[g].E));
+  }
+  return c.used;
+}
+
+size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs) {
+  if (G < 1 || G > kMaxGraphs || !probs) return 0;
+  for (int g = 0; g < G; ++g)
+    if (bad_graph_sizes(probs[g].N, probs[g].E)) return 0;
+  MultiGraph *a;
+  MultiGraphState *b;
+  int32_t *c;
+  double *d;
+  GridBarrier *e;
+  std::vector<double *> hp(G), y(2 * G);
+  std::vector<void *> pp(G);
+  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, &e, hp.data(), y.data(), pp.data());
+}
+
+int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
+                  size_t workspace_bytes, pr_result *results) {
+  if (!ctx || !probs || !workspace || !results) {
+    set_error("pr_pull_multi: NULL argument");
+    return PR_EINVAL;
+  }
+  if (G < 1 || G > kMaxGraphs) {
+    set_error("G must be in [1, %d], got %d", kMaxGraphs, G);
+    return PR_EINVAL;
+  }
+  int max_rounds = 1;
+  int64_t total_tiles = 0;
+  for (int g = 0; g < G; ++g) {
+    const pr_graph_problem &q = probs[g];
+    if (!q.in_offsets || !q.outdeg || !q.ranks || (q.E > 0 && !q.in_indices)) {
+      set_error("graph %d: NULL graph or ranks pointer", g);
+      return PR_EINVAL;
+    }
+    if (bad_graph_sizes(q.N, q.E)) return PR_EINVAL;
+    if (!(q.alpha >= 0.0 && q.alpha <= 1.0) || !(q.tau >= 0.0) || q.norm < PR_L1 || q.norm > PR_LINF ||
+        q.max_iter < 1) {
+      set_error("graph %d: alpha in [0,1], tau >= 0, norm 1..3 and max_iter >= 1 are required", g);
+      return PR_EINVAL;
+    }
+    max_rounds = std::max(max_rounds, q.max_iter);
+  }
+  MultiGraph *dgraphs;
+  MultiGraphState *dstates;
+  int32_t *dbase;
+  double *dpart;
+  GridBarrier *dbar;
+  std::vector<double *> hpart(G), ybuf(2 * G);
+  std::vector<void *> ownprep(G);
+  const size_t need = multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, &dbar, hpart.data(),
+                                   ybuf.data(), ownprep.data());
+  if (workspace_bytes < need) {
+    set_error("pr_pull_multi: workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return PR_ENOMEM;
+  }
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<MultiGraph> hg(G);
+  std::vector<int32_t> base(G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    const pr_graph_problem &q = probs[g];
+    PrepHeader h;
+    int rc;
+    const void *pp = q.prep;
+    if (!pp) {
+      rc = prepare_into(ctx, s, q.in_offsets, q.N, q.E, ownprep[g], &h);
+      pp = ownprep[g];
+    } else {
+      rc = get_prep(ctx, s, pp, q.N, q.E, &h);
+    }
+    if (rc != PR_OK) return rc;
+    const PrepPart &part = h.part[0];
+    MultiGraph &m = hg[g];
+    memset(&m, 0, sizeof m);
+    m.off = q.in_offsets;
+    m.idx = q.in_indices;
+    m.outdeg = q.outdeg;
+    m.desc = (const int4 *)((const char *)pp + part.desc_off);
+    m.hubs = (const int4 *)((const char *)pp + part.hub_off);
+    m.nhubs = part.nhubs;
+    m.hpart = hpart[g];
+    m.y[0] = ybuf[2 * g];
+    m.y[1] = ybuf[2 * g + 1];
+    m.init = q.init;
+    m.ranks = q.ranks;
+    m.trace = q.norm_trace;
+    m.alpha = q.alpha;
+    m.tau = q.tau;
+    m.N = (int32_t)q.N;
+    m.norm = q.norm;
+    m.max_iter = q.max_iter;
+    m.mid_deg = tuned_settings(ctx, h).first;
+    total_tiles += part.ndesc;
+    if (total_tiles > 2147483647LL) {
+      set_error("pr_pull_multi: more than 2^31 tiles in one batch");
+      return PR_EINVAL;
+    }
+    base[g + 1] = (int32_t)total_tiles;
+  }
+  // stage the tables through pinned memory (synchronised before the buffer is reused)
+  const size_t tbytes = sizeof(MultiGraph) * (size_t)G + sizeof(int32_t) * (size_t)(G + 1);
+  if (ctx->hmulti_bytes < tbytes) {
+    if (ctx->hmulti) (void)hipHostFree(ctx->hmulti);
+    ctx->hmulti = nullptr;
+    ctx->hmulti_bytes = 0;
+    PR_HIP(hipHostMalloc(&ctx->hmulti, tbytes, hipHostMallocDefault));
+    ctx->hmulti_bytes = tbytes;
+  }
+  char *hm = (char *)ctx->hmulti;
+  memcpy(hm, hg.data(), sizeof(MultiGraph) * (size_t)G);
+  memcpy(hm + sizeof(MultiGraph) * (size_t)G, base.data(), sizeof(int32_t) * (size_t)(G + 1));
+  PR_HIP(hipMemcpyAsync(dgraphs, hm, sizeof(MultiGraph) * (size_t)G, hipMemcpyHostToDevice, s));
+  PR_HIP(hipMemcpyAsync(dbase, hm + sizeof(MultiGraph) * (size_t)G, sizeof(int32_t) * (size_t)(G + 1),
+                        hipMemcpyHostToDevice, s));
+  MultiParams p{};
+  p.graphs = dgraphs;
+  p.states = dstates;
+  p.tile_base = dbase;
+  p.part = dpart;
+  p.bar = dbar;
+  {
+    int khz = 0;  // wall clock of the device (s_memrealtime), 100 MHz on this GPU family
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz < 1)
+      khz = 100000;
+    p.wait_ticks = (uint64_t)ctx->barrier_ms * (uint64_t)khz;
+  }
+  p.G = G;
+  p.total_tiles = (int32_t)total_tiles;
+  p.max_rounds = max_rounds;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
+  const int64_t resident = (int64_t)cus * multi_blocks_per_cu();
+  int64_t grid = ctx->max_grid > 0 ? std::min<int64_t>(ctx->max_grid, resident) : resident;
+  grid = std::max<int64_t>(1, std::min<int64_t>({grid, total_tiles > 0 ? total_tiles : 1, (int64_t)kMaxGrid}));
+  EventPair ev;  // destroyed on every return
+  if (ctx->timing) {
+    PR_HIP(hipEventCreate(&ev.a));
+    PR_HIP(hipEventCreate(&ev.b));
+    PR_HIP(hipEventRecord(ev.a, s));
+  }
+  PR_HIP(launch_fill_u32(s, (uint32_t *)dbar, sizeof(GridBarrier) / 4, 0u));
+  PR_HIP(launch_multi(s, (unsigned)grid, p, 64));
+  if (ctx->timing) PR_HIP(hipEventRecord(ev.b, s));
+  std::vector<MultiGraphState> hs(G);
+  uint32_t timed_out = 0;
+  PR_HIP(hipMemcpyAsync(ctx->hmulti, dstates, sizeof(MultiGraphState) * (size_t)G, hipMemcpyDeviceToHost, s));
+  PR_HIP(hipMemcpyAsync((char *)ctx->hmulti + sizeof(MultiGraphState) * (size_t)G, &dbar->timeout[0],
+                        sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  memcpy(hs.data(), ctx->hmulti, sizeof(MultiGraphState) * (size_t)G);
+  memcpy(&timed_out, (char *)ctx->hmulti + sizeof(MultiGraphState) * (size_t)G, sizeof(uint32_t));
+  if (ctx->timing) {
+    float ms = 0.f;
+    PR_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    ctx->stat_ms[PR_KERNEL_MULTI] += ms;
+    ctx->stat_launches[PR_KERNEL_MULTI] += 1;
+  }
+  if (timed_out) {
+    set_error("pr_pull_multi: a grid barrier wait of the launch passed its time limit");
+    return PR_EDEVICE;
+  }
+  int all = 1;
+  for (int g = 0; g < G; ++g) {
+    results[g].iterations = hs[g].iters;
+    results[g].converged = hs[g].converged;
+    results[g].fp32_iters = 0;
+    results[g].fp64_iters = hs[g].iters;
+    results[g].final_err[0] = hs[g].err[0];
+    results[g].final_err[1] = hs[g].err[1];
+    results[g].final_err[2] = hs[g].err[2];
+    all &= hs[g].converged;
+  }
+  return all ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
+                size_t workspace_bytes, pr_tune_result *out) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices)) {
+    set_error("pr_autotune: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  const Layout L = carve(workspace, N, E, PR_FP64, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_autotune: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  const void *pp = prep;
+  int rc;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+  // candidates: lane/wave threshold x update grid (in resident workgroups)
+  const int32_t mids[] = {8, 16, 32, 64, 128};
+  const int64_t res = ctx->resident[0];
+  const int64_t grids[] = {res, 2 * res, 4 * res};
+  const int64_t save_grid = ctx->max_grid, save_mid = ctx->mid_deg, save_timing = ctx->timing;
+  const bool save_set = ctx->mid_deg_set;
+  const int64_t save_tuned = ctx->use_tuned;
+  int64_t save_launch[PR_KERNEL_KINDS];
+  double save_ms[PR_KERNEL_KINDS];
+  memcpy(save_launch, ctx->stat_launches, sizeof save_launch);
+  memcpy(save_ms, ctx->stat_ms, sizeof save_ms);
+  ctx->use_tuned = 0;
+  ctx->mid_deg_set = true;
+  ctx->timing = 1;
+  double best = 1e300, dflt = 0.0;
+  int32_t best_mid = kMidDeg, best_grid = (int32_t)std::min<int64_t>(res, kMaxGrid);
+  int count = 0;
+  constexpr int kReps = 4;
+  for (int64_t gsz : grids) {
+    if (gsz > kMaxGrid) continue;
+    for (int32_t m : mids) {
+      ctx->max_grid = gsz;
+      ctx->mid_deg = m;
+      ctx->stat_launches[PR_KERNEL_UPDATE_F64] = 0;
+      ctx->stat_ms[PR_KERNEL_UPDATE_F64] = 0.0;
+      pr_result r;
+      rc = pr_pull(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, 0.85, 0.0, PR_L1, kReps, PR_FP64, nullptr,
+                   ranks, nullptr, workspace, workspace_bytes, &r);
+      if (rc < 0) break;
+      const double us = ctx->stat_launches[PR_KERNEL_UPDATE_F64]
+                            ? 1e3 * ctx->stat_ms[PR_KERNEL_UPDATE_F64] / ctx->stat_launches[PR_KERNEL_UPDATE_F64]
+                            : 1e300;
+      ++count;
+      if (gsz == res && m == kMidDeg) dflt = us;
+      if (us < best) {
+        best = us;
+        best_mid = m;
+        best_grid = (int32_t)gsz;
+      }
+    }
+    if (rc < 0) break;
+  }
+  ctx->max_grid = save_grid;
+  ctx->mid_deg = save_mid;
+  ctx->mid_deg_set = save_set;
+  ctx->timing = save_timing;
+  ctx->use_tuned = save_tuned;
+  memcpy(ctx->stat_launches, save_launch, sizeof save_launch);
+  memcpy(ctx->stat_ms, save_ms, sizeof save_ms);
+  if (rc < 0) return rc;
+  const std::vector<int64_t> sig = graph_signature(h);
+  ctx->tuned[sig] = {best_mid, best_grid};
+  save_tune_entry(ctx, sig, best_mid, best_grid);
+  out->mid_deg = best_mid;
+  out->grid = best_grid;
+  out->candidates = count;
+  out->pad = 0;
+  out->best_us = best;
+  out->default_us = dflt;
+  return PR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,428 @@
+// api_solve.hip -- the C ABI of the single and K-column solves: pr_pull (float64, mixed, float32
+// phases) and pr_pull_batch (column compaction between chunks, float32 -> float64 hand-over),
+// and the L1 distance of two rank vectors.
+#include <string.h>
+
+#include <algorithm>
+
+#include "api_internal.h"
+
+extern "C" {
+
+size_t pr_workspace_bytes(int64_t N, int64_t E, int32_t precision, int32_t with_prep) {
+  if (bad_graph_sizes(N, E) || (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32)) return 0;
+  return carve(nullptr, N, E, precision, with_prep != 0).total;
+}
+
+int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+            int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
+            int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
+            size_t workspace_bytes, pr_result *out) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices)) {
+    set_error("pr_pull: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (!(alpha >= 0.0 && alpha <= 1.0)) {
+    set_error("alpha must be in [0, 1], got %g", alpha);
+    return PR_EINVAL;
+  }
+  if (!(tau >= 0.0)) {
+    set_error("tau must be >= 0 and not NaN, got %g", tau);
+    return PR_EINVAL;
+  }
+  if (norm < PR_L1 || norm > PR_LINF) {
+    set_error("norm must be PR_L1, PR_L2 or PR_LINF, got %d", norm);
+    return PR_EINVAL;
+  }
+  if (max_iter < 1) {
+    set_error("max_iter must be >= 1, got %d", max_iter);
+    return PR_EINVAL;
+  }
+  if (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32) {
+    set_error("precision must be PR_FP64, PR_MIXED or PR_FP32, got %d", precision);
+    return PR_EINVAL;
+  }
+  const Layout L = carve(workspace, N, E, precision, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_pull: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc;
+  const void *pp = prep;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
+  const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
+  const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_FP64 ? 0 : 1];
+  const PrepPart &part = h.part[0];
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
+
+  IterParams p{};
+  p.off = in_offsets;
+  p.idx = in_indices;
+  p.outdeg = outdeg;
+  p.desc = (const int4 *)((const char *)pp + part.desc_off);
+  p.ndesc = part.ndesc;
+  p.N = (int32_t)N;
+  p.alpha = alpha;
+  p.tau = tau;
+  p.norm = norm;
+  p.max_iter = max_iter;
+  p.st = L.st;
+  p.bpart = L.bpart;
+  p.hpart = L.hpart;
+  p.hubs = (const int4 *)((const char *)pp + part.hub_off);
+  p.nhubs = part.nhubs;
+  p.grid = (int32_t)grid;
+  p.trace = norm_trace;
+  p.mid_deg = ts.first;
+
+  int fp32_iters = 0, fbuf = 0;
+  const void *final_y = nullptr;
+  bool final_fp32 = false;
+  if (precision == PR_MIXED) {
+    PR_HIP(launch_init(s, true, outdeg, (int32_t)N, init, L.y32[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 1;
+    rc = run_until_stop(ctx, s, update_chunk(ctx, true, grid, p, L.y32[0], L.y32[1]), &L.st->head, max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    fp32_iters = ((LoopHead *)ctx->hstate)->iter;
+    if (((LoopHead *)ctx->hstate)->done) {
+      final_y = L.y32[fbuf];
+      final_fp32 = true;
+    } else {
+      PR_HIP(launch_convert(s, L.y32[fbuf], L.y64[0], (int32_t)N, L.st));
+      p.phase = 2;
+      rc = run_until_stop(ctx, s, update_chunk(ctx, false, grid, p, L.y64[0], L.y64[1]), &L.st->head, max_iter,
+                          &fbuf);
+      if (rc != PR_OK) return rc;
+      final_y = L.y64[fbuf];
+    }
+  } else if (precision == PR_FP32) {
+    // the float32 phase alone, stopping like a float64 solve (tau met or max_iter)
+    PR_HIP(launch_init(s, true, outdeg, (int32_t)N, init, L.y32[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 0;
+    rc = run_until_stop(ctx, s, update_chunk(ctx, true, grid, p, L.y32[0], L.y32[1]), &L.st->head, max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    fp32_iters = ((LoopHead *)ctx->hstate)->iter;
+    final_y = L.y32[fbuf];
+    final_fp32 = true;
+  } else {
+    PR_HIP(launch_init(s, false, outdeg, (int32_t)N, init, L.y64[0], alpha, L.st, L.bpart, kMaxGrid));
+    p.phase = 0;
+    rc = run_until_stop(ctx, s, update_chunk(ctx, false, grid, p, L.y64[0], L.y64[1]), &L.st->head, max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    final_y = L.y64[fbuf];
+  }
+  PR_HIP(launch_output(s, final_fp32, outdeg, final_y, (int32_t)N, ranks));
+  PR_HIP(hipMemcpyAsync(ctx->hstate, L.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  const SolveState &hs = *ctx->hstate;
+  out->iterations = hs.head.iter;
+  out->converged = hs.converged;
+  out->fp32_iters = precision == PR_FP64 ? 0 : fp32_iters;
+  out->fp64_iters = hs.head.iter - out->fp32_iters;
+  out->final_err[0] = hs.err[0];
+  out->final_err[1] = hs.err[1];
+  out->final_err[2] = hs.err[2];
+  return hs.converged ? PR_OK : PR_NOT_CONVERGED;
+}
+
+size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep) {
+  if (bad_graph_sizes(N, E) || K < 1 || K > kMaxCols || (precision != PR_FP64 && precision != PR_MIXED)) return 0;
+  return carve_batch(nullptr, N, E, K, precision, with_prep != 0).total;
+}
+
+int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                  const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
+                  int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
+                  void *workspace, size_t workspace_bytes, pr_result *results) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !probs || !workspace || !results || (E > 0 && !in_indices)) {
+    set_error("pr_pull_batch: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (K < 1 || K > kMaxCols) {
+    set_error("K must be in [1, %d], got %d", kMaxCols, K);
+    return PR_EINVAL;
+  }
+  if (precision != PR_FP64 && precision != PR_MIXED) {
+    set_error("precision must be PR_FP64 or PR_MIXED, got %d", precision);
+    return PR_EINVAL;
+  }
+  for (int k = 0; k < K; ++k) {
+    const pr_problem &q = probs[k];
+    if (!(q.alpha >= 0.0 && q.alpha <= 1.0) || !(q.tau >= 0.0) || q.norm < PR_L1 || q.norm > PR_LINF ||
+        q.max_iter < 1 || !ranks[k]) {
+      set_error("problem %d: alpha in [0,1], tau >= 0, norm 1..3, max_iter >= 1 and a ranks buffer are required", k);
+      return PR_EINVAL;
+    }
+  }
+  const BatchLayout L = carve_batch(workspace, N, E, K, precision, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_pull_batch: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc;
+  const void *pp = prep;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+  int max_iter = 1;
+  for (int k = 0; k < K; ++k) max_iter = std::max(max_iter, probs[k].max_iter);
+
+  const PrepPart &part = h.part[1];
+  BatchParams p{};
+  p.off = in_offsets;
+  p.idx = in_indices;
+  p.outdeg = outdeg;
+  p.desc = (const int4 *)((const char *)pp + part.desc_off);
+  p.ndesc = part.ndesc;
+  p.N = (int32_t)N;
+  p.nhubs = part.nhubs;
+  p.hubs = (const int4 *)((const char *)pp + part.hub_off);
+  p.bpart = L.bpart;
+  p.hpart = L.hpart;
+  p.hacc = L.hacc;
+  p.st = L.st;
+  p.cols = L.cols;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
+  auto grid_of = [&](bool fp32, int kpw) {
+    const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, kpw);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, res, kMaxGrid}));
+  };
+
+  // The running layout: slot i holds original problem orig[i]; `master` keeps every original
+  // problem's latest column state on the host.
+  int orig[kMaxCols];
+  BatchColumn master[kMaxCols];
+  memset(master, 0, sizeof master);
+  int Kc = K;
+  for (int i = 0; i < K; ++i) orig[i] = i;
+  // Write the per-slot parameters (slot order) with the given map/ranks choice and wait for the
+  // copy, so the pinned staging buffer may be rewritten afterwards.
+  auto write_cols = [&](int n, const int *slot_orig, const int *map, bool with_ranks, const bool *rank_sel) -> int {
+    BatchCols &hc = *ctx->hcols;
+    memset(&hc, 0, sizeof hc);
+    for (int i = 0; i < n; ++i) {
+      const int k = slot_orig[i];
+      hc.alpha[i] = probs[k].alpha;
+      hc.tau[i] = probs[k].tau;
+      hc.norm[i] = probs[k].norm;
+      hc.max_iter[i] = probs[k].max_iter;
+      hc.init[i] = init ? init[k] : nullptr;
+      hc.ranks[i] = with_ranks && (!rank_sel || rank_sel[i]) ? ranks[k] : nullptr;
+      hc.trace[i] = norm_trace ? norm_trace[k] : nullptr;
+      hc.map[i] = map ? map[i] : -1;
+    }
+    PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    return PR_OK;
+  };
+  auto stat_chunk = [&](const ChunkSpec &cs, const std::vector<hipEvent_t> *ev, int did) -> int {
+    if (!ev || did <= 0) return PR_OK;
+    float ms = 0.f;
+    for (int k = 0; k < did && k < cs.count; ++k) {
+      PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
+      ctx->stat_ms[cs.kind] += ms;
+      ctx->stat_launches[cs.kind] += 1;
+      ctx->stat_ms[cs.sub_kind] += ms;
+      ctx->stat_launches[cs.sub_kind] += 1;
+    }
+    return PR_OK;
+  };
+
+  const bool mixed = precision == PR_MIXED;
+  const bool fp32 = mixed;  // first phase arithmetic
+  const bool narrow = ctx->narrow != 0;
+  int kp = batch_row_width(Kc, fp32, narrow);
+  void *b0 = fp32 ? (void *)L.y32[0] : (void *)L.y64[0];
+  void *b1 = fp32 ? (void *)L.y32[1] : (void *)L.y64[1];
+  const int kp64 = batch_row_width(K, false, narrow);
+
+  rc = write_cols(Kc, orig, nullptr, false, nullptr);
+  if (rc != PR_OK) return rc;
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(BatchState) / 4, 0u));
+  p.K = Kc;
+  p.phase = mixed ? 1 : 0;
+  p.grid = (int32_t)grid_of(fp32, kp);
+  PR_HIP(launch_batch_init(s, fp32, outdeg, (int32_t)N, Kc, kp, b0, L.bpart, kMaxGrid, p, p.phase));
+
+  // ---- first phase, with compaction of the active columns into narrower rows
+  int before = 0;
+  for (int rounds = 0;; ++rounds) {
+    ChunkSpec cs = batch_chunk(ctx, fp32, kp, (unsigned)p.grid, p, b0, b1);
+    cs.count = (int)ctx->batch_chunk;
+    const std::vector<hipEvent_t> *ev = nullptr;
+    rc = run_chunk(ctx, s, cs, &ev);
+    if (rc != PR_OK) return rc;
+    PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    BatchState &hs = *ctx->hbstate;
+    rc = stat_chunk(cs, ev, hs.head.phase_iter - before);
+    if (rc != PR_OK) return rc;
+    before = hs.head.phase_iter;
+    for (int i = 0; i < Kc; ++i) master[orig[i]] = hs.col[i];
+    if (hs.head.stop) break;
+    if (rounds > max_iter + 2) {
+      set_error("internal: update limit passed without stop");
+      return PR_EDEVICE;
+    }
+    int act[kMaxCols], nact = 0;
+    bool leaving[kMaxCols];
+    for (int i = 0; i < Kc; ++i) {
+      leaving[i] = !hs.col[i].active;
+      if (hs.col[i].active) act[nact++] = i;
+    }
+    const int kp2 = batch_row_width(nact, fp32, narrow);
+    if (ctx->compact == 0 || nact == Kc || kp2 >= kp) continue;
+    // (a) columns leaving the layout: float32 -> their float64 columns (mixed), or final ranks
+    if (mixed) {
+      int map[kMaxCols];
+      for (int i = 0; i < Kc; ++i) map[i] = leaving[i] ? orig[i] : -1;
+      rc = write_cols(Kc, orig, map, false, nullptr);
+      if (rc != PR_OK) return rc;
+      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+                                  L.cols));
+    } else {
+      rc = write_cols(Kc, orig, nullptr, true, leaving);
+      if (rc != PR_OK) return rc;
+      p.K = Kc;
+      PR_HIP(launch_batch_output(s, false, outdeg, b0, b1, kp, (int32_t)N, Kc, p));
+    }
+    // (b) repack the active columns (all at the same parity) into the other buffer
+    const int par = hs.col[act[0]].phase_updates & 1;
+    void *cur = par ? b1 : b0, *oth = par ? b0 : b1;
+    int norig[kMaxCols];
+    for (int i = 0; i < nact; ++i) norig[i] = orig[act[i]];
+    rc = write_cols(nact, norig, act, false, nullptr);
+    if (rc != PR_OK) return rc;
+    PR_HIP(launch_batch_compact(s, fp32, cur, kp, oth, kp2, (int32_t)N, nact, L.cols));
+    // (c) the slot states follow their columns; the repacked buffer becomes buffer 0
+    BatchState ns = hs;
+    for (int i = 0; i < kMaxCols; ++i) {
+      if (i < nact) {
+        ns.col[i] = hs.col[act[i]];
+        ns.col[i].phase_updates = 0;
+      } else {
+        memset(&ns.col[i], 0, sizeof ns.col[i]);
+        ns.col[i].done = 1;
+      }
+    }
+    hs = ns;
+    PR_HIP(hipMemcpyAsync(L.st, &hs, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    Kc = nact;
+    for (int i = 0; i < nact; ++i) orig[i] = norig[i];
+    kp = kp2;
+    b0 = oth;
+    b1 = cur;
+    p.K = Kc;
+    p.grid = (int32_t)grid_of(fp32, kp);
+    before = 0;
+    hs.head.phase_iter = 0;
+    PR_HIP(launch_fill_u32(s, (uint32_t *)&L.st->head.phase_iter, 1, 0u));
+  }
+
+  const BatchColumn *fin = master;
+  if (mixed) {
+    // remaining float32 columns -> float64, then the float64 phase over all K problems
+    int map[kMaxCols];
+    for (int i = 0; i < Kc; ++i) map[i] = orig[i];
+    rc = write_cols(Kc, orig, map, false, nullptr);
+    if (rc != PR_OK) return rc;
+    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+                                L.cols));
+    int all[kMaxCols];
+    for (int i = 0; i < K; ++i) all[i] = i;
+    rc = write_cols(K, all, nullptr, true, nullptr);
+    if (rc != PR_OK) return rc;
+    BatchState &hs = *ctx->hbstate;
+    memset(&hs, 0, sizeof hs);
+    for (int i = 0; i < kMaxCols; ++i) {
+      if (i < K) {
+        hs.col[i] = master[i];
+      } else {
+        hs.col[i].done = 1;
+      }
+    }
+    hs.phase = 2;
+    PR_HIP(hipMemcpyAsync(L.st, &hs, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));
+    PR_HIP(launch_batch_rearm(s, L.st, K));
+    p.K = K;
+    p.phase = 2;
+    p.grid = (int32_t)grid_of(false, kp64);
+    int fbuf = 0;
+    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, kp64, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
+                        max_iter, &fbuf);
+    if (rc != PR_OK) return rc;
+    PR_HIP(launch_batch_output(s, false, outdeg, L.y64[0], L.y64[1], kp64, (int32_t)N, K, p));
+    PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    fin = ctx->hbstate->col;
+  } else {
+    rc = write_cols(Kc, orig, nullptr, true, nullptr);
+    if (rc != PR_OK) return rc;
+    p.K = Kc;
+    PR_HIP(launch_batch_output(s, false, outdeg, b0, b1, kp, (int32_t)N, Kc, p));
+    PR_HIP(hipStreamSynchronize(s));
+  }
+  int all_conv = 1;
+  for (int k = 0; k < K; ++k) {
+    const BatchColumn &c = fin[k];
+    results[k].iterations = c.iters;
+    results[k].converged = c.converged;
+    results[k].fp32_iters = c.fp32_iters;
+    results[k].fp64_iters = c.iters - c.fp32_iters;
+    results[k].final_err[0] = c.err[0];
+    results[k].final_err[1] = c.err[1];
+    results[k].final_err[2] = c.err[2];
+    all_conv &= c.converged;
+  }
+  return all_conv ? PR_OK : PR_NOT_CONVERGED;
+}
+
+int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, int64_t N, void *workspace,
+                   size_t workspace_bytes, double *out) {
+  if (!ctx || !x || !y || !workspace || !out) {
+    set_error("pr_l1_distance: NULL argument");
+    return PR_EINVAL;
+  }
+  if (N < 1) {
+    set_error("pr_l1_distance: N must be >= 1");
+    return PR_EINVAL;
+  }
+  constexpr int32_t nb = 1024;
+  if (workspace_bytes < (nb + 1) * sizeof(double)) {
+    set_error("pr_l1_distance: workspace needs %zu bytes", (size_t)(nb + 1) * sizeof(double));
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  double *part = (double *)workspace;
+  PR_HIP(launch_l1(s, x, y, N, part, nb));
+  PR_HIP(hipMemcpyAsync(ctx->hscratch, part + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  memcpy(out, ctx->hscratch, sizeof(double));
+  return PR_OK;
+}
+
+}  // extern "C"
