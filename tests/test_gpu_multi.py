@@ -133,3 +133,24 @@ def test_barrier_time_limit_ends_the_launch(pr, ctx):
         ctx.set_option("barrier_ms", -1)
     for r, h, p in zip(pr.pull_multi(ctx, graphs, probs), hosts, probs):
         check_column(r, h, p)
+
+
+def test_the_largest_batch_of_graphs(pr, ctx):
+    # G = 4096 (the limit): the graphs' flags are staged in LDS 256 at a time and every graph is
+    # finished by workgroup g % grid; each of them equals its own oracle solve
+    G = 4096
+    rng = np.random.default_rng(2024)
+    hosts, probs = [], []
+    for k in range(G):
+        N = int(rng.integers(1, 120))
+        hosts.append(gg.random_small(N, int(rng.integers(0, 5 * N)), 10000 + k))
+        probs.append(dict(alpha=float(rng.choice([0.5, 0.85, 1.0])), tau=float(rng.choice([1e-6, 1e-10])),
+                          norm=int(rng.integers(1, 4)), max_iter=int(rng.choice([7, 500]))))
+    graphs = [pr.DeviceGraph.from_host(h) for h in hosts]
+    res = pr.pull_multi(ctx, graphs, probs)
+    assert len(res) == G
+    for r, h, p in zip(res, hosts, probs):
+        check_column(r, h, p)
+    with pytest.raises(pr.PrError) as ei:
+        pr.pull_multi(ctx, graphs + graphs[:1], probs + probs[:1])
+    assert ei.value.status == pr._lib.PR_EINVAL
