@@ -38,7 +38,8 @@ Other workloads (one JSON line each, same keys):
                         the sum of 64 sequential solves
   --workload norms      sections 3 and 4 on the same 64 graphs at alpha = 0.85: iterations and
                         times of L1/L2/Linf at tau = 1e-6 with the six composite ratios (tables
-                        3.1/3.2), and the 21-tolerance sweep read off one traced launch
+                        3.1/3.2), the 21-tolerance sweep read off one traced launch, and the same
+                        readout on a 2048 x 2048 road-like lattice (single-iteration stops)
   --workload warmstart  the learned warm start: a network trained on 20 R-MAT scale-20 graphs
                         proposes start vectors for alpha = 0.90/0.95/0.99 on three unseen scale-24
                         graphs; iterations and time from the uniform, alpha=0.85 and learned starts;
@@ -679,6 +680,21 @@ def run_norms(args, pr, gg, np, torch):
         "sensitivity_onset_taus": [[taus[o[j]] for o in onsets if o[j] is not None] for j in range(3)],
         "traced_launch_ms": round(sweep_ms, 3), "traced_launch_GTEPS": round(edges / sweep_ms / 1e6, 2),
     }
+    # section 5's single-iteration convergence on a large road-like graph: a 2048 x 2048 lattice,
+    # one traced solve (L1, the largest of the three errors) read at the 21 tolerances per norm
+    lat = gg.grid2d(2048, 2048)
+    dl = pr.DeviceGraph.from_host(lat, 0).prepare(ctx)
+    rl = pr.pull(ctx, dl, alpha=alpha, tau=min(taus), norm=pr.PR_L1, max_iter=500, trace=True)
+    S = report.stops(rl["trace"].cpu().numpy(), taus)  # [tau][norm]
+    onsets = report.sensitivity(S, 500)
+    singles = report.single_iteration(S)
+    line["road_like"] = {"graph": "2048 x 2048 lattice (each cell linked both ways to its 4 neighbours)",
+                         "N": lat.N, "E": lat.E, "alpha": alpha, "taus": list(taus)}
+    for j, name in enumerate(("L1", "L2", "Linf")):
+        line["road_like"][name] = {"iterations": [int(x) for x in S[:, j]],
+                                   "single_iteration_taus": [taus[i] for i in singles[j]],
+                                   "sensitivity_onset_tau": taus[onsets[j]] if onsets[j] is not None else None}
+    del dl
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(hosts, args.cpu_seconds, "all 64 graphs")
     ctx.close()
