@@ -8,15 +8,26 @@
 
 extern "C" {
 
+constexpr int32_t kMultiInitBlocks = 64;  // workgroups per graph of the start-vector kernels
+
+// Update partial slots: graph g needs one per workgroup that owns one of its tiles, at most
+// min(tiles, grid); bounded here by its largest possible tile count.
+static int64_t multi_slot_bound(int32_t G, const pr_graph_problem *probs) {
+  int64_t n = 0;
+  for (int g = 0; g < G; ++g) n += std::min<int64_t>(max_desc(probs[g].N, probs[g].E, kTile, kRows), kMaxGrid);
+  return n;
+}
+
 static size_t multi_layout(int32_t G, const pr_graph_problem *probs, void *ws, MultiGraph **graphs,
-                           MultiGraphState **states, int32_t **tile_base, double **part, GridBarrier **bar,
-                           double **hpart, double **y, void **preps) {
+                           MultiGraphState **states, int32_t **tile_base, double **part, double **init_part,
+                           GridBarrier **bar, double **hpart, double **y, void **preps) {
   Carver c(ws);
   *bar = (GridBarrier *)c.take(sizeof(GridBarrier));
   *graphs = (MultiGraph *)c.take(sizeof(MultiGraph) * (size_t)G);
   *states = (MultiGraphState *)c.take(sizeof(MultiGraphState) * (size_t)G);
   *tile_base = (int32_t *)c.take(sizeof(int32_t) * (size_t)(G + 1));
-  *part = (double *)c.take(sizeof(double) * 4 * (size_t)kMaxGrid * (size_t)G);
+  *part = (double *)c.take(sizeof(double) * 4 * (size_t)multi_slot_bound(G, probs));
+  *init_part = (double *)c.take(sizeof(double) * kMultiInitBlocks * (size_t)G);
   for (int g = 0; g < G; ++g) {
     hpart[g] = (double *)c.take(sizeof(double) * (size_t)max_slots(probs[g].N, probs[g].E));
     y[2 * g] = (double *)c.take(sizeof(double) * (size_t)probs[g].N);
@@ -33,11 +44,11 @@ size_t pr_multi_workspace_bytes(int32_t G, const pr_graph_problem *probs) {
   MultiGraph *a;
   MultiGraphState *b;
   int32_t *c;
-  double *d;
+  double *d, *d2;
   GridBarrier *e;
   std::vector<double *> hp(G), y(2 * G);
   std::vector<void *> pp(G);
-  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, &e, hp.data(), y.data(), pp.data());
+  return multi_layout(G, probs, nullptr, &a, &b, &c, &d, &d2, &e, hp.data(), y.data(), pp.data());
 }
 
 int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *probs, void *workspace,
@@ -69,12 +80,12 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   MultiGraph *dgraphs;
   MultiGraphState *dstates;
   int32_t *dbase;
-  double *dpart;
+  double *dpart, *dinit;
   GridBarrier *dbar;
   std::vector<double *> hpart(G), ybuf(2 * G);
   std::vector<void *> ownprep(G);
-  const size_t need = multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, &dbar, hpart.data(),
-                                   ybuf.data(), ownprep.data());
+  const size_t need = multi_layout(G, probs, workspace, &dgraphs, &dstates, &dbase, &dpart, &dinit, &dbar,
+                                   hpart.data(), ybuf.data(), ownprep.data());
   if (workspace_bytes < need) {
     set_error("pr_pull_multi: workspace has %zu bytes, needs %zu", workspace_bytes, need);
     return PR_ENOMEM;
@@ -123,6 +134,22 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     }
     base[g + 1] = (int32_t)total_tiles;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
+  const int64_t resident = (int64_t)cus * multi_blocks_per_cu();
+  int64_t grid = ctx->max_grid > 0 ? std::min<int64_t>(ctx->max_grid, resident) : resident;
+  grid = std::max<int64_t>(1, std::min<int64_t>({grid, total_tiles > 0 ? total_tiles : 1, (int64_t)kMaxGrid}));
+  // partial slots: graph g's min(tiles, grid) workgroups, one slot each, graph after graph
+  int64_t nslot = 0;
+  for (int g = 0; g < G; ++g) {
+    hg[g].pslot = (int32_t)nslot;
+    nslot += std::min<int64_t>(base[g + 1] - base[g], grid);
+  }
+  if (nslot > multi_slot_bound(G, probs)) {
+    set_error("internal: %lld partial slots exceed the workspace's %lld", (long long)nslot,
+              (long long)multi_slot_bound(G, probs));
+    return PR_EDEVICE;
+  }
   // stage the tables through pinned memory (synchronised before the buffer is reused)
   const size_t tbytes = sizeof(MultiGraph) * (size_t)G + sizeof(int32_t) * (size_t)(G + 1);
   if (ctx->hmulti_bytes < tbytes) {
@@ -143,6 +170,7 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   p.states = dstates;
   p.tile_base = dbase;
   p.part = dpart;
+  p.init_part = dinit;
   p.bar = dbar;
   {
     int khz = 0;  // wall clock of the device (s_memrealtime), 100 MHz on this GPU family
@@ -153,11 +181,6 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   p.G = G;
   p.total_tiles = (int32_t)total_tiles;
   p.max_rounds = max_rounds;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
-  const int64_t resident = (int64_t)cus * multi_blocks_per_cu();
-  int64_t grid = ctx->max_grid > 0 ? std::min<int64_t>(ctx->max_grid, resident) : resident;
-  grid = std::max<int64_t>(1, std::min<int64_t>({grid, total_tiles > 0 ? total_tiles : 1, (int64_t)kMaxGrid}));
   EventPair ev;  // destroyed on every return
   if (ctx->timing) {
     PR_HIP(hipEventCreate(&ev.a));
@@ -165,7 +188,7 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
     PR_HIP(hipEventRecord(ev.a, s));
   }
   PR_HIP(launch_fill_u32(s, (uint32_t *)dbar, sizeof(GridBarrier) / 4, 0u));
-  PR_HIP(launch_multi(s, (unsigned)grid, p, 64));
+  PR_HIP(launch_multi(s, (unsigned)grid, p, kMultiInitBlocks));
   if (ctx->timing) PR_HIP(hipEventRecord(ev.b, s));
   std::vector<MultiGraphState> hs(G);
   uint32_t timed_out = 0;

@@ -23,7 +23,7 @@ struct MultiGraph {
   int32_t norm;
   int32_t max_iter;
   int32_t mid_deg;
-  int32_t pad;
+  int32_t pslot;       // first of its min(tiles, grid) update partial slots in MultiParams::part
 };
 
 struct MultiGraphState {
@@ -52,7 +52,8 @@ struct MultiParams {
   const MultiGraph *graphs;
   MultiGraphState *states;
   const int32_t *tile_base;  // [G+1]: first global tile of each graph
-  double *part;              // [grid][G][4] per-workgroup partials (also init scratch)
+  double *part;              // [slots][4]: graph g's update partials from slot graphs[g].pslot on
+  double *init_part;         // [G][init blocks]: dangling sums of the start vectors
   GridBarrier *bar;
   uint64_t wait_ticks;       // time limit of a barrier wait, in wall-clock ticks
   int32_t G;

@@ -103,13 +103,15 @@ __device__ bool grid_barrier(GridBarrier *b, const BarSlot &slot, uint32_t k, ui
   return !__syncthreads_or(!ok);
 }
 
-__device__ __forceinline__ void flush_acc(const MultiParams &p, int g, Acc &a, double *red) {
+// The workgroup's partials of graph g into its slot k (its rank among the workgroups that own a
+// tile of g: k = first tile - the graph's first tile).
+__device__ __forceinline__ void flush_acc(const MultiParams &p, int64_t slot, Acc &a, double *red) {
   const double l1 = block_sum_n<kBlock>(a.l1, red);
   const double sq = block_sum_n<kBlock>(a.sq, red);
   const double mx = block_max_n<kBlock>(a.mx, red);
   const double dang = block_sum_n<kBlock>(a.dang, red);
   if (threadIdx.x == 0) {
-    double *bp = p.part + ((int64_t)blockIdx.x * p.G + g) * 4;
+    double *bp = p.part + slot * 4;
     bp[0] = l1;
     bp[1] = sq;
     bp[2] = mx;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
         c.mid_deg = mg.mid_deg;
         Acc a = {0.0, 0.0, 0.0, 0.0};
         for (int32_t gi = first; gi < end; gi += nblk) update_tile<double>(c, mg.desc[gi - base], mg.desc[gi - base + 1], a, vals, red);
-        flush_acc(p, g, a, red);
+        flush_acc(p, (int64_t)mg.pslot + (first - base), a, red);
       }
     }
     if (!grid_barrier(p.bar, slot, ++nbar, p.wait_ticks)) break;
@@ -186,8 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
       const int32_t base = p.tile_base[g], ntiles = p.tile_base[g + 1] - base;
       const int32_t nb = ntiles >= (int32_t)gridDim.x ? (int32_t)gridDim.x : ntiles;
       for (int32_t k = t; k < nb; k += kBlock) {
-        const int32_t b = (base + k) % (int32_t)gridDim.x;
-        const double *bp = p.part + ((int64_t)b * p.G + g) * 4;
+        const double *bp = p.part + ((int64_t)mg.pslot + k) * 4;
         f.l1 += bp[0];
         f.sq += bp[1];
         f.mx = fmax(f.mx, bp[2]);
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_multi_init(MultiParams p) {
     }
   }
   dang = block_sum(dang, red);
-  if (threadIdx.x == 0) p.part[(int64_t)g * gridDim.x + blockIdx.x] = dang;
+  if (threadIdx.x == 0) p.init_part[(int64_t)g * gridDim.x + blockIdx.x] = dang;
 }
 
 __global__ __launch_bounds__(kBlock) void k_multi_init_finish(MultiParams p, int32_t nb) {
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_multi_init_finish(MultiParams p, int
   const int g = blockIdx.x;
   const MultiGraph &mg = p.graphs[g];
   double D = 0.0;
-  for (int32_t b = threadIdx.x; b < nb; b += kBlock) D += p.part[(int64_t)g * nb + b];
+  for (int32_t b = threadIdx.x; b < nb; b += kBlock) D += p.init_part[(int64_t)g * nb + b];
   D = block_sum(D, red);
   if (threadIdx.x == 0) {
 #pragma clang fp contract(off)
