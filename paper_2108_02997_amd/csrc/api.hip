@@ -254,7 +254,7 @@ ChunkSpec update_chunk(pr_ctx *ctx, bool fp32, unsigned grid, const IterParams &
 // once K > 8: a row fetch then touches exactly one 64-byte line.
 int batch_row_width(int K, bool fp32, bool narrow) {
   if (narrow && K <= 2) return K < 1 ? 1 : K;
-  if (fp32 && K > 8) return 16;
+  if (fp32 && K > 12) return 16;
   return 4 * ((K + 3) / 4);
 }
 

@@ -95,8 +95,20 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
   }
 }
 
+// Waves per SIMD the float32 update of a row width is compiled for (its registers are capped to
+// fit them; one workgroup puts one wave on each SIMD).  The update is bound by row fetches in
+// flight, so more resident waves pay until the cap makes the compiler spill much (12 values at
+// 6 waves and 8 values at 8 lose; the 12-byte spill of 8 values at 6 waves still wins) or LDS
+// admits no more workgroups (16 values: 4).  Measured on the scale-24 R-MAT alpha sweep;
+// 1 = no cap (1 and 2 values stay under 64 registers by themselves; float64 rows are bound by
+// LDS first).
 template <typename VT, int KP>
-__global__ __launch_bounds__(kBlock, (sizeof(VT) == 4 && KP == 16) ? 4 : 1) void k_batch_update(BatchParams p) {
+constexpr int update_waves() {
+  return sizeof(VT) != 4 ? 1 : KP == 16 ? 4 : KP == 12 ? 5 : KP == 8 ? 6 : KP == 4 ? 7 : 1;
+}
+
+template <typename VT, int KP>
+__global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_update(BatchParams p) {
   constexpr int G = RowShape<KP>::G, C = RowShape<KP>::C;
   constexpr int kQuads = kBlock / G;                        // groups per block (64, 128, 256)
   constexpr int kGW = 64 / G;                               // groups per wave

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 # gc_run kinds by bytes fetched per entry (float32, float64, 16/32/64-byte rows)
-ROW_KINDS = {4: 1, 8: 0, 16: 3, 32: 4, 64: 5}
+ROW_KINDS = {4: 1, 8: 0, 16: 3, 32: 4, 48: 6, 64: 5}
 
 
 def load():
@@ -105,9 +105,12 @@ def main():
     rows.append(run(0, y64, "float64 per entry", 12 * E))
     rows.append(run(1, y64.float(), "float32 per entry", 8 * E))
     del y64
-    for q, kind in ((1, 3), (2, 4), (4, 5)):
+    for q, kind in ((1, 3), (2, 4), (3, 6), (4, 5)):
         Y = torch.rand(N * 4 * q, dtype=torch.float32, device="cuda")
         rows.append(run(kind, Y, "%d-byte row per entry" % (16 * q), (4 + 16 * q) * E))
+        if q == 3:
+            rows.append(run(7, Y, "48-byte row, 4 lanes x 12 B", 52 * E))
+            rows.append(run(8, Y, "48-byte row, 3 of 4 lanes x 16 B", 52 * E))
         del Y
 
     # the solver's update kernels on the same graph, event-timed per launch
@@ -124,7 +127,7 @@ def main():
         ctx.set_option("timing", 0)
         n, ms = ctx.stats(kind)
         kernels.append({"kernel": name, "us": round(1e3 * ms / n, 1)})
-    for K, W in ((1, 1), (2, 2), (4, 4), (8, 8), (11, 16)):
+    for K, W in ((1, 1), (2, 2), (4, 4), (8, 8), (11, 12), (16, 16)):
         probs = [dict(alpha=0.85, tau=1e-30, norm=3, max_iter=6)] * K
         pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
         ctx.reset_stats()

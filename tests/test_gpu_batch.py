@@ -100,7 +100,7 @@ def test_per_column_starts(pr, ctx):
         check_column(r, g, p, init=s0)
 
 
-@pytest.mark.parametrize("K", [1, 2, 7])
+@pytest.mark.parametrize("K", [1, 2, 7, 11])
 def test_hubs_in_batch(pr, ctx, K):
     rng = np.random.default_rng(9)
     N = 40000
@@ -116,9 +116,12 @@ def test_hubs_in_batch(pr, ctx, K):
     for r, p in zip(pr.pull_batch(ctx, dg, probs), probs):
         check_column(r, g, p)
     for r, p in zip(pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED), probs):
+        assert r["converged"], p
+        if p["alpha"] == 1.0:
+            continue  # the contraction bound alpha/(1-alpha) has no finite form at alpha = 1
         ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"])
         d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
-        assert r["converged"] and d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
+        assert d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
 
 
 def test_batch_repeatable(pr, ctx):
