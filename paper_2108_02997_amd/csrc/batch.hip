@@ -62,10 +62,11 @@ struct BAcc {
   double l1, sq, mx, dang;
 };
 
-// Per-column epilogue of one row for the lane's C columns.
+// Per-column epilogue of one row for the lane's C columns; yo holds the row's current values of
+// those columns (fetched by the caller, in the tile path together with the gathered rows).
 // c0 and alpha point at the teleport terms and damping factors of the lane's C columns.
 template <typename VT, int C>
-__device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VT *__restrict__ yin,
+__device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VT (&yold)[C],
                                                VT *__restrict__ yout, int kp, int col0, const double *c0,
                                                const double *alpha, const bool (&act)[C], BAcc (&a)[C]) {
 #pragma clang fp contract(off)
@@ -74,7 +75,7 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
   for (int c = 0; c < C; ++c) {
     if (!act[c]) continue;
     const double rn = c0[c] + alpha[c] * s[c];
-    const VT yo = yin[base + c];
+    const VT yo = yold[c];
     double old, rnew;
     if (dv > 0) {
       old = (double)yo * (double)dv;
@@ -180,6 +181,19 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
           for (int c = 0; c < C; ++c) x[k].v[c] = (VT)0;
         }
       }
+      // the current values of the group's own rows, in flight with the gather (the epilogue
+      // would otherwise wait for them after the row sums)
+      Row<VT, C> yo[kRowsQ];
+#pragma unroll
+      for (int q = 0; q < kRowsQ; ++q) {
+        const int32_t v = v0 + quad + q * kQuads;
+        if (v < v1) {
+          yo[q] = load_row<VT, C>(yin, v, KP, col0);
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) yo[q].v[c] = (VT)0;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < kPerQ; ++k) {
         const int32_t j = quad + k * kQuads;
@@ -205,7 +219,7 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
           double sd[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) sd[c] = (double)s[c];
-          batch_epilogue<VT, C>(v, sd, dv[q], yin, yout, KP, col0, c0, alpha, act, a);
+          batch_epilogue<VT, C>(v, sd, dv[q], yo[q].v, yout, KP, col0, c0, alpha, act, a);
         }
         unsigned long long m = __ballot(mid && qp == 0);
         while (m) {
@@ -221,9 +235,13 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
             for (int c = 0; c < C; ++c) s[c] += vals[j * KP + col0 + c];
           }
           double sd[C];
+          VT wo[C];  // the row's current values, from the group that owns it
 #pragma unroll
-          for (int c = 0; c < C; ++c) sd[c] = (double)xor_sum_groups<G>(s[c]);
-          if (lane < G) batch_epilogue<VT, C>(wv, sd, wd, yin, yout, KP, col0, c0, alpha, act, a);
+          for (int c = 0; c < C; ++c) {
+            sd[c] = (double)xor_sum_groups<G>(s[c]);
+            wo[c] = __shfl(yo[q].v[c], src + qp, 64);
+          }
+          if (lane < G) batch_epilogue<VT, C>(wv, sd, wd, wo, yout, KP, col0, c0, alpha, act, a);
         }
       }
       __syncthreads();
@@ -276,7 +294,8 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
         }
         if (slot < 0) {
           // one-segment long row: finish here
-          batch_epilogue<VT, C>(v, segd, p.outdeg[v], yin, yout, KP, col0, c0, alpha, act, a);
+          const Row<VT, C> o = load_row<VT, C>(yin, v, KP, col0);
+          batch_epilogue<VT, C>(v, segd, p.outdeg[v], o.v, yout, KP, col0, c0, alpha, act, a);
         } else {
 #pragma unroll
           for (int c = 0; c < C; ++c) p.hpart[(int64_t)slot * KP + col0 + c] = segd[c];
@@ -336,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
     bool act[1] = {true};
     BAcc aa[1] = {a};
     // the epilogue addresses column k of row hb.x
-    batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yin, yout, KP, k, &c0, &alpha, act, aa);
+    const VT yo[1] = {yin[(int64_t)hb.x * KP + k]};
+    batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yo, yout, KP, k, &c0, &alpha, act, aa);
     a = aa[0];
   }
   sacc[j][k][0] = a.l1;
