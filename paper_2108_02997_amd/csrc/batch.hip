@@ -98,11 +98,11 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
 
 // Waves per SIMD the float32 update of a row width is compiled for (its registers are capped to
 // fit them; one workgroup puts one wave on each SIMD).  The update is bound by row fetches in
-// flight, so more resident waves pay until the cap makes the compiler spill much (12 values at
-// 6 waves and 8 values at 8 lose; the 12-byte spill of 8 values at 6 waves still wins) or LDS
-// admits no more workgroups (16 values: 4).  Measured on the scale-24 R-MAT alpha sweep;
-// 1 = no cap (1 and 2 values stay under 64 registers by themselves; float64 rows are bound by
-// LDS first).
+// flight, so more resident waves pay as long as the cap forces only a small spill (12-20 bytes
+// per lane at these settings); 12 values at 6 waves and 8 values at 8 spilled more and lost, and
+// LDS admits no more than 4 workgroups of 16 values.  Measured on the scale-24 R-MAT alpha
+// sweep; 1 = no cap (1 and 2 values stay under 64 registers by themselves; float64 rows are
+// bound by LDS first).
 template <typename VT, int KP>
 constexpr int update_waves() {
   return sizeof(VT) != 4 ? 1 : KP == 16 ? 4 : KP == 12 ? 5 : KP == 8 ? 6 : KP == 4 ? 7 : 1;

@@ -3,7 +3,8 @@
 
 Runs, on the in-edge index array of a seeded R-MAT graph (default: scale 24, seed 24, the
 benchmark's graph), the bare accesses of an update -- the index stream alone, a float64 or float32
-scalar per entry, a 16/32/64-byte row per entry -- and, for comparison, the update kernels of
+scalar per entry, a 16/32/48/64-byte row per entry (48-byte rows also as 4 lanes x 12 bytes and as
+3 of 4 lanes x 16 bytes) -- and, for comparison, the update kernels of
 libprpull.so on the same graph (event-timed, pr_get_stats).  Prints one JSON line.
 Not part of the solver; the oracle is not used.
 """
@@ -18,7 +19,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-# gc_run kinds by bytes fetched per entry (float32, float64, 16/32/64-byte rows)
+# gc_run kinds by bytes fetched per entry (float32, float64, 16/32/48/64-byte rows)
 ROW_KINDS = {4: 1, 8: 0, 16: 3, 32: 4, 48: 6, 64: 5}
 
 

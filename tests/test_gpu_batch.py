@@ -262,5 +262,7 @@ def test_narrow_rows_against_oracle(pr, ctx, precision):
             # starts at width K; a column that stops leaves the other on width 1
             assert by_width[K] > 0 and all(n == 0 for w, n in by_width.items() if w > K), by_width
         else:
-            # the sweep ends with its slowest one or two columns
+            # ten columns start on rows of 12 values (4 * ceil(K / 4), never padded to 16) and the
+            # sweep ends with its slowest one or two columns
+            assert by_width[12] > 0 and by_width[16] == 0, by_width
             assert by_width[1] + by_width[2] > 0, by_width
