@@ -136,6 +136,36 @@ def mixed_bound(alpha, e_gpu, e_ref):
     return alpha / (1 - alpha) * (e_gpu + e_ref) + 1e-13
 
 
+@pytest.mark.parametrize("K", [9, 12])
+def test_mixed_settings_on_twelve_value_rows(pr, ctx, K):
+    # 9 to 12 float32 columns share rows of 12 values (three per lane of a four-lane group);
+    # random settings, some columns halted by max_iter inside the float32 phase
+    g = gg.rmat(13, seed=100 + K)
+    dg = pr.DeviceGraph.from_host(g)
+    rng = np.random.default_rng(100 + K)
+    probs = [dict(alpha=float(rng.choice([0.5, 0.85, 0.95])), tau=float(rng.choice([1e-6, 1e-9, 1e-11])),
+                  norm=int(rng.integers(1, 4)), max_iter=int(rng.choice([3, 500]))) for _ in range(K)]
+    ctx.reset_stats()
+    ctx.set_option("timing", 1)
+    try:
+        res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
+    finally:
+        ctx.set_option("timing", 0)
+    assert ctx.stats(pr._lib.batch_kind(True, 12))[0] > 0
+    assert ctx.stats(pr._lib.batch_kind(True, 16))[0] == 0
+    for r, p in zip(res, probs):
+        ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"], max_iter=p["max_iter"])
+        d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
+        assert r["fp32_iters"] + r["fp64_iters"] == r["iterations"]
+        if p["max_iter"] == 3:
+            # stopped by max_iter in the float32 phase: three float32 updates of the oracle's map
+            assert r["iterations"] == 3 and r["fp32_iters"] == 3 and not r["converged"], (p, r)
+            assert d <= 5e-5, (p, d)
+        else:
+            assert r["converged"] and r["err"][p["norm"] - 1] < p["tau"], (p, r)
+            assert d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
+
+
 @pytest.mark.parametrize("norm,tau", [(1, 1e-10), (3, 1e-10), (2, 1e-8), (1, 1e-4)])
 def test_mixed_single_against_oracle(pr, ctx, norm, tau):
     g = gg.rmat(15, seed=5)
