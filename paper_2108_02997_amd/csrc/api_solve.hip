@@ -299,7 +299,7 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
       for (int i = 0; i < Kc; ++i) map[i] = leaving[i] ? orig[i] : -1;
       rc = write_cols(Kc, orig, map, false, nullptr);
       if (rc != PR_OK) return rc;
-      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[1], (int32_t)N, Kc, L.st,
                                   L.cols));
     } else {
       rc = write_cols(Kc, orig, nullptr, true, leaving);
@@ -348,8 +348,11 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     for (int i = 0; i < Kc; ++i) map[i] = orig[i];
     rc = write_cols(Kc, orig, map, false, nullptr);
     if (rc != PR_OK) return rc;
-    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[0], kp64, (int32_t)N, Kc, L.st,
+    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[1], (int32_t)N, Kc, L.st,
                                 L.cols));
+    // every column is now in the column-major staging (the second float64 buffer, idle until
+    // the float64 phase): lay them out as the phase's rows in the first
+    PR_HIP(launch_batch_rows(s, L.y64[1], L.y64[0], kp64, (int32_t)N, K));
     int all[kMaxCols];
     for (int i = 0; i < K; ++i) all[i] = i;
     rc = write_cols(K, all, nullptr, true, nullptr);

@@ -113,8 +113,11 @@ hipError_t launch_batch_update(hipStream_t s, bool fp32, int kp, unsigned grid, 
 int batch_blocks_per_cu(bool fp32, int kp);
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase);
-hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
-                                int32_t kp64, int32_t N, int32_t K, const BatchState *st, const BatchCols *cols);
+// Columns leaving the float32 phase go to a column-major float64 staging area ycol[column][N]
+// (whole-line stores); launch_batch_rows then lays all K columns out as the float64 phase's rows.
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *ycol,
+                                int32_t N, int32_t K, const BatchState *st, const BatchCols *cols);
+hipError_t launch_batch_rows(hipStream_t s, const double *ycol, double *y64, int32_t kp64, int32_t N, int32_t K);
 hipError_t launch_batch_rearm(hipStream_t s, BatchState *st, int32_t K);
 hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32_t kp_src, void *dst, int32_t kp_dst,
                                 int32_t N, int32_t K, const BatchCols *cols);

@@ -533,18 +533,42 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_init_finish(const double *_
   }
 }
 
-// Float32 columns -> float64 columns: column c (its newest buffer by its update parity) goes to
-// float64 column map[c] (skipped when map[c] < 0).  Lanes keep one column (coalesced reads).
+// Float32 columns -> float64 staging, column-major: column c (its newest buffer by its update
+// parity) goes to ycol[map[c]][0..N) (skipped when map[c] < 0).  One lane per row, the columns in
+// turn, so that each column's stores are contiguous: whole lines, where stores of single values
+// into the float64 rows would rewrite every line of those rows in part.
 __global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restrict__ y32a, const float *__restrict__ y32b,
-                                                          int32_t kp32, double *__restrict__ y64, int32_t kp64,
-                                                          int32_t N, int32_t K, const BatchState *st,
-                                                          const BatchCols *cols) {
-  const ColLane cl = col_lane(kp32);
-  if (!cl.on || cl.c >= K) return;
-  const int c = cl.c, d = cols->map[c];
-  if (d < 0) return;
-  const float *__restrict__ src = (st->col[c].phase_updates & 1) ? y32b : y32a;
-  for (int64_t v = cl.v; v < N; v += cl.vstep) y64[v * kp64 + d] = (double)src[v * kp32 + c];
+                                                          int32_t kp32, double *__restrict__ ycol, int32_t N, int32_t K,
+                                                          const BatchState *st, const BatchCols *cols) {
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    for (int c = 0; c < K; ++c) {
+      const int d = cols->map[c];
+      if (d < 0) continue;
+      const float *__restrict__ src = (st->col[c].phase_updates & 1) ? y32b : y32a;
+      ycol[(int64_t)d * N + v] = (double)src[v * kp32 + c];
+    }
+  }
+}
+
+// Staging ycol[K][N] -> rows y64[N][kp64] of the float64 phase (padding columns zero), through an
+// LDS tile of kRowsT rows so that reads and stores are both contiguous.
+constexpr int kRowsT = 64;
+__global__ __launch_bounds__(kBlock) void k_batch_rows(const double *__restrict__ ycol, double *__restrict__ y64,
+                                                       int32_t kp64, int32_t N, int32_t K) {
+  __shared__ double tile[16][kRowsT + 1];
+  for (int64_t v0 = (int64_t)blockIdx.x * kRowsT; v0 < N; v0 += (int64_t)gridDim.x * kRowsT) {
+    const int rows = (int)(N - v0 < kRowsT ? N - v0 : kRowsT);
+    for (int i = threadIdx.x; i < kp64 * kRowsT; i += kBlock) {
+      const int k = i / kRowsT, r = i % kRowsT;
+      if (r < rows) tile[k][r] = k < K ? ycol[(int64_t)k * N + v0 + r] : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows * kp64; i += kBlock) {
+      const int r = i / kp64, k = i % kp64;
+      y64[(v0 + r) * kp64 + k] = tile[k][r];
+    }
+    __syncthreads();
+  }
 }
 
 // Repack: column i of dst (i < K) is column map[i] of src; padding columns are zero.  Lanes keep
@@ -676,10 +700,18 @@ hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, in
   return hipGetLastError();
 }
 
-hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *y64,
-                                int32_t kp64, int32_t N, int32_t K, const BatchState *st, const BatchCols *cols) {
-  hipLaunchKernelGGL(k_batch_convert, dim3(grid_for((int64_t)N * kp32, 8192)), dim3(kBlock), 0, s, y32a, y32b, kp32,
-                     y64, kp64, N, K, st, cols);
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *ycol,
+                                int32_t N, int32_t K, const BatchState *st, const BatchCols *cols) {
+  hipLaunchKernelGGL(k_batch_convert, dim3(grid_for(N, 8192)), dim3(kBlock), 0, s, y32a, y32b, kp32, ycol, N, K, st,
+                     cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(hipStream_t s, const double *ycol, double *y64, int32_t kp64, int32_t N, int32_t K) {
+  if (kp64 < 1 || kp64 > 16 || K > kp64) return hipErrorInvalidValue;
+  const int64_t tiles = ((int64_t)N + kRowsT - 1) / kRowsT;
+  hipLaunchKernelGGL(k_batch_rows, dim3((unsigned)(tiles < 1 ? 1 : tiles > 8192 ? 8192 : tiles)), dim3(kBlock), 0, s,
+                     ycol, y64, kp64, N, K);
   return hipGetLastError();
 }
 
