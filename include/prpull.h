@@ -96,7 +96,7 @@ const char *pr_version(void);
  *   "mid_deg": rows of at most this many in-edges are summed by one lane, longer rows (up to the
  *             1024-entry tile window) by a whole wave64, 0..1024 (default 32)
  *   "tuned" : 1 (default) = use the autotuner's choice for graphs it has seen (pr_autotune)
- *   "batch_chunk": updates of pr_pull_batch between two host checks, 1..64 (default 2)
+ *   "batch_chunk": updates of pr_pull_batch between two host checks, even, 2..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
  *   "barrier_ms": time limit of one grid-barrier wait of pr_pull_multi in milliseconds, 0..600000

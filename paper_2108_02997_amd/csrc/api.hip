@@ -250,11 +250,11 @@ ChunkSpec update_chunk(pr_ctx *ctx, bool fp32, unsigned grid, const IterParams &
 }
 
 // Row width (values per vertex) of the batch state for K columns: 1 or 2 (narrow rows, one lane
-// per row fetch), else 4, 8, 12 or 16.  For float32 a 64-byte row is preferred over a 48-byte one
-// once K > 8: a row fetch then touches exactly one 64-byte line.
+// per row fetch), else 4 * ceil(K / 4) = 4, 8, 12 or 16, in either precision (a random 48-byte
+// float32 row costs less than a 64-byte one, so 9 to 12 columns are not padded to 16).
 int batch_row_width(int K, bool fp32, bool narrow) {
+  (void)fp32;
   if (narrow && K <= 2) return K < 1 ? 1 : K;
-  if (fp32 && K > 12) return 16;
   return 4 * ((K + 3) / 4);
 }
 
@@ -439,8 +439,10 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
     }
     ctx->use_tuned = value;
   } else if (!strcmp(key, "batch_chunk")) {
-    if (value < 1 || value > 64) {
-      set_error("batch_chunk must be in [1, 64]");
+    // even: the updates of a chunk alternate the two row buffers from the first, so every chunk
+    // must end on the buffer it started from
+    if (value < 2 || value > 64 || (value & 1)) {
+      set_error("batch_chunk must be even and in [2, 64]");
       return PR_EINVAL;
     }
     ctx->batch_chunk = value;

@@ -226,6 +226,33 @@ def test_compaction_changes_nothing(pr, ctx, precision):
         assert torch.equal(r0, r1)
 
 
+def test_batch_chunk_sizes_agree(pr, ctx):
+    # The host looks at the columns every batch_chunk updates (the compaction points).  Any even
+    # chunk gives the same result (grid pinned, rows of four or more values, as above); an odd
+    # one is rejected, since the updates of a chunk alternate the two row buffers from the first.
+    g = gg.rmat(13, seed=41)
+    dg = pr.DeviceGraph.from_host(g)
+    probs = sweep_problems(tau=1e-10, norm=1)[:-1]
+    out = []
+    try:
+        ctx.set_option("grid", 300)
+        ctx.set_option("narrow", 0)
+        for bc in (2, 4, 6, 64):
+            ctx.set_option("batch_chunk", bc)
+            res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
+            out.append([(r["iterations"], r["fp32_iters"], r["ranks"].clone()) for r in res])
+        for bad in (0, 1, 3, 65, 66):
+            with pytest.raises(pr.PrError):
+                ctx.set_option("batch_chunk", bad)
+    finally:
+        ctx.set_option("batch_chunk", 2)
+        ctx.set_option("narrow", 1)
+        ctx.set_option("grid", 0)
+    for o in out[1:]:
+        for (i0, f0, r0), (i1, f1, r1) in zip(out[0], o):
+            assert i0 == i1 and f0 == f1 and torch.equal(r0, r1)
+
+
 def test_compaction_with_traces_and_max_iter(pr, ctx):
     g = gg.rmat(13, seed=22)
     dg = pr.DeviceGraph.from_host(g)
