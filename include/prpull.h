@@ -99,6 +99,10 @@ const char *pr_version(void);
  *   "batch_chunk": updates of pr_pull_batch between two host checks, even, 2..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
  *             remaining ones into narrower rows (fewer bytes per edge); 0 = keep the layout
+ *   "handover32": 1 (default) = when no column of a PR_MIXED pr_pull_batch stopped at max_iter
+ *             in its float32 phase, the first float64 update reads the float32 rows themselves
+ *             (exact in float64, half the bytes per edge) and sums in float64; the result is
+ *             bitwise the one of 0 = first lay the columns out as float64 rows
  *   "barrier_ms": time limit of one grid-barrier wait of pr_pull_multi in milliseconds, 0..600000
  *             (default 5000); a wait that passes it ends the launch with PR_EDEVICE
  *   "narrow": 1 (default) = one or two columns of pr_pull_batch run on rows of one or two values;

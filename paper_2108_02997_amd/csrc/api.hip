@@ -452,6 +452,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->compact = value;
+  } else if (!strcmp(key, "handover32")) {
+    if (value != 0 && value != 1) {
+      set_error("handover32 must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->handover32 = value;
   } else if (!strcmp(key, "narrow")) {
     if (value != 0 && value != 1) {
       set_error("narrow must be 0 or 1");

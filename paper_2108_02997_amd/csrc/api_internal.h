@@ -91,6 +91,7 @@ struct pr_ctx {
   std::string tune_file;
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
+  int64_t handover32 = 1;   // 1: the first float64 update of a mixed batch reads float32 rows
   int64_t barrier_ms = 5000;  // time limit of a grid-barrier wait in pr_pull_multi
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};

@@ -299,8 +299,8 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
       for (int i = 0; i < Kc; ++i) map[i] = leaving[i] ? orig[i] : -1;
       rc = write_cols(Kc, orig, map, false, nullptr);
       if (rc != PR_OK) return rc;
-      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[1], (int32_t)N, Kc, L.st,
-                                  L.cols));
+      PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, (float *)L.y64[1], (int32_t)N, Kc,
+                                  L.st, L.cols));
     } else {
       rc = write_cols(Kc, orig, nullptr, true, leaving);
       if (rc != PR_OK) return rc;
@@ -348,11 +348,19 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     for (int i = 0; i < Kc; ++i) map[i] = orig[i];
     rc = write_cols(Kc, orig, map, false, nullptr);
     if (rc != PR_OK) return rc;
-    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, L.y64[1], (int32_t)N, Kc, L.st,
-                                L.cols));
-    // every column is now in the column-major staging (the second float64 buffer, idle until
-    // the float64 phase): lay them out as the phase's rows in the first
-    PR_HIP(launch_batch_rows(s, L.y64[1], L.y64[0], kp64, (int32_t)N, K));
+    PR_HIP(launch_batch_convert(s, (const float *)b0, (const float *)b1, kp, (float *)L.y64[1], (int32_t)N, Kc,
+                                L.st, L.cols));
+    // Every column is now in the column-major staging (the second float64 buffer, idle until the
+    // float64 phase).  When every column goes on to the float64 phase, they are laid out as
+    // float32 rows (the float32 buffers are free now) and the phase's first update reads those:
+    // their float64 values are exact, so the update is the float64 one at half the bytes per
+    // edge.  Otherwise (a column stopped by max_iter keeps its iterate in the float64 rows) as
+    // float64 rows in the first buffer.
+    bool live = true;
+    for (int i = 0; i < K; ++i) live = live && !master[i].done;
+    const bool rows32 = live && ctx->handover32 != 0;
+    PR_HIP(launch_batch_rows(s, (const float *)L.y64[1], rows32 ? (void *)L.y32[0] : (void *)L.y64[0], !rows32, kp64,
+                             (int32_t)N, K));
     int all[kMaxCols];
     for (int i = 0; i < K; ++i) all[i] = i;
     rc = write_cols(K, all, nullptr, true, nullptr);
@@ -372,11 +380,47 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     PR_HIP(launch_batch_rearm(s, L.st, K));
     p.K = K;
     p.phase = 2;
+    void *f0 = L.y64[0], *f1 = L.y64[1];
+    bool stopped = false;
+    if (rows32) {
+      // the first float64 update: float32 rows in, float64 rows out to the second buffer, so that
+      // every column's update parity (1) names that buffer and the later updates start from it
+      BatchParams q = p;
+      const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu_f32rows(kp64);
+      q.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, res, kMaxGrid}));
+      q.y_in = L.y32[0];
+      q.y_out = L.y64[1];
+      EventPair ev;
+      if (ctx->timing) {
+        PR_HIP(hipEventCreate(&ev.a));
+        PR_HIP(hipEventCreate(&ev.b));
+        PR_HIP(hipEventRecord(ev.a, s));
+      }
+      PR_HIP(launch_batch_update_f32rows(s, kp64, (unsigned)q.grid, q));
+      if (ctx->timing) PR_HIP(hipEventRecord(ev.b, s));
+      PR_HIP(hipMemcpyAsync(&ctx->hbstate->head, &L.st->head, sizeof(LoopHead), hipMemcpyDeviceToHost, s));
+      PR_HIP(hipStreamSynchronize(s));
+      stopped = ctx->hbstate->head.stop != 0;
+      if (ctx->timing) {
+        float ms = 0.f;
+        PR_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        const ChunkSpec tag = batch_chunk(ctx, false, kp64, (unsigned)q.grid, q, nullptr, nullptr);
+        ctx->stat_ms[tag.kind] += ms;
+        ctx->stat_launches[tag.kind] += 1;
+        ctx->stat_ms[tag.sub_kind] += ms;
+        ctx->stat_launches[tag.sub_kind] += 1;
+      }
+      PR_HIP(launch_fill_u32(s, (uint32_t *)&L.st->head.phase_iter, 1, 0u));
+      f0 = L.y64[1];
+      f1 = L.y64[0];
+    }
     p.grid = (int32_t)grid_of(false, kp64);
     int fbuf = 0;
-    rc = run_until_stop(ctx, s, batch_chunk(ctx, false, kp64, (unsigned)p.grid, p, L.y64[0], L.y64[1]), &L.st->head,
-                        max_iter, &fbuf);
-    if (rc != PR_OK) return rc;
+    if (!stopped) {
+      rc = run_until_stop(ctx, s, batch_chunk(ctx, false, kp64, (unsigned)p.grid, p, f0, f1), &L.st->head, max_iter,
+                          &fbuf);
+      if (rc != PR_OK) return rc;
+    }
     PR_HIP(launch_batch_output(s, false, outdeg, L.y64[0], L.y64[1], kp64, (int32_t)N, K, p));
     PR_HIP(hipMemcpyAsync(ctx->hbstate, L.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
     PR_HIP(hipStreamSynchronize(s));

@@ -111,13 +111,17 @@ __host__ __device__ inline int64_t hub_blocks(int64_t nhubs) { return (nhubs + k
 // kp: row width, 1, 2, 4, 8, 12 or 16 values
 hipError_t launch_batch_update(hipStream_t s, bool fp32, int kp, unsigned grid, const BatchParams &p);
 int batch_blocks_per_cu(bool fp32, int kp);
+// A float64 update whose y_in holds float32 rows (the first float64 update of a mixed batch).
+hipError_t launch_batch_update_f32rows(hipStream_t s, int kp, unsigned grid, const BatchParams &p);
+int batch_blocks_per_cu_f32rows(int kp);
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase);
-// Columns leaving the float32 phase go to a column-major float64 staging area ycol[column][N]
-// (whole-line stores); launch_batch_rows then lays all K columns out as the float64 phase's rows.
-hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *ycol,
+// Columns leaving the float32 phase go to a column-major float32 staging area ycol[column][N]
+// (whole-line stores); launch_batch_rows then lays all K columns out as rows y[N][kp], float64
+// (f64) or float32.
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, float *ycol,
                                 int32_t N, int32_t K, const BatchState *st, const BatchCols *cols);
-hipError_t launch_batch_rows(hipStream_t s, const double *ycol, double *y64, int32_t kp64, int32_t N, int32_t K);
+hipError_t launch_batch_rows(hipStream_t s, const float *ycol, void *y, bool f64, int32_t kp, int32_t N, int32_t K);
 hipError_t launch_batch_rearm(hipStream_t s, BatchState *st, int32_t K);
 hipError_t launch_batch_compact(hipStream_t s, bool fp32, const void *src, int32_t kp_src, void *dst, int32_t kp_dst,
                                 int32_t N, int32_t K, const BatchCols *cols);

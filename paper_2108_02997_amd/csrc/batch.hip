@@ -65,8 +65,8 @@ struct BAcc {
 // Per-column epilogue of one row for the lane's C columns; yo holds the row's current values of
 // those columns (fetched by the caller, in the tile path together with the gathered rows).
 // c0 and alpha point at the teleport terms and damping factors of the lane's C columns.
-template <typename VT, int C>
-__device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VT (&yold)[C],
+template <typename VT, int C, typename VI = VT>
+__device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], int32_t dv, const VI (&yold)[C],
                                                VT *__restrict__ yout, int kp, int col0, const double *c0,
                                                const double *alpha, const bool (&act)[C], BAcc (&a)[C]) {
 #pragma clang fp contract(off)
@@ -75,7 +75,7 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
   for (int c = 0; c < C; ++c) {
     if (!act[c]) continue;
     const double rn = c0[c] + alpha[c] * s[c];
-    const VT yo = yold[c];
+    const VT yo = (VT)yold[c];
     double old, rnew;
     if (dv > 0) {
       old = (double)yo * (double)dv;
@@ -103,19 +103,23 @@ __device__ __forceinline__ void batch_epilogue(int32_t v, const double (&s)[C], 
 // LDS admits no more than 4 workgroups of 16 values.  Measured on the scale-24 R-MAT alpha
 // sweep; 1 = no cap (1 and 2 values stay under 64 registers by themselves; float64 rows are
 // bound by LDS first).
-template <typename VT, int KP>
+// The first float64 update of a mixed batch reads the float32 rows of the handover (VI = float,
+// exact in float64) and sums in float64.
+constexpr int kF32RowsWaves = 1;
+
+template <typename VT, int KP, typename VI = VT>
 constexpr int update_waves() {
-  return sizeof(VT) != 4 ? 1 : KP == 16 ? 4 : KP == 12 ? 5 : KP == 8 ? 6 : KP == 4 ? 7 : 1;
+  return sizeof(VT) != 4 ? (sizeof(VI) == 4 ? kF32RowsWaves : 1) : KP == 16 ? 4 : KP == 12 ? 5 : KP == 8 ? 6 : KP == 4 ? 7 : 1;
 }
 
-template <typename VT, int KP>
-__global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_update(BatchParams p) {
+template <typename VT, int KP, typename VI = VT>
+__global__ __launch_bounds__(kBlock, (update_waves<VT, KP, VI>())) void k_batch_update(BatchParams p) {
   constexpr int G = RowShape<KP>::G, C = RowShape<KP>::C;
   constexpr int kQuads = kBlock / G;                        // groups per block (64, 128, 256)
   constexpr int kGW = 64 / G;                               // groups per wave
   constexpr int kPerQ = kSpanB / kQuads;                    // entries gathered per group per tile (8, 4, 2)
   constexpr int kRowsQ = (kRowsB + kQuads - 1) / kQuads;    // rows owned per group per tile (2, 1, 1)
-  __shared__ VT vals[kSpanB * KP];
+  __shared__ VI vals[kSpanB * KP];
   __shared__ double sred[kWaves][KP];
   __shared__ double sacc[kWaves][KP][4];
   __shared__ double sc0[KP], salpha[KP];  // per-column terms in LDS rather than 2*C registers
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
   }
   const double *c0 = sc0 + col0, *alpha = salpha + col0;
   __syncthreads();
-  const VT *__restrict__ yin = (const VT *)p.y_in;
+  const VI *__restrict__ yin = (const VI *)p.y_in;
   VT *__restrict__ yout = (VT *)p.y_out;
   const int32_t *__restrict__ off = p.off;
   const int32_t *__restrict__ idx = p.idx;
@@ -171,27 +175,27 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
           dv[q] = __builtin_nontemporal_load(p.outdeg + v);
         }
       }
-      Row<VT, C> x[kPerQ];
+      Row<VI, C> x[kPerQ];
 #pragma unroll
       for (int k = 0; k < kPerQ; ++k) {
         if (u[k] >= 0) {
-          x[k] = load_row<VT, C>(yin, u[k], KP, col0);
+          x[k] = load_row<VI, C>(yin, u[k], KP, col0);
         } else {
 #pragma unroll
-          for (int c = 0; c < C; ++c) x[k].v[c] = (VT)0;
+          for (int c = 0; c < C; ++c) x[k].v[c] = (VI)0;
         }
       }
       // the current values of the group's own rows, in flight with the gather (the epilogue
       // would otherwise wait for them after the row sums)
-      Row<VT, C> yo[kRowsQ];
+      Row<VI, C> yo[kRowsQ];
 #pragma unroll
       for (int q = 0; q < kRowsQ; ++q) {
         const int32_t v = v0 + quad + q * kQuads;
         if (v < v1) {
-          yo[q] = load_row<VT, C>(yin, v, KP, col0);
+          yo[q] = load_row<VI, C>(yin, v, KP, col0);
         } else {
 #pragma unroll
-          for (int c = 0; c < C; ++c) yo[q].v[c] = (VT)0;
+          for (int c = 0; c < C; ++c) yo[q].v[c] = (VI)0;
         }
       }
 #pragma unroll
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
           double sd[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) sd[c] = (double)s[c];
-          batch_epilogue<VT, C>(v, sd, dv[q], yo[q].v, yout, KP, col0, c0, alpha, act, a);
+          batch_epilogue<VT, C, VI>(v, sd, dv[q], yo[q].v, yout, KP, col0, c0, alpha, act, a);
         }
         unsigned long long m = __ballot(mid && qp == 0);
         while (m) {
@@ -235,13 +239,13 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
             for (int c = 0; c < C; ++c) s[c] += vals[j * KP + col0 + c];
           }
           double sd[C];
-          VT wo[C];  // the row's current values, from the group that owns it
+          VI wo[C];  // the row's current values, from the group that owns it
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             sd[c] = (double)xor_sum_groups<G>(s[c]);
             wo[c] = __shfl(yo[q].v[c], src + qp, 64);
           }
-          if (lane < G) batch_epilogue<VT, C>(wv, sd, wd, wo, yout, KP, col0, c0, alpha, act, a);
+          if (lane < G) batch_epilogue<VT, C, VI>(wv, sd, wd, wo, yout, KP, col0, c0, alpha, act, a);
         }
       }
       __syncthreads();
@@ -258,14 +262,14 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
           const int32_t j = c8 + k * kQuads;
           u[k] = j < e1 ? __builtin_nontemporal_load(idx + j) : -1;
         }
-        Row<VT, C> x[kPerQ];
+        Row<VI, C> x[kPerQ];
 #pragma unroll
         for (int k = 0; k < kPerQ; ++k) {
           if (u[k] >= 0) {
-            x[k] = load_row<VT, C>(yin, u[k], KP, col0);
+            x[k] = load_row<VI, C>(yin, u[k], KP, col0);
           } else {
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[k].v[c] = (VT)0;
+            for (int c = 0; c < C; ++c) x[k].v[c] = (VI)0;
           }
         }
 #pragma unroll
@@ -294,8 +298,8 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
         }
         if (slot < 0) {
           // one-segment long row: finish here
-          const Row<VT, C> o = load_row<VT, C>(yin, v, KP, col0);
-          batch_epilogue<VT, C>(v, segd, p.outdeg[v], o.v, yout, KP, col0, c0, alpha, act, a);
+          const Row<VI, C> o = load_row<VI, C>(yin, v, KP, col0);
+          batch_epilogue<VT, C, VI>(v, segd, p.outdeg[v], o.v, yout, KP, col0, c0, alpha, act, a);
         } else {
 #pragma unroll
           for (int c = 0; c < C; ++c) p.hpart[(int64_t)slot * KP + col0 + c] = segd[c];
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP>())) void k_batch_upda
 // Hub rows: lane t of workgroup b finishes column t % 16 of hub row 16*b + t/16 (its segment
 // sums in segment order, then the epilogue); the workgroup's per-column partials are combined over
 // its 16 rows in row order and stored to hacc[b].
-template <typename VT, int KP>
+template <typename VT, int KP, typename VI = VT>
 __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
   __shared__ double sacc[kHubsPerBlock][16][4];
   const BatchState *st = p.st;
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
   const int32_t h = (int32_t)blockIdx.x * kHubsPerBlock + j;
   BAcc a = {0.0, 0.0, 0.0, 0.0};
   if (h < p.nhubs && k < p.K && k < KP && st->col[k].active) {
-    const VT *__restrict__ yin = (const VT *)p.y_in;
+    const VI *__restrict__ yin = (const VI *)p.y_in;
     VT *__restrict__ yout = (VT *)p.y_out;
     const double c0 = st->col[k].c0, alpha = p.cols->alpha[k];
     const int4 hb = p.hubs[h];
@@ -355,8 +359,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_hubs(BatchParams p) {
     bool act[1] = {true};
     BAcc aa[1] = {a};
     // the epilogue addresses column k of row hb.x
-    const VT yo[1] = {yin[(int64_t)hb.x * KP + k]};
-    batch_epilogue<VT, 1>(hb.x, sv, p.outdeg[hb.x], yo, yout, KP, k, &c0, &alpha, act, aa);
+    const VI yo[1] = {yin[(int64_t)hb.x * KP + k]};
+    batch_epilogue<VT, 1, VI>(hb.x, sv, p.outdeg[hb.x], yo, yout, KP, k, &c0, &alpha, act, aa);
     a = aa[0];
   }
   sacc[j][k][0] = a.l1;
@@ -533,39 +537,42 @@ __global__ __launch_bounds__(kFinBlock) void k_batch_init_finish(const double *_
   }
 }
 
-// Float32 columns -> float64 staging, column-major: column c (its newest buffer by its update
-// parity) goes to ycol[map[c]][0..N) (skipped when map[c] < 0).  One lane per row, the columns in
-// turn, so that each column's stores are contiguous: whole lines, where stores of single values
-// into the float64 rows would rewrite every line of those rows in part.
+// Float32 columns leaving the float32 phase -> column-major staging: column c (its newest buffer
+// by its update parity) goes to ycol[map[c]][0..N) (skipped when map[c] < 0).  One lane per row,
+// the columns in turn, so that each column's stores are contiguous: whole lines, where stores of
+// single values into the float64 rows would rewrite every line of those rows in part.  The values
+// stay float32 (their float64 value is exact).
 __global__ __launch_bounds__(kBlock) void k_batch_convert(const float *__restrict__ y32a, const float *__restrict__ y32b,
-                                                          int32_t kp32, double *__restrict__ ycol, int32_t N, int32_t K,
+                                                          int32_t kp32, float *__restrict__ ycol, int32_t N, int32_t K,
                                                           const BatchState *st, const BatchCols *cols) {
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
     for (int c = 0; c < K; ++c) {
       const int d = cols->map[c];
       if (d < 0) continue;
       const float *__restrict__ src = (st->col[c].phase_updates & 1) ? y32b : y32a;
-      ycol[(int64_t)d * N + v] = (double)src[v * kp32 + c];
+      ycol[(int64_t)d * N + v] = src[v * kp32 + c];
     }
   }
 }
 
-// Staging ycol[K][N] -> rows y64[N][kp64] of the float64 phase (padding columns zero), through an
-// LDS tile of kRowsT rows so that reads and stores are both contiguous.
+// Staging ycol[K][N] -> rows y[N][kp] of the float64 phase (padding columns zero), as float64 or
+// as the float32 values themselves, through an LDS tile of kRowsT rows so that reads and stores
+// are both contiguous.
 constexpr int kRowsT = 64;
-__global__ __launch_bounds__(kBlock) void k_batch_rows(const double *__restrict__ ycol, double *__restrict__ y64,
+template <typename VO>
+__global__ __launch_bounds__(kBlock) void k_batch_rows(const float *__restrict__ ycol, VO *__restrict__ y64,
                                                        int32_t kp64, int32_t N, int32_t K) {
-  __shared__ double tile[16][kRowsT + 1];
+  __shared__ float tile[16][kRowsT + 1];
   for (int64_t v0 = (int64_t)blockIdx.x * kRowsT; v0 < N; v0 += (int64_t)gridDim.x * kRowsT) {
     const int rows = (int)(N - v0 < kRowsT ? N - v0 : kRowsT);
     for (int i = threadIdx.x; i < kp64 * kRowsT; i += kBlock) {
       const int k = i / kRowsT, r = i % kRowsT;
-      if (r < rows) tile[k][r] = k < K ? ycol[(int64_t)k * N + v0 + r] : 0.0;
+      if (r < rows) tile[k][r] = k < K ? ycol[(int64_t)k * N + v0 + r] : 0.f;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < rows * kp64; i += kBlock) {
       const int r = i / kp64, k = i % kp64;
-      y64[(v0 + r) * kp64 + k] = tile[k][r];
+      y64[(v0 + r) * kp64 + k] = (VO)tile[k][r];
     }
     __syncthreads();
   }
@@ -646,10 +653,10 @@ static unsigned out_grid(int64_t N) {
   return (unsigned)(tiles < 1 ? 1 : tiles > 4096 ? 4096 : tiles);
 }
 
-template <typename VT, int KP>
+template <typename VT, int KP, typename VI = VT>
 static void batch_update_w(hipStream_t s, unsigned grid, const BatchParams &p) {
-  hipLaunchKernelGGL((k_batch_update<VT, KP>), dim3(grid), dim3(kBlock), 0, s, p);
-  if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, KP>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL((k_batch_update<VT, KP, VI>), dim3(grid), dim3(kBlock), 0, s, p);
+  if (p.nhubs > 0) hipLaunchKernelGGL((k_batch_hubs<VT, KP, VI>), dim3(hub_blocks(p.nhubs)), dim3(kBlock), 0, s, p);
   hipLaunchKernelGGL((k_batch_finish<VT, KP>), dim3(1), dim3(kFinBlock), 0, s, p);
 }
 
@@ -671,6 +678,19 @@ hipError_t launch_batch_update(hipStream_t s, bool fp32, int kp, unsigned grid, 
   return fp32 ? batch_update_t<float>(s, kp, grid, p) : batch_update_t<double>(s, kp, grid, p);
 }
 
+hipError_t launch_batch_update_f32rows(hipStream_t s, int kp, unsigned grid, const BatchParams &p) {
+  switch (kp) {
+    case 1: batch_update_w<double, 1, float>(s, grid, p); break;
+    case 2: batch_update_w<double, 2, float>(s, grid, p); break;
+    case 4: batch_update_w<double, 4, float>(s, grid, p); break;
+    case 8: batch_update_w<double, 8, float>(s, grid, p); break;
+    case 12: batch_update_w<double, 12, float>(s, grid, p); break;
+    case 16: batch_update_w<double, 16, float>(s, grid, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename VT>
 static int blocks_per_cu_t(int kp) {
   int n = 0;
@@ -688,6 +708,20 @@ static int blocks_per_cu_t(int kp) {
 
 int batch_blocks_per_cu(bool fp32, int kp) { return fp32 ? blocks_per_cu_t<float>(kp) : blocks_per_cu_t<double>(kp); }
 
+int batch_blocks_per_cu_f32rows(int kp) {
+  int n = 0;
+  hipError_t e;
+  switch (kp) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 1, float>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 2, float>, kBlock, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 4, float>, kBlock, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 8, float>, kBlock, 0); break;
+    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 12, float>, kBlock, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_update<double, 16, float>, kBlock, 0); break;
+  }
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, int32_t N, int32_t K, int32_t kp,
                              void *y, double *bpart, int64_t bpart_blocks, const BatchParams &p, int32_t phase) {
   const unsigned g = grid_for((int64_t)N * kp, bpart_blocks < 2048 ? bpart_blocks : 2048);
@@ -700,18 +734,21 @@ hipError_t launch_batch_init(hipStream_t s, bool fp32, const int32_t *outdeg, in
   return hipGetLastError();
 }
 
-hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, double *ycol,
+hipError_t launch_batch_convert(hipStream_t s, const float *y32a, const float *y32b, int32_t kp32, float *ycol,
                                 int32_t N, int32_t K, const BatchState *st, const BatchCols *cols) {
   hipLaunchKernelGGL(k_batch_convert, dim3(grid_for(N, 8192)), dim3(kBlock), 0, s, y32a, y32b, kp32, ycol, N, K, st,
                      cols);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_rows(hipStream_t s, const double *ycol, double *y64, int32_t kp64, int32_t N, int32_t K) {
-  if (kp64 < 1 || kp64 > 16 || K > kp64) return hipErrorInvalidValue;
+hipError_t launch_batch_rows(hipStream_t s, const float *ycol, void *y, bool f64, int32_t kp, int32_t N, int32_t K) {
+  if (kp < 1 || kp > 16 || K > kp) return hipErrorInvalidValue;
   const int64_t tiles = ((int64_t)N + kRowsT - 1) / kRowsT;
-  hipLaunchKernelGGL(k_batch_rows, dim3((unsigned)(tiles < 1 ? 1 : tiles > 8192 ? 8192 : tiles)), dim3(kBlock), 0, s,
-                     ycol, y64, kp64, N, K);
+  const dim3 grid((unsigned)(tiles < 1 ? 1 : tiles > 8192 ? 8192 : tiles));
+  if (f64)
+    hipLaunchKernelGGL(k_batch_rows<double>, grid, dim3(kBlock), 0, s, ycol, (double *)y, kp, N, K);
+  else
+    hipLaunchKernelGGL(k_batch_rows<float>, grid, dim3(kBlock), 0, s, ycol, (float *)y, kp, N, K);
   return hipGetLastError();
 }
 

@@ -253,6 +253,33 @@ def test_batch_chunk_sizes_agree(pr, ctx):
             assert i0 == i1 and f0 == f1 and torch.equal(r0, r1)
 
 
+def test_float32_row_handover_is_the_float64_update(pr, ctx):
+    # The first float64 update of a mixed batch reads the handover's float32 rows (exact in
+    # float64) instead of float64 copies and sums in float64: with the grid pinned (the same
+    # block partials) every result is bitwise the one of the float64 rows.  A column stopped by
+    # max_iter in the float32 phase keeps the float64-row path (third case).
+    g = gg.rmat(14, seed=51)
+    dg = pr.DeviceGraph.from_host(g)
+    cases = [sweep_problems(tau=1e-10, norm=3), sweep_problems(tau=1e-9, norm=1)[:5],
+             [dict(alpha=0.85, tau=1e-10, norm=2, max_iter=500), dict(alpha=0.9, tau=1e-10, norm=1, max_iter=4)]]
+    try:
+        ctx.set_option("grid", 300)
+        for probs in cases:
+            out = {}
+            for h in (0, 1):
+                ctx.set_option("handover32", h)
+                res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED, trace=True)
+                out[h] = [(r["iterations"], r["fp32_iters"], r["converged"], r["ranks"].clone(), r["trace"].clone())
+                          for r in res]
+            for a, b in zip(out[0], out[1]):
+                assert a[:3] == b[:3] and torch.equal(a[3], b[3]) and torch.equal(a[4], b[4]), a[:3]
+        with pytest.raises(pr.PrError):
+            ctx.set_option("handover32", 2)
+    finally:
+        ctx.set_option("handover32", 1)
+        ctx.set_option("grid", 0)
+
+
 def test_compaction_with_traces_and_max_iter(pr, ctx):
     g = gg.rmat(13, seed=22)
     dg = pr.DeviceGraph.from_host(g)
