@@ -256,11 +256,13 @@ def test_batch_chunk_sizes_agree(pr, ctx):
 def test_float32_row_handover_is_the_float64_update(pr, ctx):
     # The first float64 update of a mixed batch reads the handover's float32 rows (exact in
     # float64) instead of float64 copies and sums in float64: with the grid pinned (the same
-    # block partials) every result is bitwise the one of the float64 rows.  A column stopped by
-    # max_iter in the float32 phase keeps the float64-row path (third case).
+    # block partials) every result is bitwise the one of the float64 rows, on rows of 12, 8, 1
+    # and 2 values.  A column stopped by max_iter in the float32 phase keeps the float64-row
+    # path (last case).
     g = gg.rmat(14, seed=51)
     dg = pr.DeviceGraph.from_host(g)
     cases = [sweep_problems(tau=1e-10, norm=3), sweep_problems(tau=1e-9, norm=1)[:5],
+             sweep_problems(tau=1e-10, norm=3)[7:8], sweep_problems(tau=1e-10, norm=1)[8:10],
              [dict(alpha=0.85, tau=1e-10, norm=2, max_iter=500), dict(alpha=0.9, tau=1e-10, norm=1, max_iter=4)]]
     try:
         ctx.set_option("grid", 300)
