@@ -189,7 +189,7 @@ def cpu_baseline(graphs, seconds, what):
     for g in graphs:
         oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=1)
     t1 = time.perf_counter() - t
-    k = int(max(1, min(40, round(seconds / max(t1, 1e-3)))))
+    k = int(max(1, min(200, round(seconds / max(t1, 1e-3)))))
     t = time.perf_counter()
     for g in graphs:
         oracle.pagerank_graph(g, alpha=0.85, tau=0.0, norm=oracle.L1, max_iter=k)
