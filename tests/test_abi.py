@@ -68,3 +68,14 @@ def test_size_limits_of_the_int32_csr():
     assert lib.pr_batch_workspace_bytes(n_max, e_max, 17, 1, 1) == 0
     assert lib.pr_batch_workspace_bytes(n_max, e_max, 4, 2, 1) == 0   # no float32-only batches
     assert lib.pr_mlp_backward_workspace_bytes(n_max) > 0 and lib.pr_mlp_backward_workspace_bytes(0) == 0
+
+
+def test_every_option_key_is_documented():
+    # the keys pr_set_option accepts (its string compares) and the ones the header documents
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = open(os.path.join(root, "paper_2108_02997_amd", "csrc", "api.hip")).read()
+    header = open(os.path.join(root, "include", "prpull.h")).read()
+    accepted = set(re.findall(r'strcmp\(key, "([a-z_0-9]+)"\)', code))
+    documented = set(re.findall(r'^ \*   "([a-z_0-9]+)"', header, flags=re.M))
+    assert accepted and accepted == documented, (sorted(accepted - documented), sorted(documented - accepted))
