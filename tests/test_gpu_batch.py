@@ -282,6 +282,28 @@ def test_float32_row_handover_is_the_float64_update(pr, ctx):
         ctx.set_option("grid", 0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_on_the_relabelled_graph(pr, ctx, precision):
+    # the sweep solved on the out-degree-ordered graph (pr_relabel), each column mapped back with
+    # pr_unpermute, against the oracle on the graph as generated
+    g = gg.rmat(14, seed=61)
+    dg = pr.DeviceGraph.from_host(g)
+    h, perm = dg.relabelled(ctx)
+    probs = sweep_problems(tau=1e-10, norm=3)[:-1]
+    res = pr.pull_batch(ctx, h, probs, precision=precision)
+    for r, p in zip(res, probs):
+        back = pr.unpermute(ctx, perm, r["ranks"]).cpu().numpy()
+        if precision == pr.PR_FP64:
+            ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"], trace=True)
+            assert iterations_ok(r["iterations"], ref, p["tau"], p["norm"]), (p, r["iterations"], ref["iterations"])
+            if r["iterations"] == ref["iterations"]:
+                assert np.abs(back - ref["ranks"]).sum() <= 1e-12, p
+        else:
+            ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"])
+            d = np.abs(back - ref["ranks"]).sum()
+            assert r["converged"] and d <= mixed_bound(p["alpha"], r["err"][0], ref["err"][0]), (p, d)
+
+
 def test_compaction_with_traces_and_max_iter(pr, ctx):
     g = gg.rmat(13, seed=22)
     dg = pr.DeviceGraph.from_host(g)
