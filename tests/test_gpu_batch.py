@@ -136,10 +136,10 @@ def mixed_bound(alpha, e_gpu, e_ref):
     return alpha / (1 - alpha) * (e_gpu + e_ref) + 1e-13
 
 
-@pytest.mark.parametrize("K", [9, 12])
-def test_mixed_settings_on_twelve_value_rows(pr, ctx, K):
-    # 9 to 12 float32 columns share rows of 12 values (three per lane of a four-lane group);
-    # random settings, some columns halted by max_iter inside the float32 phase
+@pytest.mark.parametrize("K", [9, 12, 16])
+def test_mixed_settings_on_wide_rows(pr, ctx, K):
+    # 9 to 12 float32 columns share rows of 12 values (three per lane of a four-lane group), 13
+    # to 16 rows of 16; random settings, some columns halted by max_iter inside the float32 phase
     g = gg.rmat(13, seed=100 + K)
     dg = pr.DeviceGraph.from_host(g)
     rng = np.random.default_rng(100 + K)
@@ -151,8 +151,9 @@ def test_mixed_settings_on_twelve_value_rows(pr, ctx, K):
         res = pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED)
     finally:
         ctx.set_option("timing", 0)
-    assert ctx.stats(pr._lib.batch_kind(True, 12))[0] > 0
-    assert ctx.stats(pr._lib.batch_kind(True, 16))[0] == 0
+    width = 12 if K <= 12 else 16
+    assert ctx.stats(pr._lib.batch_kind(True, width))[0] > 0
+    assert all(ctx.stats(pr._lib.batch_kind(True, w))[0] == 0 for w in pr._lib.BATCH_ROW_WIDTHS if w > width)
     for r, p in zip(res, probs):
         ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"], max_iter=p["max_iter"])
         d = np.abs(r["ranks"].cpu().numpy() - ref["ranks"]).sum()
@@ -256,13 +257,14 @@ def test_batch_chunk_sizes_agree(pr, ctx):
 def test_float32_row_handover_is_the_float64_update(pr, ctx):
     # The first float64 update of a mixed batch reads the handover's float32 rows (exact in
     # float64) instead of float64 copies and sums in float64: with the grid pinned (the same
-    # block partials) every result is bitwise the one of the float64 rows, on rows of 12, 8, 1
-    # and 2 values.  A column stopped by max_iter in the float32 phase keeps the float64-row
+    # block partials) every result is bitwise the one of the float64 rows, on rows of 12, 8, 1,
+    # 2 and 16 values.  A column stopped by max_iter in the float32 phase keeps the float64-row
     # path (last case).
     g = gg.rmat(14, seed=51)
     dg = pr.DeviceGraph.from_host(g)
     cases = [sweep_problems(tau=1e-10, norm=3), sweep_problems(tau=1e-9, norm=1)[:5],
              sweep_problems(tau=1e-10, norm=3)[7:8], sweep_problems(tau=1e-10, norm=1)[8:10],
+             [dict(alpha=a, tau=1e-10, norm=2, max_iter=500) for a in np.linspace(0.5, 0.97, 16)],
              [dict(alpha=0.85, tau=1e-10, norm=2, max_iter=500), dict(alpha=0.9, tau=1e-10, norm=1, max_iter=4)]]
     try:
         ctx.set_option("grid", 300)
