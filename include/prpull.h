@@ -91,7 +91,8 @@ const char *pr_version(void);
 /* Tunables of a context (read by later solves):
  *   "grid"  : maximum number of workgroups of an update launch, 1..16384, or 0 (default) for one
  *             workgroup per resident slot (compute units x occupancy of the update kernel)
- *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 8)
+ *   "chunk" : updates per captured HIP graph between two host checks, even, 2..64 (default 16;
+ *             a host check costs tens of microseconds, an update past the stop a few)
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
  *   "mid_deg": rows of at most this many in-edges are summed by one lane, longer rows (up to the
  *             1024-entry tile window) by a whole wave64, 0..1024 (default 32)

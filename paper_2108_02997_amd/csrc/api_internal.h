@@ -80,7 +80,7 @@ struct pr_ctx {
   // tunables (pr_set_option)
   int64_t max_grid = 0;     // 0: one workgroup per resident slot (compute units x occupancy)
   int64_t resident[2] = {1, 1};  // resident update workgroups: [float64, float32]
-  int64_t chunk = 8;
+  int64_t chunk = 16;
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
   int64_t timing = 0;     // 1: bracket every update launch with HIP events
   int64_t batch_chunk = 2;  // updates between host checks of a batch solve (compaction points)

@@ -225,7 +225,7 @@ def test_loop_modes_and_grids_agree(pr, ctx):
     finally:
         ctx.set_option("loop", 0)
         ctx.set_option("grid", 0)
-        ctx.set_option("chunk", 8)
+        ctx.set_option("chunk", 16)
 
 
 def test_prepare_inside_workspace(pr, ctx):
