@@ -10,7 +10,6 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from test_gpu_batch import check_column  # noqa: E402
-from test_gpu_pull import TRACE_ATOL  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -42,9 +41,7 @@ def test_uneven_batch_each_graph_matches_oracle(pr, ctx):
     probs = [dict(alpha=s["alpha"], tau=s["tau"], norm=s["norm"], max_iter=500) for s in specs]
     res = pr.pull_multi(ctx, graphs, probs, trace=True)
     for r, h, p in zip(res, hosts, probs):
-        ref = check_column(r, h, p)
-        if r["iterations"] == ref["iterations"]:
-            np.testing.assert_allclose(r["trace"].cpu().numpy(), ref["trace"], rtol=1e-9, atol=TRACE_ATOL)
+        check_column(r, h, p)  # ranks, iteration count and the whole trace
 
 
 def test_multi_edge_cases(pr, ctx):

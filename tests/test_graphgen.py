@@ -1,4 +1,6 @@
 """Input generators and the CSR builder (host only)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -97,6 +99,23 @@ def test_load_mtx_general_and_symmetric(tmp_path):
     out.write_text("%%MatrixMarket matrix coordinate pattern general\n2 2 1\n3 1\n")
     with pytest.raises(ValueError):
         gg.load_mtx(str(out))
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_committed_mtx_fixtures():
+    # the two hand-written MatrixMarket files the GPU test solves: structure read off by hand
+    g = gg.load_mtx(os.path.join(GOLDEN, "small_general.mtx"))
+    assert g.N == 12 and g.E == 19                        # 21 entries - 1 duplicate - 1 self-loop
+    assert g.outdeg.tolist() == [2, 2, 2, 2, 0, 2, 2, 2, 0, 2, 3, 0]
+    assert [v for v in range(12) if g.outdeg[v] == 0] == [4, 8, 11]   # 5, 9, 12 in the file
+    assert g.indeg[11] == 0 and g.indeg[6] == 1           # 12 isolated; 7 only from 6
+    src, dst = g.edges()
+    assert (2, 3) in set(zip(src.tolist(), dst.tolist())) and (6, 6) not in set(zip(src.tolist(), dst.tolist()))
+    h = gg.load_mtx(os.path.join(GOLDEN, "small_symmetric.mtx"))
+    assert h.N == 8 and h.E == 16                         # 8 undirected edges, both ways
+    assert np.array_equal(h.outdeg, h.indeg) and h.outdeg.tolist() == [3, 2, 3, 3, 2, 2, 1, 0]
 
 
 def test_degree_order_is_a_permutation_by_decreasing_out_degree():
