@@ -15,7 +15,9 @@ Reported:
   sweep            per-column iterations, the same sweep as eleven sequential float64 solves
                    (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
   roofline         the dominant kernel's algorithmic bytes per launch over its average launch
-                   duration, timed with HIP events on the solve stream inside the timed steps;
+                   duration, timed with HIP events on the solve stream in a pass of the same step
+                   run right after the timed steps (the timed steps replay captured HIP graphs,
+                   whose kernels events cannot bracket one by one);
                    beside it (after the timed steps) the bare gather of the same rows over the
                    same index array (microbench/gather_ceiling.hip), and the kernel's time as a
                    fraction of that bare time
@@ -255,11 +257,17 @@ def run_sweep(args, pr, gg, np, torch):
     for i in range(args.warmup):
         sweep_batch()
         log("warmup %d done" % (i + 1))
+    # the timed steps run as a caller runs them (captured update chunks replayed as HIP graphs)
+    times, results = timed(sweep_batch, args.steps, "step (batched sweep)")
+    step_s = float(np.mean(times))
+    # per-launch kernel times: HIP events cannot bracket the kernels of a replayed graph, so the
+    # same step runs again with every update launched directly between two events on the solve
+    # stream (option "timing"), right after the timed steps
+    stat_steps = max(1, min(args.steps, 5))
     ctx.reset_stats()
     ctx.set_option("timing", 1)
-    times, results = timed(sweep_batch, args.steps, "step (batched sweep)")
+    ev_times, _ = timed(sweep_batch, stat_steps, "step with per-launch events")
     ctx.set_option("timing", 0)
-    step_s = float(np.mean(times))
     iters = [r["iterations"] for r in results]
     col_edges = sum(E * k for k in iters)
     gteps = col_edges / step_s / 1e9
@@ -275,7 +283,7 @@ def run_sweep(args, pr, gg, np, torch):
     dom_kind = pr._lib.batch_kind(fp32, kp0)
     phase1 = [r["fp32_iters"] for r in results] if fp32 else iters
     n_dom, ms_dom = ctx.stats(dom_kind)
-    per_step = max(1, round(n_dom / args.steps))
+    per_step = max(1, round(n_dom / stat_steps))
     alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(per_step)]
     alg_per_launch = float(np.mean(alg))
     avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
@@ -322,9 +330,10 @@ def run_sweep(args, pr, gg, np, torch):
         "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
         "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
         "step_ms_min_median": [round(min(times) * 1e3, 3), round(float(np.median(times)) * 1e3, 3)],
-        "graph_passes_per_s": round((n_all / args.steps + max(r["fp64_iters"] for r in results)) / step_s, 2)
+        "step_ms_with_launch_events": round(float(np.mean(ev_times)) * 1e3, 3),
+        "graph_passes_per_s": round((n_all / stat_steps + max(r["fp64_iters"] for r in results)) / step_s, 2)
         if n_all else None,
-        "first_phase_updates_per_step": round(n_all / args.steps, 2) if n_all else None,
+        "first_phase_updates_per_step": round(n_all / stat_steps, 2) if n_all else None,
         "first_phase_update_us_all_widths": round(1e3 * ms_all / n_all, 2) if n_all else None,
     }
     if not args.no_relabel:

@@ -79,6 +79,9 @@ SIGNATURES = {
     "pr_prep_bytes": ([_i64, _i64], _sz),
     "pr_prepare": ([_vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),
     "pr_validate_graph": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz], ctypes.c_int),
+    "pr_segment_count": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _vp, _sz, ctypes.POINTER(_i64)], ctypes.c_int),
+    "pr_segment_bytes": ([_vp, _i64, _i64, _i32, _i64], _sz),
+    "pr_prepare_segmented": ([_vp, _vp, _vp, _vp, _i64, _i64, _i32, _i64, _vp, _sz], ctypes.c_int),
     "pr_relabel_workspace_bytes": ([_vp, _i64, _i64], _sz),
     "pr_relabel": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _sz], ctypes.c_int),
     "pr_unpermute": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),

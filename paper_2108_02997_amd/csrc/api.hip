@@ -10,6 +10,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "api_internal.h"
 
 namespace prpull {
@@ -62,7 +64,7 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
                  PrepHeader *out) {
   PrepHeader h{};
   h.magic = kPrepMagic;
-  h.version = 2;
+  h.version = kPrepVersion;
   h.N = N;
   h.E = E;
   h.seg = kSeg;
@@ -93,12 +95,68 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
       return PR_EDEVICE;
     }
   }
+  int rc = write_prep_header(ctx, s, prep, h);
+  if (rc != PR_OK) return rc;
+  *out = h;
+  return PR_OK;
+}
+
+// The header to the device (synchronised) and into the context's table of preps.
+int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &h) {
+  static_assert(sizeof(PrepHeader) <= 56 * sizeof(unsigned long long), "header staging");
   memcpy(ctx->hscratch + 8, &h, sizeof h);
   PR_HIP(hipMemcpyAsync(prep, ctx->hscratch + 8, sizeof h, hipMemcpyHostToDevice, s));
   PR_HIP(hipStreamSynchronize(s));
   ctx->preps[prep] = h;
-  *out = h;
   return PR_OK;
+}
+
+// Key bits of the segment sort: enough for every segment id of N sources (at least 1).
+int seg_key_bits(int64_t N, int bits) {
+  const int64_t S = ((N - 1) >> bits) + 1;
+  int k = 1;
+  while (k < 31 && ((int64_t)1 << k) < S) ++k;
+  return k;
+}
+
+// Layout of the source-segmented part of a prep buffer with P pairs, after the plain prep;
+// false when a hipCUB size query fails.
+bool seg_layout(int64_t N, int64_t E, int bits, int64_t P, SegLayout *sl) {
+  size_t sort_b = 0, scan_e = 0, scan_p = 0;
+  if (seg_sort_temp_bytes(P, seg_key_bits(N, bits), &sort_b) != hipSuccess ||
+      seg_scan_temp_bytes(E + 1, &scan_e) != hipSuccess || seg_scan_temp_bytes(P + 1, &scan_p) != hipSuccess)
+    return false;
+  SegLayout L{};
+  L.pairs = P;
+  size_t o = align_up(prep_bytes(N, E), 256);
+  auto take = [&o](size_t n) {
+    const size_t at = o;
+    o += align_up(n, 256);
+    return (int64_t)at;
+  };
+  L.poff_off = take(4 * (size_t)(P + 1));
+  L.moff_off = take(4 * (size_t)(N + 1));
+  L.mpos_off = take(4 * (size_t)P);
+  L.sidx_off = take(4 * (size_t)(E + 1));
+  L.part_off = take(8 * (size_t)P);
+  L.pair_part.tile = kTile;
+  L.pair_part.rows = kRows;
+  L.pair_part.desc_off = take((size_t)(max_desc(P, E, kTile, kRows) + 1) * sizeof(int4));
+  L.pair_part.hub_off = take((size_t)max_hubs(P, E) * sizeof(int4));
+  L.merge_part.tile = kTile;
+  L.merge_part.rows = kRows;
+  L.merge_part.desc_off = take((size_t)(max_desc(N, P, kTile, kRows) + 1) * sizeof(int4));
+  L.merge_part.hub_off = take((size_t)max_hubs(N, P) * sizeof(int4));
+  L.scan_off = take((size_t)(scan_block_count(std::max<int64_t>(N, P)) + 1) * 2 * sizeof(unsigned long long));
+  L.temp_off = take(4 * (size_t)(E + 1));
+  take(4 * (size_t)(P + 1));
+  take(4 * (size_t)(P + 1));
+  take(4 * (size_t)P);
+  // hipCUB's storage; first the pair count's block sums
+  L.cub_off = take(std::max({sort_b, scan_e, scan_p, (size_t)(seg_count_blocks() + 1) * sizeof(unsigned long long)}));
+  L.total = (int64_t)o;
+  *sl = L;
+  return true;
 }
 
 int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E, PrepHeader *out) {
@@ -111,7 +169,7 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
     PR_HIP(hipStreamSynchronize(s));
     memcpy(&h, ctx->hscratch + 8, sizeof h);
   }
-  if (h.magic != kPrepMagic || h.version != 2) {
+  if (h.magic != kPrepMagic || h.version != kPrepVersion) {
     set_error("prep buffer was not written by pr_prepare");
     return PR_EINVAL;
   }
@@ -458,6 +516,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->handover32 = value;
+  } else if (!strcmp(key, "segmented")) {
+    if (value != 0 && value != 1) {
+      set_error("segmented must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->segmented = value;
   } else if (!strcmp(key, "narrow")) {
     if (value != 0 && value != 1) {
       set_error("narrow must be 0 or 1");
@@ -530,6 +594,120 @@ int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, 
   DeviceGuard g(ctx->device);
   PrepHeader h;
   return prepare_into(ctx, (hipStream_t)stream, in_offsets, N, E, prep, &h);
+}
+
+static bool bad_seg_args(int64_t N, int64_t E, int32_t seg_bits) {
+  if (bad_graph_sizes(N, E)) return true;
+  if (E > 2147483646LL) {
+    set_error("the source-segmented layout needs E <= 2^31-2, got %lld", (long long)E);
+    return true;
+  }
+  if (seg_bits < kMinSegBits || seg_bits > 30) {
+    set_error("seg_bits must be in [%d, 30], got %d", kMinSegBits, seg_bits);
+    return true;
+  }
+  return false;
+}
+
+int pr_segment_count(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
+                     int64_t E, int32_t seg_bits, void *workspace, size_t workspace_bytes, int64_t *pairs) {
+  if (!ctx || !in_offsets || !workspace || !pairs || (E > 0 && !in_indices)) {
+    set_error("pr_segment_count: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_seg_args(N, E, seg_bits)) return PR_EINVAL;
+  const size_t need = (size_t)(seg_count_blocks() + 1) * sizeof(unsigned long long);
+  if (workspace_bytes < need) {
+    set_error("pr_segment_count: workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return PR_ENOMEM;
+  }
+  *pairs = 0;
+  if (E == 0) return PR_OK;
+  DeviceGuard g(ctx->device);
+  PR_HIP(launch_seg_count((hipStream_t)stream, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits,
+                          (unsigned long long *)workspace, ctx->hscratch));
+  *pairs = (int64_t)ctx->hscratch[0];
+  return PR_OK;
+}
+
+size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_bits, int64_t pairs) {
+  if (!ctx || bad_seg_args(N, E, seg_bits) || pairs < 0 || pairs > E || (E > 0 && pairs < 1)) return 0;
+  if (E == 0) return prep_bytes(N, E);
+  DeviceGuard g(ctx->device);
+  SegLayout sl;
+  if (!seg_layout(N, E, seg_bits, pairs, &sl)) {
+    set_error("pr_segment_bytes: hipCUB size query failed");
+    return 0;
+  }
+  return (size_t)sl.total;
+}
+
+int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
+                         int64_t E, int32_t seg_bits, int64_t pairs, void *prep, size_t prep_bytes_) {
+  if (!ctx || !in_offsets || !prep || (E > 0 && !in_indices)) {
+    set_error("pr_prepare_segmented: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_seg_args(N, E, seg_bits)) return PR_EINVAL;
+  if (pairs < 0 || pairs > E || (E > 0 && pairs < 1)) {
+    set_error("pr_prepare_segmented: pairs %lld out of range (use pr_segment_count)", (long long)pairs);
+    return PR_EINVAL;
+  }
+  const size_t need = pr_segment_bytes(ctx, N, E, seg_bits, pairs);
+  if (need == 0) return PR_EINVAL;
+  if (prep_bytes_ < need) {
+    set_error("pr_prepare_segmented: prep buffer has %zu bytes, needs %zu", prep_bytes_, need);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc = prepare_into(ctx, s, in_offsets, N, E, prep, &h);
+  if (rc != PR_OK || E == 0) return rc;  // no edges: the plain partitions alone
+  SegLayout sl;
+  if (!seg_layout(N, E, seg_bits, pairs, &sl)) {
+    set_error("pr_prepare_segmented: hipCUB size query failed");
+    return PR_EDEVICE;
+  }
+  char *base = (char *)prep;
+  // the count again, so that a stale or mistyped `pairs` cannot overrun the layout
+  PR_HIP(launch_seg_count(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits,
+                          (unsigned long long *)(base + sl.cub_off), ctx->hscratch));
+  if ((int64_t)ctx->hscratch[0] != pairs) {
+    set_error("pr_prepare_segmented: the graph has %llu pairs at seg_bits %d, %lld given", ctx->hscratch[0], seg_bits,
+              (long long)pairs);
+    return PR_EINVAL;
+  }
+  PR_HIP(launch_seg_build(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits, seg_key_bits(N, seg_bits),
+                          pairs, base, sl));
+  // tile partitions of the pair CSR (P rows over E entries) and of the merge CSR (N rows over P)
+  struct {
+    PrepPart *pp;
+    const int32_t *off;
+    int64_t rows, entries;
+  } parts[2] = {{&sl.pair_part, (const int32_t *)(base + sl.poff_off), pairs, E},
+                {&sl.merge_part, (const int32_t *)(base + sl.moff_off), N, pairs}};
+  for (auto &q : parts) {
+    PrepPart &pp = *q.pp;
+    PR_HIP(launch_prepare(s, 0, q.off, q.rows, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
+                          base + sl.scan_off, ctx->hscratch));
+    pp.ndesc = (int32_t)ctx->hscratch[0];
+    pp.nslots = (int32_t)(ctx->hscratch[1] >> 32);
+    pp.nhubs = (int32_t)(ctx->hscratch[1] & 0xffffffffull);
+    if (pp.ndesc < 1 || pp.ndesc > max_desc(q.rows, q.entries, kTile, kRows) ||
+        pp.nslots > max_slots(q.rows, q.entries) || pp.nhubs > max_hubs(q.rows, q.entries)) {
+      set_error("internal: segmented tile partition out of bounds (ndesc %d, slots %d, hubs %d)", pp.ndesc, pp.nslots,
+                pp.nhubs);
+      return PR_EDEVICE;
+    }
+  }
+  if (sl.pair_part.nhubs != 0 || sl.pair_part.nslots != 0) {
+    set_error("internal: a pair longer than one tile window");
+    return PR_EDEVICE;
+  }
+  h.seg_bits = seg_bits;
+  h.sl = sl;
+  return write_prep_header(ctx, s, prep, h);
 }
 
 int pr_validate_graph(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,

@@ -92,6 +92,7 @@ struct pr_ctx {
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
   int64_t handover32 = 1;   // 1: the first float64 update of a mixed batch reads float32 rows
+  int64_t segmented = 1;    // 1: pr_pull uses the source-segmented layout of a prep that has one
   int64_t barrier_ms = 5000;  // time limit of a grid-barrier wait in pr_pull_multi
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
@@ -164,6 +165,9 @@ bool bad_graph_sizes(int64_t N, int64_t E);
 Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep);
 int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep, PrepHeader *out);
 int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E, PrepHeader *out);
+int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &h);
+int seg_key_bits(int64_t N, int bits);
+bool seg_layout(int64_t N, int64_t E, int bits, int64_t P, SegLayout *sl);
 int make_events(std::vector<hipEvent_t> &ev, size_t n);
 int run_chunk(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const std::vector<hipEvent_t> **events);
 int run_until_stop(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const LoopHead *head, int max_updates,
@@ -176,5 +180,9 @@ std::vector<int64_t> graph_signature(const PrepHeader &h);
 std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h);
 void load_tune_file(pr_ctx *ctx);
 void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid);
+int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+               int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
+               int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
+               size_t workspace_bytes, pr_result *out);
 
 }  // namespace prpull

@@ -22,6 +22,19 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
     set_error("pr_pull: NULL argument");
     return PR_EINVAL;
   }
+  return pull_solve(ctx, stream, in_offsets, in_indices, outdeg, N, E, prep, alpha, tau, norm, max_iter, precision,
+                    init, ranks, norm_trace, workspace, workspace_bytes, out);
+}
+
+}  // extern "C"
+
+namespace prpull {
+
+// pr_pull after its NULL checks (also the body of the entry point that allocates nothing).
+int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
+               int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
+               int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
+               size_t workspace_bytes, pr_result *out) {
   if (bad_graph_sizes(N, E)) return PR_EINVAL;
   if (!(alpha >= 0.0 && alpha <= 1.0)) {
     set_error("alpha must be in [0, 1], got %g", alpha);
@@ -64,12 +77,26 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
   const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
   const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_FP64 ? 0 : 1];
-  const PrepPart &part = h.part[0];
+  // a prep with the source-segmented layout: the merge step's tiles take the place of the plain
+  // update's, the per-segment step runs before it
+  const bool seg = ctx->segmented != 0 && h.seg_bits > 0;
+  const PrepPart &part = seg ? h.sl.merge_part : h.part[0];
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
 
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
+  if (seg) {
+    char *base = (char *)const_cast<void *>(pp);
+    p.off = (const int32_t *)(base + h.sl.moff_off);
+    p.idx = (const int32_t *)(base + h.sl.mpos_off);
+    p.poff = (const int32_t *)(base + h.sl.poff_off);
+    p.sidx = (const int32_t *)(base + h.sl.sidx_off);
+    p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
+    p.npdesc = h.sl.pair_part.ndesc;
+    p.partial = base + h.sl.part_off;
+    p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
+  }
   p.outdeg = outdeg;
   p.desc = (const int4 *)((const char *)pp + part.desc_off);
   p.ndesc = part.ndesc;
@@ -136,6 +163,10 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   out->final_err[2] = hs.err[2];
   return hs.converged ? PR_OK : PR_NOT_CONVERGED;
 }
+
+}  // namespace prpull
+
+extern "C" {
 
 size_t pr_batch_workspace_bytes(int64_t N, int64_t E, int32_t K, int32_t precision, int32_t with_prep) {
   if (bad_graph_sizes(N, E) || K < 1 || K > kMaxCols || (precision != PR_FP64 && precision != PR_MIXED)) return 0;

@@ -92,26 +92,34 @@ __device__ __forceinline__ double block_max_n(double v, double *lds) {
 // ------------------------------------------------------------------ one tile
 // Everything one workgroup does for one tile descriptor d (dn is the next descriptor) of one
 // graph in one update; the row epilogues accumulate into a (per lane).
+// Rows are summed over xs[idx[j]]: xs is the iterate itself in the plain update; in the merge
+// step of the source-segmented update it is the array of per-segment partial sums, idx listing a
+// row's partial sums in segment order.  yin (the row's own current value) and yout serve the
+// epilogue.  With Part = true a row's sum is stored as it is into part[row] (the per-segment
+// step of the source-segmented update: rows are then (segment, row) pairs, no epilogue).
 template <typename VT>
 struct TileCtx {
   const int32_t *off;
   const int32_t *idx;
   const int32_t *outdeg;
+  const VT *xs;
   const VT *yin;
   VT *yout;
+  VT *part;
   double *hpart;
   double c0;
   double alpha;
   int32_t mid_deg;  // rows with more entries are summed by a whole wave
 };
 
-template <typename VT>
+template <typename VT, bool Part = false>
 __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, const int4 dn, Acc &a, VT *vals,
                                             double *red) {
   const int t = threadIdx.x, lane = t & 63;
   constexpr int kPer = kSpan / kBlock;
   const int32_t *__restrict__ off = c.off;
   const int32_t *__restrict__ idx = c.idx;
+  const VT *__restrict__ xs = c.xs;
   const VT *__restrict__ yin = c.yin;
   VT *__restrict__ yout = c.yout;
   const int32_t e0 = d.y, e1 = dn.y;
@@ -137,13 +145,15 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
       if (v < v1) {
         ra[q] = __builtin_nontemporal_load(off + v) - e0;
         rb[q] = __builtin_nontemporal_load(off + v + 1) - e0;
-        dv[q] = __builtin_nontemporal_load(c.outdeg + v);
-        yo[q] = __builtin_nontemporal_load(yin + v);
+        if (!Part) {
+          dv[q] = __builtin_nontemporal_load(c.outdeg + v);
+          yo[q] = __builtin_nontemporal_load(yin + v);
+        }
       }
     }
     VT x[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? yin[u[k]] : (VT)0;
+    for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? xs[u[k]] : (VT)0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int j = t + k * kBlock;
@@ -158,7 +168,10 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
       if (mine && !mid) {
         VT s = (VT)0;
         for (int32_t j = ra[q]; j < rb[q]; ++j) s += vals[j];
-        epilogue<VT>(v, (double)s, c.c0, c.alpha, dv[q], yo[q], yout, a);
+        if (Part)
+          c.part[v] = s;
+        else
+          epilogue<VT>(v, (double)s, c.c0, c.alpha, dv[q], yo[q], yout, a);
       }
       unsigned long long m = __ballot(mid);
       while (m) {
@@ -168,7 +181,12 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
         VT s = (VT)0;
         for (int32_t j = wa + lane; j < wb; j += 64) s += vals[j];
         s = wave_sum(s);
-        if (lane == src) epilogue<VT>(v, (double)s, c.c0, c.alpha, dv[q], yo[q], yout, a);
+        if (lane == src) {
+          if (Part)
+            c.part[v] = s;
+          else
+            epilogue<VT>(v, (double)s, c.c0, c.alpha, dv[q], yo[q], yout, a);
+        }
       }
     }
     __syncthreads();
@@ -186,13 +204,15 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
       }
       VT x[kPer];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? yin[u[k]] : (VT)0;
+      for (int k = 0; k < kPer; ++k) x[k] = u[k] >= 0 ? xs[u[k]] : (VT)0;
 #pragma unroll
       for (int k = 0; k < kPer; ++k) s += x[k];
     }
     const double seg = block_sum((double)s, red);
     if (t == 0) {
-      if (slot < 0)
+      if (Part)
+        c.part[v] = (VT)seg;  // not reached: pairs are never longer than a tile window
+      else if (slot < 0)
         epilogue<VT>(v, seg, c.c0, c.alpha, c.outdeg[v], yin[v], yout, a);
       else
         c.hpart[slot] = seg;

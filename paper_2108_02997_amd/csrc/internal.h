@@ -58,6 +58,30 @@ struct PrepPart {
   int32_t tile, rows, ndesc, nslots, nhubs, pad;
 };
 
+// Source-segmented layout (pr_prepare_segmented), in the same buffer after the plain prep's
+// regions.  Source ids are cut into segments of 2^bits consecutive ids; a pair is a run of one
+// row's entries whose sources lie in one segment (at most kPairMax entries: longer runs are cut
+// at row-relative multiples of kPairMax).  Pairs are listed segment by segment, rows ascending
+// within a segment (the pair CSR: poff[P+1] over the permuted indices sidx[E]); the merge CSR
+// lists, for every row, its pairs in segment order (moff[N+1] over mpos[P]).  part holds one
+// partial sum per pair (float64, or float32 in a float32 phase) during a solve.
+struct SegLayout {
+  int64_t pairs;     // P
+  int64_t poff_off;  // byte offsets of the arrays in the prep buffer
+  int64_t moff_off;
+  int64_t mpos_off;
+  int64_t sidx_off;
+  int64_t part_off;
+  int64_t scan_off;  // scan scratch of the two tile partitions
+  int64_t temp_off;  // construction scratch
+  int64_t cub_off;   // hipCUB's storage inside it
+  int64_t total;     // bytes of the whole buffer
+  PrepPart pair_part;   // tiles over the pair CSR (no long rows)
+  PrepPart merge_part;  // tiles over the merge CSR
+};
+constexpr int32_t kPairMax = kTile;
+constexpr int32_t kMinSegBits = 8;
+
 struct PrepHeader {
   int32_t magic;
   int32_t version;
@@ -66,8 +90,12 @@ struct PrepHeader {
   int32_t seg, pad;
   int64_t scan_off;   // byte offset of the scan scratch
   PrepPart part[2];
+  int32_t seg_bits;   // 0: no source-segmented layout, else 2^seg_bits source ids per segment
+  int32_t pad2;
+  SegLayout sl;
 };
 constexpr int32_t kPrepMagic = 0x50525032;  // "PRP2"
+constexpr int32_t kPrepVersion = 3;
 
 size_t prep_bytes(int64_t N, int64_t E);
 int64_t max_desc(int64_t N, int64_t E, int tile, int rows);
@@ -116,6 +144,16 @@ struct IterParams {
   int32_t nhubs;
   int32_t grid;        // number of blocks of the update launch (partials to reduce)
   double *trace;       // [max_iter][3] or null
+  // Source-segmented update (poff null: the plain update).  Its per-segment step sums, over the
+  // tiles pdesc, the entries sidx[poff[p] .. poff[p+1]) of pair p into partial[p] (type of the
+  // phase); off / idx / desc / hubs then describe the merge step, in which row v sums
+  // partial[idx[j]] over its entries j of off (its pairs in segment order).
+  const int32_t *poff;
+  const int32_t *sidx;
+  const int4 *pdesc;
+  void *partial;
+  int32_t npdesc;
+  int32_t pgrid;       // workgroups of the per-segment step
 };
 
 // ---------------------------------------------------------------- host helpers
@@ -140,5 +178,13 @@ hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N
                           unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
+// Source-segmented layout (segment.hip).
+int64_t seg_count_blocks();
+hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
+                            unsigned long long *block_counts, unsigned long long *host_total);
+hipError_t seg_sort_temp_bytes(int64_t P, int key_bits, size_t *bytes);
+hipError_t seg_scan_temp_bytes(int64_t n, size_t *bytes);
+hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
+                            int key_bits, int64_t P, char *base, const SegLayout &sl);
 
 }  // namespace prpull

@@ -44,7 +44,6 @@ struct GridBarrier {
   uint32_t xcd[kMaxXcd * kBarPad];      // arrivals on each XCD, all barriers so far
   uint32_t release[kMaxXcd * kBarPad];  // per XCD: the last barrier its workgroups may leave
   uint32_t global[kBarPad];             // XCD arrivals, all barriers so far
-  uint32_t setup[kBarPad];              // workgroups counted into members
   uint32_t timeout[kBarPad];            // nonzero: a wait passed its time limit (all workgroups quit)
 };
 

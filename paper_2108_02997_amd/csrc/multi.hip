@@ -62,19 +62,37 @@ struct BarSlot {
   uint32_t nxcd;  // XCDs with workgroups of the launch
 };
 
-// Count the launch's workgroups per XCD.  Block-uniform result; false on time-out.
+// Count the launch's workgroups per XCD.  Every workgroup adds itself to its XCD's count and
+// then waits until the per-XCD counts sum to the grid: the words it waits on are the counted
+// words themselves, and since each only grows, a total of gridDim.x means every count is final
+// (no ordering between atomics on different words is relied on).  Block-uniform result; false
+// on time-out.
 __device__ bool bar_setup(GridBarrier *b, BarSlot &slot, uint64_t limit) {
   __shared__ uint32_t s_v[3];
   int ok = 1;
   if (threadIdx.x == 0) {
     const uint32_t x = xcc_id();
     bar_add(&b->members[x * kBarPad]);
-    bar_add(&b->setup[0]);
-    ok = bar_wait(b, &b->setup[0], gridDim.x, limit);
+    const uint64_t t0 = wall_clock64();
     uint32_t n = 0;
-    for (int i = 0; i < kMaxXcd; ++i) n += bar_load(&b->members[i * kBarPad]) > 0;
+    for (;;) {
+      uint32_t total = 0;
+      n = 0;
+      for (int i = 0; i < kMaxXcd; ++i) {
+        const uint32_t c = bar_load(&b->members[i * kBarPad]);
+        total += c;
+        n += c > 0;
+      }
+      if (total >= gridDim.x) break;
+      if (bar_load(&b->timeout[0]) || wall_clock64() - t0 > limit) {
+        __hip_atomic_store(&b->timeout[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
     s_v[0] = x;
-    s_v[1] = bar_load(&b->members[x * kBarPad]);
+    s_v[1] = bar_load(&b->members[x * kBarPad]);  // final once the counts sum to the grid
     s_v[2] = n;
   }
   if (__syncthreads_or(!ok)) return false;
@@ -156,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_multi(MultiParams p) {
         c.idx = mg.idx;
         c.outdeg = mg.outdeg;
         c.yin = mg.y[par];
+        c.xs = c.yin;
         c.yout = mg.y[par ^ 1];
         c.hpart = mg.hpart;
         c.c0 = gs.c0;

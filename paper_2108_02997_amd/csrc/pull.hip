@@ -80,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
   c.idx = p.idx;
   c.outdeg = p.outdeg;
   c.yin = (const VT *)p.y_in;
+  c.xs = p.partial ? (const VT *)p.partial : c.yin;
   c.yout = (VT *)p.y_out;
   c.hpart = p.hpart;
   c.c0 = st->c0;
@@ -100,6 +101,25 @@ __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
     bp[2] = mx;
     bp[3] = dang;
   }
+}
+
+// Per-segment step of the source-segmented update: every pair's entries of the iterate summed
+// into its partial (pairs listed segment by segment, so the workgroups running at one time
+// gather from one or two segments' slice of the iterate, which the XCDs' L2 caches hold).
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_seg_gather(IterParams p) {
+  __shared__ VT vals[kSpan];
+  __shared__ double red[kWaves];
+  if (p.st->head.stop) return;
+  TileCtx<VT> c{};
+  c.off = p.poff;
+  c.idx = p.sidx;
+  c.xs = (const VT *)p.y_in;
+  c.part = (VT *)p.partial;
+  c.mid_deg = p.mid_deg;
+  Acc a = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t i = blockIdx.x; i < p.npdesc; i += gridDim.x)
+    update_tile<VT, true>(c, p.pdesc[i], p.pdesc[i + 1], a, vals, red);
 }
 
 // One block: hub rows (segment partials combined in segment order, then the epilogue), the
@@ -256,8 +276,15 @@ int update_blocks_per_cu(bool fp32) {
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
-// One update = the tile kernel and the one-block finishing kernel.
+// One update = the tile kernel and the one-block finishing kernel (source-segmented: the
+// per-segment step, then the merge step as the tile kernel, then the finishing kernel).
 hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterParams &p) {
+  if (p.poff) {
+    if (fp32)
+      hipLaunchKernelGGL(k_seg_gather<float>, dim3((unsigned)p.pgrid), dim3(kBlock), 0, s, p);
+    else
+      hipLaunchKernelGGL(k_seg_gather<double>, dim3((unsigned)p.pgrid), dim3(kBlock), 0, s, p);
+  }
   if (fp32) {
     hipLaunchKernelGGL(k_update<float>, dim3(grid), dim3(kBlock), 0, s, p);
     hipLaunchKernelGGL(k_finish<float>, dim3(1), dim3(kFinBlock), 0, s, p);

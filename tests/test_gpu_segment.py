@@ -1,0 +1,237 @@
+"""The source-segmented layout (pr_segment_count, pr_prepare_segmented) and pr_pull on it, through
+the C ABI.
+
+* The layout is integer work and is compared bit for bit with a plain numpy construction from its
+  definition (pairs = runs of one row's entries whose sources share a segment of 2^bits ids, cut
+  every 1024 entries of the row; pair CSR listed segment by segment, rows ascending; merge CSR
+  listing every row's pairs in segment order).
+* Solves on it keep the float64 bar of tests/parity.py against the oracle (1e-12 L1 after the
+  same number of updates, traces, iteration counts with the tie rule), and the mixed and
+  float32-only bars; they are bitwise repeatable; with option "segmented" = 0 the same buffer
+  gives the plain update.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+from parity import check_fp64_result, check_mixed_result
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PAIR_MAX = 1024
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2108_02997_amd as pr
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return pr
+
+
+@pytest.fixture(scope="module")
+def ctx(pr):
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+class PrepPart(ctypes.Structure):
+    _fields_ = [("desc_off", ctypes.c_int64), ("hub_off", ctypes.c_int64), ("tile", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("ndesc", ctypes.c_int32), ("nslots", ctypes.c_int32),
+                ("nhubs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SegLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("pairs", "poff_off", "moff_off", "mpos_off", "sidx_off", "part_off",
+                                              "scan_off", "temp_off", "cub_off", "total")] + \
+               [("pair_part", PrepPart), ("merge_part", PrepPart)]
+
+
+class PrepHeader(ctypes.Structure):
+    """The library's prep header as laid out in the buffer (internal.h)."""
+    _fields_ = [("magic", ctypes.c_int32), ("version", ctypes.c_int32), ("N", ctypes.c_int64), ("E", ctypes.c_int64),
+                ("seg", ctypes.c_int32), ("pad", ctypes.c_int32), ("scan_off", ctypes.c_int64),
+                ("part", PrepPart * 2), ("seg_bits", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sl", SegLayout)]
+
+
+def expected_layout(g, bits):
+    """The segmented layout from its definition (numpy, row order first)."""
+    off = g.off.astype(np.int64)
+    idx = g.idx.astype(np.int64)
+    E = g.E
+    rows = np.repeat(np.arange(g.N, dtype=np.int64), np.diff(off))
+    rel = np.arange(E, dtype=np.int64) - off[rows]
+    seg = idx >> bits
+    start = (rel % PAIR_MAX == 0)
+    start[1:] |= seg[1:] != seg[:-1]
+    q_start = np.flatnonzero(start)                     # row-order pairs
+    P = q_start.size
+    q_len = np.diff(np.append(q_start, E))
+    q_seg = seg[q_start]
+    perm = np.argsort(q_seg, kind="stable")              # segment-major position -> row-order pair
+    mpos = np.empty(P, dtype=np.int64)
+    mpos[perm] = np.arange(P)
+    poff = np.concatenate([[0], np.cumsum(q_len[perm])])
+    sidx = np.concatenate([idx[q_start[q]:q_start[q] + q_len[q]] for q in perm]) if P else np.zeros(0, np.int64)
+    first_pair = np.cumsum(start) - 1                    # row-order pair of every entry
+    moff = np.empty(g.N + 1, dtype=np.int64)
+    moff[g.N] = P
+    nonempty = np.diff(off) > 0
+    moff[:g.N][nonempty] = first_pair[off[:-1][nonempty]]
+    # an empty row's pairs start where the next pairs start
+    for v in range(g.N - 1, -1, -1):
+        if not nonempty[v]:
+            moff[v] = moff[v + 1]
+    return P, poff, sidx, moff, mpos
+
+
+def read_layout(dg):
+    raw = dg.prep.cpu().numpy()
+    h = PrepHeader.from_buffer_copy(raw[:ctypes.sizeof(PrepHeader)].tobytes())
+    sl = h.sl
+
+    def arr(at, n):
+        return raw[at:at + 4 * n].view(np.int32).astype(np.int64)
+    P = sl.pairs
+    return h, P, arr(sl.poff_off, P + 1), arr(sl.sidx_off, dg.E), arr(sl.moff_off, dg.N + 1), arr(sl.mpos_off, P)
+
+
+def segmented(pr, ctx, g, bits):
+    dg = pr.DeviceGraph.from_host(g)
+    dg.prepare_segmented(ctx, seg_bits=bits)
+    return dg
+
+
+def hub_graph(N=6000, seed=4):
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for v, deg in ((0, 5000), (3, 2500), (7, 1100), (11, 300)):
+        src.extend(rng.choice(N, size=deg, replace=False).tolist())
+        dst.extend([v] * deg)
+    src.extend(rng.integers(0, N, 30000).tolist())
+    dst.extend(rng.integers(0, N, 30000).tolist())
+    return gg.from_edges(N, src, dst)
+
+
+GRAPHS = {
+    "rmat13": lambda: gg.rmat(13, seed=31),
+    "er_c1": gg.workload_c1,
+    "hubs": hub_graph,
+}
+
+
+@pytest.mark.parametrize("name,bits", [("rmat13", 8), ("rmat13", 10), ("rmat13", 13), ("er_c1", 9),
+                                       ("hubs", 8), ("hubs", 12)])
+def test_layout_matches_definition(pr, ctx, name, bits):
+    g = GRAPHS[name]()
+    dg = segmented(pr, ctx, g, bits)
+    P, poff, sidx, moff, mpos = expected_layout(g, bits)
+    h, Pd, poff_d, sidx_d, moff_d, mpos_d = read_layout(dg)
+    assert h.seg_bits == bits and Pd == P == dg.seg_pairs
+    np.testing.assert_array_equal(poff_d, poff)
+    np.testing.assert_array_equal(sidx_d, sidx)
+    np.testing.assert_array_equal(moff_d, moff)
+    np.testing.assert_array_equal(mpos_d, mpos)
+    assert h.sl.pair_part.nhubs == 0 and int(np.diff(poff).max()) <= PAIR_MAX
+
+
+@pytest.mark.parametrize("name,bits", [("rmat13", 8), ("rmat13", 11), ("er_c1", 10), ("hubs", 9)])
+def test_fp64_parity_every_norm(pr, ctx, name, bits):
+    g = GRAPHS[name]()
+    dg = segmented(pr, ctx, g, bits)
+    for norm in (1, 2, 3):
+        for alpha, tau in ((0.85, 1e-10), (0.5, 1e-6), (0.99, 1e-8)):
+            res = pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, max_iter=500, trace=True)
+            check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], alpha, tau, norm,
+                              500, gpu_trace=res["trace"].cpu().numpy())
+
+
+def test_alpha_one_and_zero(pr, ctx):
+    g = gg.rmat(12, seed=5)
+    dg = segmented(pr, ctx, g, 8)
+    for alpha in (0.0, 1.0):
+        res = pr.pull(ctx, dg, alpha=alpha, tau=1e-9, norm=1, max_iter=300, trace=True)
+        check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], alpha, 1e-9, 1, 300,
+                          gpu_trace=res["trace"].cpu().numpy())
+
+
+def test_mixed_and_fp32_only(pr, ctx):
+    g = gg.rmat(14, seed=8)
+    dg = segmented(pr, ctx, g, 10)
+    for norm in (1, 3):
+        res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=norm, max_iter=500, precision=pr.PR_MIXED)
+        assert res["converged"] and res["fp32_iters"] >= 1
+        check_mixed_result(g, res["ranks"].cpu().numpy(), res["err"], 0.85, 1e-10, norm)
+        res = pr.pull(ctx, dg, alpha=0.85, tau=1e-7, norm=norm, max_iter=500, precision=pr.PR_FP32)
+        check_mixed_result(g, res["ranks"].cpu().numpy(), res["err"], 0.85, 1e-7, norm, fp32_only=True)
+
+
+def test_bitwise_repeatable_and_plain_switch(pr, ctx):
+    g = gg.rmat(14, seed=9)
+    dg = segmented(pr, ctx, g, 9)
+    a = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)
+    b = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)
+    assert torch.equal(a["ranks"], b["ranks"]) and a["iterations"] == b["iterations"]
+    ctx.set_option("segmented", 0)
+    try:
+        c = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)
+    finally:
+        ctx.set_option("segmented", 1)
+    assert abs(c["iterations"] - a["iterations"]) <= 1
+    assert pr.l1_distance(ctx, a["ranks"], c["ranks"]) <= 1e-12
+
+
+def test_given_start_and_edgeless(pr, ctx):
+    g = gg.rmat(12, seed=12)
+    dg = segmented(pr, ctx, g, 8)
+    rng = np.random.default_rng(3)
+    init = rng.random(g.N)
+    init /= init.sum()
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-9, norm=2, init=torch.from_numpy(init).cuda(), trace=True)
+    check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-9, 2, 500,
+                      init=init, gpu_trace=res["trace"].cpu().numpy())
+    # no edges: the plain partitions alone (every vertex dangling, 1/N after one update)
+    e = gg.from_edges(50, [], [])
+    de = segmented(pr, ctx, e, 8)
+    r = pr.pull(ctx, de, alpha=0.85, tau=1e-12, norm=1)
+    assert r["iterations"] == 1 and float((r["ranks"] - 1.0 / 50).abs().max()) < 1e-17
+
+
+def test_count_and_arguments(pr, ctx):
+    g = gg.rmat(10, seed=2)
+    dg = pr.DeviceGraph.from_host(g)
+    ws = torch.empty(16384, dtype=torch.uint8, device="cuda")
+    pairs = ctypes.c_int64()
+    lib = ctx.lib
+    for bits in (8, 10, 20):
+        assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, bits,
+                                    ws.data_ptr(), ws.numel(), ctypes.byref(pairs)) == 0
+        assert pairs.value == expected_layout(g, bits)[0]
+    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 7,
+                                ws.data_ptr(), ws.numel(), ctypes.byref(pairs)) == pr._lib.PR_EINVAL
+    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+                                ws.data_ptr(), 100, ctypes.byref(pairs)) == pr._lib.PR_ENOMEM
+    P = expected_layout(g, 10)[0]
+    nbytes = lib.pr_segment_bytes(ctx.handle, g.N, g.E, 10, P)
+    assert nbytes > lib.pr_prep_bytes(g.N, g.E)
+    assert lib.pr_segment_bytes(ctx.handle, g.N, g.E, 10, g.E + 1) == 0
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    # a pair count that is not the graph's is refused before the layout is built
+    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+                                    P - 1, buf.data_ptr(), nbytes) == pr._lib.PR_EINVAL
+    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+                                    P, buf.data_ptr(), nbytes - 1) == pr._lib.PR_ENOMEM
+
+
+def test_scale22_fp64_against_oracle(pr, ctx):
+    g = gg.rmat(22, edge_factor=16, seed=22)
+    dg = segmented(pr, ctx, g, 18)
+    print("scale 22: N %d E %d pairs %d (%.3f E)" % (g.N, g.E, dg.seg_pairs, dg.seg_pairs / g.E), flush=True)
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1, max_iter=500, trace=True)
+    ref = check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, 1, 500,
+                            gpu_trace=res["trace"].cpu().numpy())
+    print("scale 22 segmented: %d updates (oracle %d)" % (res["iterations"], ref["iterations"]), flush=True)
