@@ -5,13 +5,20 @@ Default workload (--workload sweep; one "step"): the damping-factor sweep of the
 section 2 -- eleven rank vectors for alpha = 0.50, 0.55, ..., 1.00 -- on a seeded R-MAT graph of
 scale 24 (16,777,216 vertices, edge factor 16, a,b,c,d = .57,.19,.19,.05, seed 24, duplicates
 and self-loops removed), each solved to tau = 1e-10 in the L-infinity norm (section 3) from the
-uniform start, max 500 iterations, all eleven together in one batched solve (pr_pull_batch;
-float32 gather with float64 norms, teleport terms and final float64 updates).  The graph is
-synthetic: the paper's SuiteSparse graphs are not available.
+uniform start, max 500 iterations, all eleven together.  Default path (--path series): one
+float64 iteration serves all eleven columns (pr_pull_sweep: from the uniform start the iterate of
+damping factor a is a^k v_k + (1-a) sum_{j<k} a^j v_j with v_j the a = 1 iterates, and its
+change a^k times theirs), each column stopping exactly where its own iteration would; the batched
+mixed-precision sweep (pr_pull_batch: float32 gather with float64 norms, teleport terms and final
+float64 updates) is timed beside it (--path batch_mixed makes it the headline).  The graph is
+synthetic: the paper's SuiteSparse graphs are not available; it is prepared with the
+source-segmented layout (--seg-bits, default 2^19 ids per segment).
 
 Reported:
   value            column-edge updates per second of the timed sweep (sum over the eleven columns
                    of E * iterations, divided by the step time), in GTEPS
+  batch_mixed      the batched mixed-precision sweep of the same columns (time, iterations, the
+                   roofline of its dominant kernel), when the series path is the headline
   sweep            per-column iterations, the same sweep as eleven sequential float64 solves
                    (time and speed-up), errors against them, L1 distance to the alpha=0.85 ranks
   roofline         the dominant kernel's algorithmic bytes per launch over its average launch
@@ -22,9 +29,13 @@ Reported:
                    same index array (microbench/gather_ceiling.hip), and the kernel's time as a
                    fraction of that bare time
   plain_fp64_gather  the same for the single-vector float64 update of the sequential solves
+  warm_sweep       the same sweep with learned warm starts, the alpha=0.85 solve, features, inference
+                   and the judge inside the timed step (and a variant without the judge)
   degree_order     the same sweep and sequential solves on the graph relabelled by out-degree
                    (pr_relabel, excluded from the timing like the prep), ranks mapped back
-  cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph
+  cpu_baseline     the CPU oracle (FP64, OpenMP gather) timed on a bounded sample of the same graph:
+                   the columns alpha = 0.85, 0.95, 1.00 solved in full, each compared with the
+                   headline's column (iterations, L1, L-infinity)
 
 Other workloads (one JSON line each, same keys):
   --workload small      Erdos-Renyi N=10,000 (average out-degree 8, 5% dangling), one float64 solve
@@ -210,6 +221,31 @@ def base_line(metric, value, unit, args, ms, dtype, config, higher=True):
 
 # ------------------------------------------------------------------ the damping-factor sweep
 
+def batch_roofline(pr, ctx, results, stat_steps, fp32, N, E, scale, dg, copy_gbs):
+    """Roofline of the dominant kernel of a batched sweep: the first phase's update on the widest
+    rows (the launches before the first compaction of the active columns).  Algorithmic bytes of
+    one launch with K_a active columns: 4E (indices) + 4(N+1) (offsets) + 4N (out-degrees) +
+    2*s*K_a*N (read and write of the active columns, s bytes each)."""
+    s_bytes = 4 if fp32 else 8
+    kp0 = max(w for w in pr._lib.BATCH_ROW_WIDTHS if ctx.stats(pr._lib.batch_kind(fp32, w))[0] > 0)
+    phase1 = [r["fp32_iters"] for r in results] if fp32 else [r["iterations"] for r in results]
+    n_dom, ms_dom = ctx.stats(pr._lib.batch_kind(fp32, kp0))
+    per_step = max(1, round(n_dom / stat_steps))
+    alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(per_step)]
+    avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
+    digest = source_digest([CSRC + "batch.hip", CSRC + "batch.h", CSRC + "internal.h"])
+    traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if fp32 else "f64", scale), digest)
+    out = roofline("k_batch_update<%s,%d>" % ("float" if fp32 else "double", kp0), float(np_mean(alg)), avg_launch_s,
+                   n_dom, traffic)
+    out["frac_of_stream"] = round(out["achieved"] / copy_gbs, 4)
+    add_ceiling(out, dg, kp0 * s_bytes)
+    return out
+
+
+def np_mean(x):
+    return sum(x) / len(x)
+
+
 def run_sweep(args, pr, gg, np, torch):
     scale = args.scale or 24
     seed = args.seed if args.seed is not None else 24
@@ -220,21 +256,31 @@ def run_sweep(args, pr, gg, np, torch):
     ctx = pr.Context(0)
     dg = pr.DeviceGraph.from_host(g, 0)
     t = time.time()
-    dg.prepare(ctx)
+    if args.seg_bits:
+        # tile partitions plus the source-segmented layout: single-vector updates (the sequential
+        # float64 solves, the power-series sweep) run as per-segment partial sums and a merge
+        dg.prepare_segmented(ctx, seg_bits=args.seg_bits)
+    else:
+        dg.prepare(ctx)
     torch.cuda.synchronize()
     prep_ms = (time.time() - t) * 1e3
-    log("prepared in %.1f ms" % prep_ms)
+    log("prepared in %.1f ms (segment bits %d, %d pairs)" % (prep_ms, args.seg_bits, dg.seg_pairs))
 
     alphas = gg.ALPHA_SWEEP
     tau, norm, max_iter = 1e-10, pr.PR_LINF, 500
     problems = [dict(alpha=a, tau=tau, norm=norm, max_iter=max_iter) for a in alphas]
-    K = len(problems)
-    ranks_b = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
+    ranks_h = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
     ranks_s = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
-    batch_prec = pr.PR_FP64 if args.path == "batch_fp64" else pr.PR_MIXED
 
-    def sweep_batch():
-        return pr.pull_batch(ctx, dg, problems, precision=batch_prec, ranks=ranks_b)
+    def sweep_series():
+        return pr.pull_sweep(ctx, dg, problems, ranks=ranks_h)
+
+    def sweep_batch(prec, ranks):
+        return pr.pull_batch(ctx, dg, problems, precision=prec, ranks=ranks)
+
+    headline = {"series": sweep_series,
+                "batch_mixed": lambda: sweep_batch(pr.PR_MIXED, ranks_h),
+                "batch_fp64": lambda: sweep_batch(pr.PR_FP64, ranks_h)}[args.path]
 
     def sweep_sequential():
         return [pr.pull(ctx, dg, alpha=p["alpha"], tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64,
@@ -251,14 +297,25 @@ def run_sweep(args, pr, gg, np, torch):
     sweep_sequential()
     ctx.set_option("timing", 0)
     n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+    # the same float64 update without the segmented layout (one solve, event-timed), for comparison
+    plain64_us = None
+    if args.seg_bits:
+        ctx.set_option("segmented", 0)
+        ctx.reset_stats()
+        ctx.set_option("timing", 1)
+        pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_FP64)
+        ctx.set_option("timing", 0)
+        ctx.set_option("segmented", 1)
+        a, b = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+        plain64_us = 1e3 * b / a if a else None
     seq_times, seq_res = timed(sweep_sequential, args.seq_reps, "sequential fp64 sweep")
     seq_s = float(np.mean(seq_times))
 
     for i in range(args.warmup):
-        sweep_batch()
+        headline()
         log("warmup %d done" % (i + 1))
     # the timed steps run as a caller runs them (captured update chunks replayed as HIP graphs)
-    times, results = timed(sweep_batch, args.steps, "step (batched sweep)")
+    times, results = timed(headline, args.steps, "step (%s sweep)" % args.path)
     step_s = float(np.mean(times))
     # per-launch kernel times: HIP events cannot bracket the kernels of a replayed graph, so the
     # same step runs again with every update launched directly between two events on the solve
@@ -266,58 +323,60 @@ def run_sweep(args, pr, gg, np, torch):
     stat_steps = max(1, min(args.steps, 5))
     ctx.reset_stats()
     ctx.set_option("timing", 1)
-    ev_times, _ = timed(sweep_batch, stat_steps, "step with per-launch events")
+    ev_times, _ = timed(headline, stat_steps, "step with per-launch events")
     ctx.set_option("timing", 0)
     iters = [r["iterations"] for r in results]
     col_edges = sum(E * k for k in iters)
     gteps = col_edges / step_s / 1e9
-
-    # dominant kernel: the batched update of the first phase (float32 for the mixed path) on the
-    # widest rows, i.e. the launches before the first compaction of the active columns.
-    # Algorithmic bytes of one launch with K_a active columns: 4E (indices) + 4(N+1) (offsets)
-    # + 4N (out-degrees) + 2*s*K_a*N (read and write of the active columns, s bytes each).
-    fp32 = batch_prec == pr.PR_MIXED
-    s_bytes = 4 if fp32 else 8
-    # the widest row width that ran: the one of the first launches
-    kp0 = max(w for w in pr._lib.BATCH_ROW_WIDTHS if ctx.stats(pr._lib.batch_kind(fp32, w))[0] > 0)
-    dom_kind = pr._lib.batch_kind(fp32, kp0)
-    phase1 = [r["fp32_iters"] for r in results] if fp32 else iters
-    n_dom, ms_dom = ctx.stats(dom_kind)
-    per_step = max(1, round(n_dom / stat_steps))
-    alg = [4 * E + 4 * (N + 1) + 4 * N + 2 * s_bytes * N * sum(1 for k in phase1 if k > i) for i in range(per_step)]
-    alg_per_launch = float(np.mean(alg))
-    avg_launch_s = (ms_dom / n_dom) * 1e-3 if n_dom else float("nan")
-    n_f64, ms_f64 = ctx.stats(pr._lib.PR_KERNEL_BATCH_F64)
-    n_all, ms_all = ctx.stats(pr._lib.PR_KERNEL_BATCH_F32 if fp32 else pr._lib.PR_KERNEL_BATCH_F64)
-    kname = "k_batch_update<%s,%d>" % ("float" if fp32 else "double", kp0)
-    digest = source_digest([CSRC + "batch.hip", CSRC + "batch.h", CSRC + "internal.h"])
-    traffic = read_traffic("batch_update_%s_rmat_s%d" % ("f32" if s_bytes == 4 else "f64", scale), digest)
-    d64 = source_digest([CSRC + "pull.hip", CSRC + "device.h", CSRC + "internal.h"])
+    d64 = source_digest([CSRC + "pull.hip", CSRC + "device.h", CSRC + "internal.h", CSRC + "segment.hip"])
     traffic64 = read_traffic("update_f64_rmat_s%d" % scale, d64)
+    b64 = single_update_bytes(N, E, 8)
+    name64 = ("segmented float64 update (k_seg_gather<double> + k_update<double> merge + k_finish<double>)"
+              if args.seg_bits else "k_update<double>")
 
-    # section 2 report: L1 distance of every column to the alpha = 0.85 column; and the batched
+    extra = {}
+    if args.path == "series":
+        # dominant kernel: the a = 1 iteration's float64 update (one per update of the slowest column)
+        nu, msu = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
+        nf, msf = ctx.stats(pr._lib.PR_KERNEL_SWEEP_FOLD)
+        roof = roofline(name64, b64, msu / nu * 1e-3, nu, traffic64)
+        roof["frac_of_stream"] = round(roof["achieved"] / copy_gbs, 4)
+        add_ceiling(roof, dg, 8)
+        extra = {"updates_per_step": round(nu / stat_steps, 2), "update_us": round(1e3 * msu / nu, 1),
+                 "folds_per_step": round(nf / stat_steps, 2), "fold_us": round(1e3 * msf / nf, 1) if nf else None}
+        dtype = "f64"
+        how = ("float64, one iteration for all columns (PageRank as a power series in the damping factor: the a = 1 "
+               "iterates v_j, column a's change a^k (v_k - v_{k-1}), ranks a^k v_k + (1-a) sum_{j<k} a^j v_j)")
+    else:
+        fp32 = args.path == "batch_mixed"
+        roof = batch_roofline(pr, ctx, results, stat_steps, fp32, N, E, scale, dg, copy_gbs)
+        dtype = "f32+f64" if fp32 else "f64"
+        how = "float32 gather + float64 norms/c0/refinement" if fp32 else "float64 batch"
+
+    # section 2 report: L1 distance of every column to the alpha = 0.85 column; and the sweep's
     # result against the sequential FP64 solves
     i85 = list(alphas).index(0.85)
     l1_vs_085 = [pr.l1_distance(ctx, r["ranks"], results[i85]["ranks"]) for r in results]
-    l1_vs_fp64 = [pr.l1_distance(ctx, rb, rs) for rb, rs in zip(ranks_b, ranks_s)]
-    linf_vs_fp64 = [float((rb - rs).abs().max()) for rb, rs in zip(ranks_b, ranks_s)]
+    l1_vs_fp64 = [pr.l1_distance(ctx, rb, rs) for rb, rs in zip(ranks_h, ranks_s)]
+    linf_vs_fp64 = [float((rb - rs).abs().max()) for rb, rs in zip(ranks_h, ranks_s)]
 
-    line = base_line(METRIC, round(gteps, 3), "GTEPS", args, step_s * 1e3,
-                     "f32+f64" if batch_prec == pr.PR_MIXED else "f64", {
-                         "workload": "alpha sweep: 11 rank columns alpha=0.50..1.00 solved together to tau=1e-10 "
-                                     "(Linf) on R-MAT scale %d, edge factor 16, (.57,.19,.19,.05), seed %d; %s" % (
-                                         scale, seed, "float32 gather + float64 norms/c0/refinement"
-                                         if batch_prec == pr.PR_MIXED else "float64"),
-                         "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path})
-    line["roofline"] = roofline(kname, alg_per_launch, avg_launch_s, n_dom, traffic)
-    line["roofline"]["frac_of_stream"] = round(line["roofline"]["achieved"] / copy_gbs, 4)
+    line = base_line(METRIC, round(gteps, 3), "GTEPS", args, step_s * 1e3, dtype, {
+        "workload": "alpha sweep: 11 rank columns alpha=0.50..1.00 solved together to tau=1e-10 (Linf) on R-MAT "
+                    "scale %d, edge factor 16, (.57,.19,.19,.05), seed %d; %s" % (scale, seed, how),
+        "N": N, "E": E, "tau": tau, "norm": "Linf", "max_iter": max_iter, "path": args.path})
+    line["roofline"] = roof
     if n64:
-        b64 = single_update_bytes(N, E, 8)
-        line["plain_fp64_gather"] = roofline("k_update<double>", b64, ms64 / n64 * 1e-3, n64, traffic64)
+        line["plain_fp64_gather"] = roofline(name64, b64, ms64 / n64 * 1e-3, n64, traffic64)
         line["plain_fp64_gather"]["gteps_per_update"] = round(E / (ms64 / n64 * 1e-3) / 1e9, 2)
         line["plain_fp64_gather"]["frac_of_stream"] = round(line["plain_fp64_gather"]["achieved"] / copy_gbs, 4)
+        if args.seg_bits:
+            line["plain_fp64_gather"]["segment_bits"] = args.seg_bits
+            line["plain_fp64_gather"]["pairs"] = dg.seg_pairs
+            line["plain_fp64_gather"]["unsegmented_update_us"] = round(plain64_us, 1) if plain64_us else None
+            if plain64_us:
+                line["plain_fp64_gather"]["unsegmented_frac"] = round(b64 / (plain64_us * 1e-6) / 1e9 /
+                                                                      HBM_PEAK_GBS, 4)
         add_ceiling(line["plain_fp64_gather"], dg, 8)
-    add_ceiling(line["roofline"], dg, kp0 * s_bytes)
     line["stream_copy_GBps"] = round(copy_gbs, 1)
     line["sweep"] = {
         "alphas": list(alphas), "iterations": iters, "fp32_iters": [r["fp32_iters"] for r in results],
@@ -328,24 +387,120 @@ def run_sweep(args, pr, gg, np, torch):
         "speedup_vs_sequential_fp64": round(seq_s / step_s, 3),
         "l1_vs_alpha_085": [round(x, 6) for x in l1_vs_085],
         "l1_vs_sequential_fp64": l1_vs_fp64, "linf_vs_sequential_fp64": linf_vs_fp64,
-        "batch_f64_update_us": round(1e3 * ms_f64 / n_f64, 2) if n_f64 else None,
         "step_ms_min_median": [round(min(times) * 1e3, 3), round(float(np.median(times)) * 1e3, 3)],
         "step_ms_with_launch_events": round(float(np.mean(ev_times)) * 1e3, 3),
-        "graph_passes_per_s": round((n_all / stat_steps + max(r["fp64_iters"] for r in results)) / step_s, 2)
-        if n_all else None,
-        "first_phase_updates_per_step": round(n_all / stat_steps, 2) if n_all else None,
-        "first_phase_update_us_all_widths": round(1e3 * ms_all / n_all, 2) if n_all else None,
     }
+    line["sweep"].update(extra)
+    if args.path == "series":
+        # the batched mixed-precision sweep of the same columns, timed beside it
+        ranks_m = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in alphas]
+        mixed = lambda: sweep_batch(pr.PR_MIXED, ranks_m)  # noqa: E731
+        mixed()
+        ts_m, res_m = timed(mixed, max(1, min(args.steps, 5)), "step (batched mixed sweep)")
+        ctx.reset_stats()
+        ctx.set_option("timing", 1)
+        timed(mixed, 2, "batched mixed sweep with per-launch events")
+        ctx.set_option("timing", 0)
+        step_m = float(np.mean(ts_m))
+        line["batch_mixed"] = {
+            "step_ms": round(step_m * 1e3, 3), "gteps": round(sum(E * r["iterations"] for r in res_m) / step_m / 1e9, 3),
+            "iterations": [r["iterations"] for r in res_m], "fp32_iters": [r["fp32_iters"] for r in res_m],
+            "speedup_vs_sequential_fp64": round(seq_s / step_m, 3),
+            "linf_vs_headline": [float((a - b).abs().max()) for a, b in zip(ranks_m, ranks_h)],
+            "roofline": batch_roofline(pr, ctx, res_m, 2, True, N, E, scale, dg, copy_gbs)}
+        del ranks_m
+    if not args.no_warm:
+        line["warm_sweep"] = warm_sweep(args, pr, gg, ctx, dg, problems, tau, norm, max_iter, step_s, iters, np, torch)
     if not args.no_relabel:
-        line["degree_order"] = relabelled_sweep(args, pr, ctx, dg, problems, batch_prec, tau, norm, max_iter, N, E,
-                                                step_s, seq_s, ranks_b, torch, np)
+        line["degree_order"] = relabelled_sweep(args, pr, ctx, dg, problems, args.path, tau, norm, max_iter, N, E,
+                                                step_s, seq_s, ranks_h, torch, np)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline([g], args.cpu_seconds, "the full graph")
+        line["cpu_baseline"] = cpu_baseline_sweep(g, problems, results, np)
     ctx.close()
     return line
 
 
-def relabelled_sweep(args, pr, ctx, dg, problems, batch_prec, tau, norm, max_iter, N, E, step_s, seq_s, ranks_b,
+def cpu_baseline_sweep(g, problems, results, np):
+    """The oracle (FP64, OpenMP gather) timed on a bounded sample of the sweep: the columns alpha =
+    0.85, 0.95 and 1.00 solved in full (tau = 1e-10, Linf, uniform start), each compared with the
+    headline's column (iterations, L1 and L-infinity distance)."""
+    import oracle
+    log("cpu oracle sample: three full columns")
+    pick = [i for i, p in enumerate(problems) if round(p["alpha"], 2) in (0.85, 0.95, 1.0)]
+    spent, edges, cmp = 0.0, 0, {}
+    for i in pick:
+        p = problems[i]
+        t = time.perf_counter()
+        ref = oracle.pagerank_graph(g, alpha=p["alpha"], tau=p["tau"], norm=p["norm"], max_iter=p["max_iter"])
+        spent += time.perf_counter() - t
+        edges += g.E * ref["iterations"]
+        d = np.abs(results[i]["ranks"].cpu().numpy() - ref["ranks"])
+        cmp["%.2f" % p["alpha"]] = {"oracle_iterations": ref["iterations"], "gpu_iterations": results[i]["iterations"],
+                                    "l1": float(d.sum()), "linf": float(d.max())}
+    log("cpu oracle: %d edge visits in %.2f s" % (edges, spent))
+    return {"value": round(edges / spent / 1e9, 4), "unit": "GTEPS", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "the columns alpha = 0.85, 0.95, 1.00 of the sweep solved in full by the FP64 oracle "
+                      "(%d updates in all over the full graph, %.1f s); host CPU %s"
+                      % (edges // g.E, spent, cpu_model()),
+            "headline_vs_oracle": cmp}
+
+
+def warm_sweep(args, pr, gg, ctx, dg, problems, tau, norm, max_iter, step_s, iters_uniform, np, torch):
+    """The same sweep with learned warm starts (not part of the headline): the alpha = 0.85 column is
+    solved first (mixed precision, uniform start); for every other alpha the network proposes a start
+    from it (features + inference); the judge runs the candidate starts {network, alpha = 0.85 ranks,
+    uniform} for three float64 updates as columns of one batch and keeps the smallest last change;
+    then the ten remaining columns are solved together (mixed) from the judged iterates.  The timed
+    step includes all of it.  A second variant skips the judge (network starts as proposed).  The
+    network is trained first on ranks the method produces (R-MAT scale-20 graphs, seeds from 2000)."""
+    from paper_2108_02997_amd import warmstart as wsm
+    model = wsm.WarmStart(ctx, seed=0)
+    train_alphas = [0.5, 0.55, 0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95, 0.99]
+    t0 = time.time()
+    samples = []
+    for s in range(args.warm_graphs):
+        h = gg.rmat(20, edge_factor=16, seed=2000 + s)
+        samples += model.make_samples(pr.DeviceGraph.from_host(h, 0), train_alphas)
+    hist = model.train(samples, epochs=args.epochs, lr=3e-3)
+    del samples
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log("warm start: trained on %d graphs in %.1f s (loss %.4f -> %.4f)" % (args.warm_graphs, train_s, hist[0],
+                                                                           hist[-1]))
+    alphas = [p["alpha"] for p in problems]
+    i85 = alphas.index(0.85)
+    others = [p for i, p in enumerate(problems) if i != i85]
+
+    def step(judged):
+        r85 = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm, max_iter=max_iter, precision=pr.PR_MIXED)
+        starts, choices, look = [], [], 0
+        for p in others:
+            if judged:
+                r0, name, _, steps, _ = model.start(dg, r85["ranks"], p["alpha"], norm=norm)
+                look = steps
+            else:
+                r0, name = model.propose(dg, r85["ranks"], p["alpha"]), "mlp"
+            starts.append(r0)
+            choices.append(name)
+        res = pr.pull_batch(ctx, dg, others, precision=pr.PR_MIXED, inits=starts)
+        return r85, res, choices, look
+
+    out = {"train_graphs": args.warm_graphs, "train_s": round(train_s, 2), "epochs": args.epochs}
+    for judged in (True, False):
+        tag = "judged" if judged else "network_only"
+        step(judged)
+        ts, (r85, res, choices, look) = timed(lambda: step(judged), max(1, min(args.steps, 3)),
+                                              "warm-started sweep (%s)" % tag)
+        t = float(np.mean(ts))
+        its = [look + r["iterations"] for r in res]
+        its.insert(i85, r85["iterations"])
+        out[tag] = {"step_ms": round(t * 1e3, 3), "vs_uniform_sweep": round(step_s / t, 3),
+                    "iterations": its, "choices": choices, "look_ahead_updates": look,
+                    "max_iterations_uniform": max(iters_uniform), "max_iterations_warm": max(its)}
+    return out
+
+
+def relabelled_sweep(args, pr, ctx, dg, problems, path, tau, norm, max_iter, N, E, step_s, seq_s, ranks_b,
                      torch, np):
     """The same sweep and sequential solves on the graph in out-degree order (pr_relabel, timed on
     its own; not part of the headline numbers), the ranks mapped back and compared."""
@@ -354,9 +509,16 @@ def relabelled_sweep(args, pr, ctx, dg, problems, batch_prec, tau, norm, max_ite
     dh, perm = dg.relabelled(ctx)
     torch.cuda.synchronize()
     relabel_ms = (time.perf_counter() - t0) * 1e3
-    dh.prepare(ctx)
+    if args.seg_bits:
+        dh.prepare_segmented(ctx, seg_bits=args.seg_bits)
+    else:
+        dh.prepare(ctx)
     log("relabelled by out-degree in %.1f ms" % relabel_ms)
-    sweep = lambda: pr.pull_batch(ctx, dh, problems, precision=batch_prec)  # noqa: E731
+    if path == "series":
+        sweep = lambda: pr.pull_sweep(ctx, dh, problems)  # noqa: E731
+    else:
+        prec = pr.PR_MIXED if path == "batch_mixed" else pr.PR_FP64
+        sweep = lambda: pr.pull_batch(ctx, dh, problems, precision=prec)  # noqa: E731
     seq = lambda: [pr.pull(ctx, dh, alpha=p["alpha"], tau=tau, norm=norm, max_iter=max_iter,  # noqa: E731
                            precision=pr.PR_FP64) for p in problems]
     sweep()
@@ -607,7 +769,10 @@ def run_multi(args, pr, gg, np, torch):
                      "max_l1_vs_sequential": max(pr.l1_distance(ctx, a["ranks"], b["ranks"])
                                                  for a, b in zip(res, seq_res)),
                      "prep_ms": round(prep_ms, 2), "autotune_s": round(tune_s, 2),
-                     "tuned_mid_deg": [t["mid_deg"] for t in tuned], "tuned_grid": [t["grid"] for t in tuned]}
+                     "tuned_mid_deg": [t["mid_deg"] for t in tuned], "tuned_grid": [t["grid"] for t in tuned],
+                     "tuned_tile": [t["tile"] for t in tuned], "tuned_tile_batch": [t["tile_batch"] for t in tuned],
+                     "tuned_mid_deg_batch": [t["mid_deg_batch"] for t in tuned],
+                     "tuned_grid_batch_factor": [t["grid_batch_factor"] for t in tuned]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(hosts, args.cpu_seconds, "all 64 graphs")
     ctx.close()
@@ -838,10 +1003,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--calibrate", action="store_true", help="accepted for older command lines; the 1 GiB copy "
                     "that calibrates the memory counters now always runs")
-    ap.add_argument("--path", choices=["batch_mixed", "batch_fp64"], default="batch_mixed",
-                    help="the timed sweep: batched mixed precision (default) or batched float64")
+    ap.add_argument("--path", choices=["series", "batch_mixed", "batch_fp64"], default="series",
+                    help="the timed sweep: one float64 iteration for all columns (power series in the damping "
+                         "factor, default), the batched mixed-precision columns, or batched float64 columns")
     ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 baseline")
     ap.add_argument("--epochs", type=int, default=20, help="training epochs of the warm-start network")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-started sweep")
+    ap.add_argument("--seg-bits", type=int, default=19, help="source segments of 2^bits ids for the single-vector "
+                    "solves of the sweep workload (0: the plain update)")
+    ap.add_argument("--warm-graphs", type=int, default=8, help="training graphs of the warm-started sweep's network")
     args = ap.parse_args()
 
     if args.gpus != 1:

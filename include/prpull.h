@@ -95,7 +95,10 @@ const char *pr_version(void);
  *             a host check costs tens of microseconds, an update past the stop a few)
  *   "loop"  : 0 = replay captured HIP graphs (default), 1 = launch the updates one by one
  *   "mid_deg": rows of at most this many in-edges are summed by one lane, longer rows (up to the
- *             1024-entry tile window) by a whole wave64, 0..1024 (default 32)
+ *             tile window) by a whole wave64, 0..1024 (default 32); pr_pull only
+ *   "tile"  : tile window of partition A written by later prepares: 1024 (default), 512 or 256
+ *             entries (rows = entries / 2)
+ *   "tile_b": the same for partition B (the K-column tiles): 256 (default) or 128
  *   "tuned" : 1 (default) = use the autotuner's choice for graphs it has seen (pr_autotune)
  *   "batch_chunk": updates of pr_pull_batch between two host checks, even, 2..64 (default 2)
  *   "compact": 1 (default) = when enough columns of pr_pull_batch have stopped, repack the
@@ -123,6 +126,7 @@ enum {
   PR_KERNEL_BATCH_F64 = 2,  /* one float64 update of pr_pull_batch (all active columns) */
   PR_KERNEL_BATCH_F32 = 3,  /* one float32 update of pr_pull_batch */
   PR_KERNEL_MULTI = 4,      /* one whole pr_pull_multi launch (all rounds of all graphs) */
+  PR_KERNEL_SWEEP_FOLD = 5, /* one fold of pr_pull_sweep (a chunk of iterates into the columns) */
   /* pr_pull_batch updates again, split by the row width (values per vertex) the update ran on:
    * widths 1, 2, 4, 8, 12, 16 are kinds ..._W1 + 0 .. 5 */
   PR_KERNEL_BATCH_F64_W1 = 8,
@@ -263,6 +267,37 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
                   int32_t precision, const double *const *init, double *const *ranks, double *const *norm_trace,
                   void *workspace, size_t workspace_bytes, pr_result *results);
 
+/* ------------------------------------------------------------------ the damping-factor sweep */
+
+/* Device workspace bytes of pr_pull_sweep (0 for out-of-range sizes); with_prep as for pr_pull. */
+size_t pr_sweep_workspace_bytes(int64_t N, int64_t E, int32_t with_prep);
+
+/* K problems on one graph that differ only in damping factor, tolerance, error function and
+ * max_iter, all from the uniform start: the damping-factor sweep of section 2 (with any mix of
+ * the tolerances and error functions of sections 3-4), in float64, by ONE iteration.  From the
+ * uniform start u, k updates of section 2's map with damping factor a give
+ *     r_a(k) = a^k v_k + (1 - a) sum_{j<k} a^j v_j,   v_j = the iterates of the a = 1 map from u
+ * (PageRank as a power series in the damping factor), and the change of update k, in every norm,
+ * is a^k times the change of the a = 1 iteration's update k.  pr_pull_sweep runs the a = 1
+ * iteration (the float64 update of pr_pull, source-segmented when prep has that layout); after
+ * every update each problem's change a_k^k e_k decides its stop exactly as its own iteration
+ * would (same tolerance test, same count), and every 16 updates the iterates are added with the
+ * weights above into each problem's ranks.  Each result (ranks, iterations, converged, final
+ * errors, trace rows) is that of problem k's own power iteration up to float64 rounding; the
+ * iteration runs until the last problem stops.
+ *   K          : 1..64
+ *   probs      : host, K problems (any alpha in [0, 1], tau >= 0, norm, max_iter >= 1)
+ *   ranks      : host array of K distinct device pointers (N float64 each, out)
+ *   norm_trace : host array of K device pointers (max_iter x 3 float64 each) or NULL
+ *   workspace  : device, >= pr_sweep_workspace_bytes(N, E, prep == NULL) (holds 17 iterates)
+ *   results    : host, K entries (fp32_iters = 0)
+ * Returns PR_OK when every problem converged, PR_NOT_CONVERGED when at least one stopped at its
+ * max_iter, or a negative status. */
+int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                  const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
+                  double *const *ranks, double *const *norm_trace, void *workspace, size_t workspace_bytes,
+                  pr_result *results);
+
 /* ------------------------------------------------------------------ many graphs, one launch */
 
 /* One graph of a many-graph batch with its own parameters (sections 2 and 3). */
@@ -297,23 +332,41 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
 /* ------------------------------------------------------------------ autotuner */
 
 typedef struct {
-  int32_t mid_deg;    /* chosen lane-per-row / wave-per-row threshold */
-  int32_t grid;       /* chosen number of update workgroups */
-  int32_t candidates; /* configurations timed */
+  int32_t mid_deg;           /* single-vector update: lane-per-row / wave-per-row threshold */
+  int32_t grid;              /* single-vector update: workgroups */
+  int32_t tile, rows;        /* partition A tile window (entries, rows): 1024/512, 512/256 or 256/128 */
+  int32_t mid_deg_batch;     /* K-column update: group-per-row / wave-per-row threshold */
+  int32_t grid_batch_factor; /* K-column update: workgroups per resident slot (1 or 2) */
+  int32_t tile_batch, rows_batch; /* partition B tile window: 256/128 or 128/64 */
+  int32_t candidates;        /* configurations timed */
   int32_t pad;
-  double best_us;     /* mean float64 update time of the choice, microseconds */
-  double default_us;  /* the same with the defaults (threshold 32, one workgroup per resident slot) */
+  double best_us;            /* mean float64 update time of the choice, microseconds */
+  double default_us;         /* the same with the defaults (1024/512, threshold 32, one workgroup per slot) */
+  double best_batch_us;      /* mean 8-column float32 update time of the batch choice */
+  double default_batch_us;   /* the same with the defaults (256/128, threshold 32, one workgroup per slot) */
 } pr_tune_result;
 
-/* Times four float64 updates of this graph for every candidate (threshold 8/16/32/64/128 x
- * 1/2/4 workgroups per resident slot) and keeps the fastest in the context's table, keyed by
- * the graph's size and tile counts; pr_pull and pr_pull_multi then use it for graphs with that
- * signature unless "grid" / "mid_deg" were set explicitly or "tuned" is 0.  With the
- * environment variable PRPULL_TUNE_FILE set, the table is read at pr_create and every choice is
- * appended to that file.  ranks: device scratch of N values; workspace as for pr_pull.
- * Statistics of pr_get_stats are left as they were. */
+/* Device workspace bytes of pr_autotune (0 for out-of-range sizes); with_prep as for pr_pull. */
+size_t pr_tune_workspace_bytes(int64_t N, int64_t E, int32_t with_prep);
+
+/* The tile windows and degree-bin thresholds of this graph's updates, chosen by timing them (the
+ * hot path's partition and lane/wave/block bins, section 2 update).
+ *   single-vector float64 update (pr_pull, pr_pull_multi): partition A window 1024/512, 512/256 or
+ *     256/128 entries/rows (rows longer than the window are split over workgroups) x lane/wave
+ *     threshold 8/16/32/64/128 x 1/2/4 workgroups per resident slot, four updates each, timed on
+ *     the plain (unsegmented) update;
+ *   K-column float32 update (pr_pull_batch): partition B window 256/128 or 128/64 x group/wave
+ *     threshold 16/32/64 x 1/2 workgroups per resident slot, three updates of 8 columns each.
+ * The chosen windows are written into the prep buffer (prep != NULL: re-partitioned in place; a
+ * source-segmented layout in it is kept), and the thresholds and grids are kept in the context's
+ * table, keyed by the graph's size, tile counts and windows; pr_pull, pr_pull_multi and
+ * pr_pull_batch then use them for graphs with that signature unless "grid" / "mid_deg" were set
+ * explicitly or "tuned" is 0.  With the environment variable PRPULL_TUNE_FILE set, the table is
+ * read at pr_create and every choice is appended to that file.  ranks: device scratch of N
+ * values; workspace: device, >= pr_tune_workspace_bytes(N, E, prep == NULL).  Statistics of
+ * pr_get_stats are left as they were. */
 int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
-                const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
+                const int32_t *outdeg, int64_t N, int64_t E, void *prep, double *ranks, void *workspace,
                 size_t workspace_bytes, pr_tune_result *out);
 
 /* ------------------------------------------------------------------ learned warm start

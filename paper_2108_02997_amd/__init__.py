@@ -150,18 +150,19 @@ class DeviceGraph:
         return ws
 
     def autotune(self, ctx: Context) -> dict:
-        """pr_autotune: pick the lane/wave threshold and the update grid for this graph (kept in ctx)."""
+        """pr_autotune: choose the tile windows (written into this graph's prep), the degree-bin
+        thresholds and the grids of the single-vector and K-column updates (kept in ctx)."""
         if self.prep is None:
             self.prepare(ctx)
         ranks = torch.empty(self.N, dtype=torch.float64, device=self.off.device)
-        ws = self.workspace(ctx, PR_FP64, False)
+        nbytes = ctx.lib.pr_tune_workspace_bytes(self.N, self.E, 0)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.off.device)
         out = _lib.pr_tune_result()
         _lib.check("pr_autotune", ctx.lib.pr_autotune(ctx.handle, ctx.stream, self.off.data_ptr(),
                                                       _lib.ptr(self.idx) if self.E else None, self.outdeg.data_ptr(),
                                                       self.N, self.E, self.prep.data_ptr(), ranks.data_ptr(),
                                                       ws.data_ptr(), ws.numel(), ctypes.byref(out)))
-        return dict(mid_deg=out.mid_deg, grid=out.grid, candidates=out.candidates, best_us=out.best_us,
-                    default_us=out.default_us)
+        return {n: getattr(out, n) for n, _ in _lib.pr_tune_result._fields_ if n != "pad"}
 
     def validate(self, ctx: Context) -> None:
         nbytes = 4 * self.N + 512
@@ -279,6 +280,52 @@ def pull_batch(ctx: Context, g: DeviceGraph, problems, precision: int = PR_FP64,
             r["ranks"] = ranks[sl.start + j]
             r["trace"] = traces[sl.start + j][:r["iterations"]] if trace else None
             out.append(r)
+    return out
+
+
+MAX_SWEEP = 64
+
+
+def pull_sweep(ctx: Context, g: DeviceGraph, problems, trace: bool = False, ranks=None) -> list:
+    """pr_pull_sweep: problems that differ only in alpha / tau / norm / max_iter, all from the
+    uniform start, solved in float64 by one iteration (the sweep as a power series in the damping
+    factor).  Returns one dict per problem like pull_batch."""
+    if g.prep is None:
+        g.prepare(ctx)
+    K = len(problems)
+    if not 1 <= K <= MAX_SWEEP:
+        raise ValueError("pr_pull_sweep takes 1..64 problems")
+    dev = g.off.device
+    if ranks is None:
+        ranks = [torch.empty(g.N, dtype=torch.float64, device=dev) for _ in range(K)]
+    for r in ranks:
+        if r.dtype != torch.float64 or r.numel() != g.N or not r.is_contiguous() or r.device != dev:
+            raise ValueError("rank vectors must be contiguous float64 tensors of N elements on the graph's device")
+    traces = ([torch.full((int(p["max_iter"]), 3), float("nan"), dtype=torch.float64, device=dev)
+               for p in problems] if trace else None)
+    probs = (pr_problem * K)(*[pr_problem(float(p["alpha"]), float(p["tau"]), int(p["norm"]), int(p["max_iter"]))
+                              for p in problems])
+    vp = ctypes.c_void_p
+    rank_arr = (vp * K)(*[r.data_ptr() for r in ranks])
+    trace_arr = (vp * K)(*[t.data_ptr() for t in traces]) if trace else None
+    key = ("sweep",)
+    ws = g._ws.get(key)
+    if ws is None:
+        nbytes = ctx.lib.pr_sweep_workspace_bytes(g.N, g.E, 0)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        g._ws[key] = ws
+    res = (pr_result * K)()
+    st = ctx.lib.pr_pull_sweep(ctx.handle, ctx.stream, g.off.data_ptr(), _lib.ptr(g.idx) if g.E else None,
+                               g.outdeg.data_ptr(), g.N, g.E, g.prep.data_ptr(), K, probs, rank_arr, trace_arr,
+                               ws.data_ptr(), ws.numel(), res)
+    _lib.check("pr_pull_sweep", st)
+    out = []
+    for k, r in enumerate(res):
+        d = r.as_dict()
+        d["status"] = st
+        d["ranks"] = ranks[k]
+        d["trace"] = traces[k][:d["iterations"]] if trace else None
+        out.append(d)
     return out
 
 

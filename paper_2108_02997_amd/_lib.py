@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "prpull.h")
 PR_L1, PR_L2, PR_LINF = 1, 2, 3
 PR_FP64, PR_MIXED, PR_FP32 = 0, 1, 2
 PR_KERNEL_UPDATE_F64, PR_KERNEL_UPDATE_F32, PR_KERNEL_BATCH_F64, PR_KERNEL_BATCH_F32, PR_KERNEL_MULTI = 0, 1, 2, 3, 4
+PR_KERNEL_SWEEP_FOLD = 5
 PR_KERNEL_BATCH_F64_W1, PR_KERNEL_BATCH_F32_W1, PR_KERNEL_KINDS = 8, 14, 20
 BATCH_ROW_WIDTHS = (1, 2, 4, 8, 12, 16)
 
@@ -56,8 +57,10 @@ class pr_graph_problem(ctypes.Structure):
 
 
 class pr_tune_result(ctypes.Structure):
-    _fields_ = [("mid_deg", ctypes.c_int32), ("grid", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+    _fields_ = [(n, ctypes.c_int32) for n in ("mid_deg", "grid", "tile", "rows", "mid_deg_batch",
+                                              "grid_batch_factor", "tile_batch", "rows_batch", "candidates",
+                                              "pad")] + \
+               [(n, ctypes.c_double) for n in ("best_us", "default_us", "best_batch_us", "default_batch_us")]
 
 
 class PrError(RuntimeError):
@@ -91,6 +94,7 @@ SIGNATURES = {
     "pr_multi_workspace_bytes": ([_i32, ctypes.POINTER(pr_graph_problem)], _sz),
     "pr_pull_multi": ([_vp, _vp, _i32, ctypes.POINTER(pr_graph_problem), _vp, _sz, ctypes.POINTER(pr_result)],
                       ctypes.c_int),
+    "pr_tune_workspace_bytes": ([_i64, _i64, _i32], _sz),
     "pr_autotune": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _sz, ctypes.POINTER(pr_tune_result)],
                     ctypes.c_int),
     "pr_mlp_param_count": ([], ctypes.c_int),
@@ -102,6 +106,9 @@ SIGNATURES = {
                       ctypes.c_float, _i32], ctypes.c_int),
     "pr_warm_start_vector": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _sz], ctypes.c_int),
     "pr_l1_distance": ([_vp, _vp, _vp, _vp, _i64, _vp, _sz, ctypes.POINTER(_dbl)], ctypes.c_int),
+    "pr_sweep_workspace_bytes": ([_i64, _i64, _i32], _sz),
+    "pr_pull_sweep": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem),
+                       ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _sz, ctypes.POINTER(pr_result)], ctypes.c_int),
     "pr_batch_workspace_bytes": ([_i64, _i64, _i32, _i32, _i32], _sz),
     "pr_pull_batch": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, ctypes.POINTER(pr_problem), _i32,
                        ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _sz,

@@ -68,13 +68,26 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
   h.N = N;
   h.E = E;
   h.seg = kSeg;
+  return prepare_parts(ctx, s, off, N, E, prep, (int)ctx->window_tile[0], (int)ctx->window_tile[1], &h, out);
+}
+
+// Partitions A and B of `prep` with the given tile windows (rows = tile / 2) into header h (its
+// other fields kept), header written and remembered.
+int prepare_parts(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep, int tile_a,
+                  int tile_b, PrepHeader *hin, PrepHeader *out) {
+  PrepHeader h = *hin;
+  const int tiles[2] = {tile_a, tile_b};
   int64_t o = (int64_t)align_up(sizeof(PrepHeader), 256);
   for (int i = 0; i < 2; ++i) {
     PrepPart &pp = h.part[i];
-    pp.tile = kPartTile[i];
-    pp.rows = kPartRows[i];
+    pp.tile = tiles[i];
+    pp.rows = tiles[i] / 2;
+    if (!valid_window(i, pp.tile, pp.rows)) {
+      set_error("internal: tile window %d/%d not available for partition %d", pp.tile, pp.rows, i);
+      return PR_EINVAL;
+    }
     pp.desc_off = o;
-    o += (int64_t)align_up((size_t)(max_desc(N, E, pp.tile, pp.rows) + 1) * sizeof(int4), 256);
+    o += (int64_t)align_up((size_t)(max_desc(N, E, kMinPartTile[i], kMinPartRows[i]) + 1) * sizeof(int4), 256);
     pp.hub_off = o;
     o += (int64_t)align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
   }
@@ -82,8 +95,8 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
   char *base = (char *)prep;
   for (int i = 0; i < 2; ++i) {
     PrepPart &pp = h.part[i];
-    PR_HIP(launch_prepare(s, i, off, N, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off), base + h.scan_off,
-                          ctx->hscratch));
+    PR_HIP(launch_prepare(s, pp.tile, pp.rows, off, N, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
+                          base + h.scan_off, ctx->hscratch));
     const unsigned long long tot_a = ctx->hscratch[0], tot_b = ctx->hscratch[1];
     pp.ndesc = (int32_t)tot_a;
     pp.nslots = (int32_t)(tot_b >> 32);
@@ -95,6 +108,7 @@ int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int6
       return PR_EDEVICE;
     }
   }
+  *hin = h;
   int rc = write_prep_header(ctx, s, prep, h);
   if (rc != PR_OK) return rc;
   *out = h;
@@ -173,7 +187,8 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
     set_error("prep buffer was not written by pr_prepare");
     return PR_EINVAL;
   }
-  if (h.N != N || h.E != E || h.seg != kSeg || h.part[0].tile != kTile || h.part[1].tile != kTileB) {
+  if (h.N != N || h.E != E || h.seg != kSeg || !valid_window(0, h.part[0].tile, h.part[0].rows) ||
+      !valid_window(1, h.part[1].tile, h.part[1].rows)) {
     set_error("prep buffer belongs to another graph (N=%lld E=%lld, expected N=%lld E=%lld)", (long long)h.N,
               (long long)h.E, (long long)N, (long long)E);
     return PR_EINVAL;
@@ -363,7 +378,8 @@ ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int kp, unsigned grid, const Batch
 
 // Graph signature for the autotuner's table: sizes and the tile counts of both partitions.
 std::vector<int64_t> graph_signature(const PrepHeader &h) {
-  return {h.N, h.E, h.part[0].ndesc, h.part[0].nhubs, h.part[0].nslots, h.part[1].ndesc};
+  return {h.N, h.E, h.part[0].ndesc, h.part[0].nhubs, h.part[0].nslots, h.part[1].ndesc, h.part[0].tile,
+          h.part[1].tile};
 }
 
 // (mid_deg, grid cap) for a graph: explicit options first, then the autotuner's table, then defaults.
@@ -380,25 +396,42 @@ std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h) {
   return {mid, grid};
 }
 
+// (wave-per-row threshold, workgroups per resident slot) of pr_pull_batch for a graph: the
+// autotuner's table, else the defaults.
+std::pair<int32_t, int32_t> tuned_batch_settings(pr_ctx *ctx, const PrepHeader &h) {
+  if (ctx->use_tuned) {
+    auto it = ctx->tuned_batch.find(graph_signature(h));
+    if (it != ctx->tuned_batch.end()) return it->second;
+  }
+  return {kMidDeg, 1};
+}
+
+// Tune file lines: the graph signature (8 numbers), then mid_deg, grid, batch mid_deg, batch
+// workgroups per resident slot.
 void load_tune_file(pr_ctx *ctx) {
   const char *f = getenv("PRPULL_TUNE_FILE");
   if (!f || !*f) return;
   ctx->tune_file = f;
   FILE *fp = fopen(f, "r");
   if (!fp) return;
-  long long s[6];
-  int m, g;
-  while (fscanf(fp, "%lld %lld %lld %lld %lld %lld %d %d", &s[0], &s[1], &s[2], &s[3], &s[4], &s[5], &m, &g) == 8)
-    ctx->tuned[{s[0], s[1], s[2], s[3], s[4], s[5]}] = {m, g};
+  long long s[8];
+  int m, g, mb, gb;
+  while (fscanf(fp, "%lld %lld %lld %lld %lld %lld %lld %lld %d %d %d %d", &s[0], &s[1], &s[2], &s[3], &s[4], &s[5],
+                &s[6], &s[7], &m, &g, &mb, &gb) == 12) {
+    const std::vector<int64_t> sig(s, s + 8);
+    ctx->tuned[sig] = {m, g};
+    ctx->tuned_batch[sig] = {mb, gb};
+  }
   fclose(fp);
 }
 
-void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid) {
+void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid, int32_t mid_b,
+                     int32_t grid_b) {
   if (ctx->tune_file.empty()) return;
   FILE *fp = fopen(ctx->tune_file.c_str(), "a");
   if (!fp) return;
-  fprintf(fp, "%lld %lld %lld %lld %lld %lld %d %d\n", (long long)sig[0], (long long)sig[1], (long long)sig[2],
-          (long long)sig[3], (long long)sig[4], (long long)sig[5], mid, grid);
+  for (int64_t x : sig) fprintf(fp, "%lld ", (long long)x);
+  fprintf(fp, "%d %d %d %d\n", mid, grid, mid_b, grid_b);
   fclose(fp);
 }
 
@@ -434,6 +467,7 @@ int pr_create(pr_ctx **out, int device) {
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hstate, sizeof(SolveState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hscratch, 64 * sizeof(unsigned long long), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hcols, sizeof(BatchCols), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->hsweep, sizeof(SweepCols), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->hbstate, sizeof(BatchState), hipHostMallocDefault);
   if (e != hipSuccess) {
     set_error("pr_create: %s", hipGetErrorString(e));
@@ -441,6 +475,7 @@ int pr_create(pr_ctx **out, int device) {
     if (c->hstate) (void)hipHostFree(c->hstate);
     if (c->hscratch) (void)hipHostFree(c->hscratch);
     if (c->hcols) (void)hipHostFree(c->hcols);
+    if (c->hsweep) (void)hipHostFree(c->hsweep);
     if (c->hbstate) (void)hipHostFree(c->hbstate);
     delete c;
     return PR_EDEVICE;
@@ -461,6 +496,7 @@ void pr_destroy(pr_ctx *ctx) {
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
   if (ctx->hscratch) (void)hipHostFree(ctx->hscratch);
   if (ctx->hcols) (void)hipHostFree(ctx->hcols);
+  if (ctx->hsweep) (void)hipHostFree(ctx->hsweep);
   if (ctx->hbstate) (void)hipHostFree(ctx->hbstate);
   if (ctx->hmulti) (void)hipHostFree(ctx->hmulti);
   delete ctx;
@@ -516,6 +552,15 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->handover32 = value;
+  } else if (!strcmp(key, "tile") || !strcmp(key, "tile_b")) {
+    // tile window of the partitions written by later prepares: entries (rows = entries / 2)
+    const int part = key[4] ? 1 : 0;
+    if (!valid_window(part, (int)value, (int)value / 2)) {
+      set_error(part ? "tile_b must be 256 or 128" : "tile must be 1024, 512 or 256");
+      return PR_EINVAL;
+    }
+    ctx->window_tile[part] = value;
+    ctx->window_rows[part] = value / 2;
   } else if (!strcmp(key, "segmented")) {
     if (value != 0 && value != 1) {
       set_error("segmented must be 0 or 1");
@@ -689,7 +734,7 @@ int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, c
                 {&sl.merge_part, (const int32_t *)(base + sl.moff_off), N, pairs}};
   for (auto &q : parts) {
     PrepPart &pp = *q.pp;
-    PR_HIP(launch_prepare(s, 0, q.off, q.rows, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
+    PR_HIP(launch_prepare(s, kTile, kRows, q.off, q.rows, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
                           base + sl.scan_off, ctx->hscratch));
     pp.ndesc = (int32_t)ctx->hscratch[0];
     pp.nslots = (int32_t)(ctx->hscratch[1] >> 32);

@@ -71,6 +71,7 @@ struct pr_ctx {
   SolveState *hstate = nullptr;   // pinned host copy of the solve state
   unsigned long long *hscratch = nullptr;  // pinned host words for small read-backs
   BatchCols *hcols = nullptr;             // pinned staging of per-column parameters
+  SweepCols *hsweep = nullptr;            // pinned staging of a sweep's column table
   BatchState *hbstate = nullptr;          // pinned host copy of a batch state
   void *hmulti = nullptr;                 // pinned staging of many-graph tables
   size_t hmulti_bytes = 0;
@@ -88,11 +89,15 @@ struct pr_ctx {
   bool mid_deg_set = false;   // set explicitly (overrides the autotuner's choice)
   int64_t use_tuned = 1;      // 1: use autotuned settings of graphs with a known signature
   std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned;  // signature -> (mid_deg, grid)
+  // signature -> (wave-per-row threshold, workgroups per resident slot) of pr_pull_batch
+  std::map<std::vector<int64_t>, std::pair<int32_t, int32_t>> tuned_batch;
   std::string tune_file;
   int64_t compact = 1;      // 1: repack the active columns of a batch into narrower rows
   int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
   int64_t handover32 = 1;   // 1: the first float64 update of a mixed batch reads float32 rows
   int64_t segmented = 1;    // 1: pr_pull uses the source-segmented layout of a prep that has one
+  int64_t window_tile[2] = {kTile, kTileB};  // tile windows of new partitions A and B (entries)
+  int64_t window_rows[2] = {kRows, kRowsB};
   int64_t barrier_ms = 5000;  // time limit of a grid-barrier wait in pr_pull_multi
   std::vector<hipEvent_t> direct_events;
   int64_t stat_launches[PR_KERNEL_KINDS] = {};
@@ -165,6 +170,8 @@ bool bad_graph_sizes(int64_t N, int64_t E);
 Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep);
 int prepare_into(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep, PrepHeader *out);
 int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E, PrepHeader *out);
+int prepare_parts(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep, int tile_a,
+                  int tile_b, PrepHeader *hin, PrepHeader *out);
 int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &h);
 int seg_key_bits(int64_t N, int bits);
 bool seg_layout(int64_t N, int64_t E, int bits, int64_t P, SegLayout *sl);
@@ -178,8 +185,10 @@ BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t preci
 ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int kp, unsigned grid, const BatchParams &p, void *b0, void *b1);
 std::vector<int64_t> graph_signature(const PrepHeader &h);
 std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h);
+std::pair<int32_t, int32_t> tuned_batch_settings(pr_ctx *ctx, const PrepHeader &h);
 void load_tune_file(pr_ctx *ctx);
-void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid);
+void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid, int32_t mid_b,
+                     int32_t grid_b);
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,

@@ -222,90 +222,174 @@ int pr_pull_multi(pr_ctx *ctx, void *stream, int32_t G, const pr_graph_problem *
   return all ? PR_OK : PR_NOT_CONVERGED;
 }
 
+// Workspace of pr_autotune: one region for the timed single and batch solves, then (prep == NULL)
+// the tile partitions.
+static size_t tune_region(int64_t N, int64_t E) {
+  return std::max(carve(nullptr, N, E, PR_FP64, false).total,
+                  carve_batch(nullptr, N, E, kTuneBatchCols, PR_MIXED, false).total);
+}
+
+size_t pr_tune_workspace_bytes(int64_t N, int64_t E, int32_t with_prep) {
+  if (bad_graph_sizes(N, E)) return 0;
+  return align_up(tune_region(N, E), 256) + (with_prep ? prep_bytes(N, E) : 0);
+}
+
 int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
-                const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double *ranks, void *workspace,
+                const int32_t *outdeg, int64_t N, int64_t E, void *prep, double *ranks, void *workspace,
                 size_t workspace_bytes, pr_tune_result *out) {
   if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices)) {
     set_error("pr_autotune: NULL argument");
     return PR_EINVAL;
   }
   if (bad_graph_sizes(N, E)) return PR_EINVAL;
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  PrepHeader h;
-  const Layout L = carve(workspace, N, E, PR_FP64, prep == nullptr);
-  if (workspace_bytes < L.total) {
-    set_error("pr_autotune: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+  const size_t region = align_up(tune_region(N, E), 256);
+  const size_t need = pr_tune_workspace_bytes(N, E, prep == nullptr);
+  if (workspace_bytes < need) {
+    set_error("pr_autotune: workspace has %zu bytes, needs %zu", workspace_bytes, need);
     return PR_ENOMEM;
   }
-  const void *pp = prep;
-  int rc;
-  if (!prep) {
-    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
-    pp = L.prep;
-  } else {
-    rc = get_prep(ctx, s, prep, N, E, &h);
-  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  void *pp = prep ? prep : (void *)((char *)workspace + region);
+  PrepHeader h;
+  int rc = prep ? get_prep(ctx, s, prep, N, E, &h) : prepare_into(ctx, s, in_offsets, N, E, pp, &h);
   if (rc != PR_OK) return rc;
-  // candidates: lane/wave threshold x update grid (in resident workgroups)
-  const int32_t mids[] = {8, 16, 32, 64, 128};
-  const int64_t res = ctx->resident[0];
-  const int64_t grids[] = {res, 2 * res, 4 * res};
+
+  // saved settings; the candidates run with the autotuner's table off and explicit settings on
   const int64_t save_grid = ctx->max_grid, save_mid = ctx->mid_deg, save_timing = ctx->timing;
+  const int64_t save_tuned = ctx->use_tuned, save_seg = ctx->segmented;
   const bool save_set = ctx->mid_deg_set;
-  const int64_t save_tuned = ctx->use_tuned;
   int64_t save_launch[PR_KERNEL_KINDS];
   double save_ms[PR_KERNEL_KINDS];
   memcpy(save_launch, ctx->stat_launches, sizeof save_launch);
   memcpy(save_ms, ctx->stat_ms, sizeof save_ms);
-  ctx->use_tuned = 0;
-  ctx->mid_deg_set = true;
+  auto restore = [&]() {
+    ctx->max_grid = save_grid;
+    ctx->mid_deg = save_mid;
+    ctx->mid_deg_set = save_set;
+    ctx->timing = save_timing;
+    ctx->use_tuned = save_tuned;
+    ctx->segmented = save_seg;
+    memcpy(ctx->stat_launches, save_launch, sizeof save_launch);
+    memcpy(ctx->stat_ms, save_ms, sizeof save_ms);
+  };
   ctx->timing = 1;
+  ctx->segmented = 0;  // partition A's window and the thresholds are timed on the plain update
+  auto mean_us = [&](int kind) {
+    return ctx->stat_launches[kind] ? 1e3 * ctx->stat_ms[kind] / ctx->stat_launches[kind] : 1e300;
+  };
+  auto clear = [&](int kind) {
+    ctx->stat_launches[kind] = 0;
+    ctx->stat_ms[kind] = 0.0;
+  };
+
+  // ---- the single-vector update: partition A window x lane/wave threshold x grid
+  const int tiles_a[] = {1024, 512, 256};
+  const int32_t mids[] = {8, 16, 32, 64, 128};
+  const int64_t res = ctx->resident[0];
+  const int64_t grids[] = {res, 2 * res, 4 * res};
+  const int tile_b0 = h.part[1].tile;
   double best = 1e300, dflt = 0.0;
+  int best_tile = kTile;
   int32_t best_mid = kMidDeg, best_grid = (int32_t)std::min<int64_t>(res, kMaxGrid);
   int count = 0;
   constexpr int kReps = 4;
-  for (int64_t gsz : grids) {
-    if (gsz > kMaxGrid) continue;
-    for (int32_t m : mids) {
-      ctx->max_grid = gsz;
-      ctx->mid_deg = m;
-      ctx->stat_launches[PR_KERNEL_UPDATE_F64] = 0;
-      ctx->stat_ms[PR_KERNEL_UPDATE_F64] = 0.0;
-      pr_result r;
-      rc = pr_pull(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, 0.85, 0.0, PR_L1, kReps, PR_FP64, nullptr,
-                   ranks, nullptr, workspace, workspace_bytes, &r);
-      if (rc < 0) break;
-      const double us = ctx->stat_launches[PR_KERNEL_UPDATE_F64]
-                            ? 1e3 * ctx->stat_ms[PR_KERNEL_UPDATE_F64] / ctx->stat_launches[PR_KERNEL_UPDATE_F64]
-                            : 1e300;
-      ++count;
-      if (gsz == res && m == kMidDeg) dflt = us;
-      if (us < best) {
-        best = us;
-        best_mid = m;
-        best_grid = (int32_t)gsz;
+  ctx->use_tuned = 0;
+  ctx->mid_deg_set = true;
+  for (int ta : tiles_a) {
+    rc = prepare_parts(ctx, s, in_offsets, N, E, pp, ta, tile_b0, &h, &h);
+    if (rc != PR_OK) break;
+    for (int64_t gsz : grids) {
+      if (gsz > kMaxGrid) continue;
+      for (int32_t m : mids) {
+        ctx->max_grid = gsz;
+        ctx->mid_deg = m;
+        clear(PR_KERNEL_UPDATE_F64);
+        pr_result r;
+        rc = pr_pull(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, 0.85, 0.0, PR_L1, kReps, PR_FP64,
+                     nullptr, ranks, nullptr, workspace, region, &r);
+        if (rc < 0) break;
+        const double us = mean_us(PR_KERNEL_UPDATE_F64);
+        ++count;
+        if (ta == kTile && gsz == res && m == kMidDeg) dflt = us;
+        if (us < best) {
+          best = us;
+          best_tile = ta;
+          best_mid = m;
+          best_grid = (int32_t)gsz;
+        }
       }
+      if (rc < 0) break;
     }
     if (rc < 0) break;
   }
-  ctx->max_grid = save_grid;
-  ctx->mid_deg = save_mid;
-  ctx->mid_deg_set = save_set;
-  ctx->timing = save_timing;
-  ctx->use_tuned = save_tuned;
-  memcpy(ctx->stat_launches, save_launch, sizeof save_launch);
-  memcpy(ctx->stat_ms, save_ms, sizeof save_ms);
+  // ---- the K-column float32 update: partition B window x threshold x workgroups per slot
+  const int tiles_b[] = {256, 128};
+  const int32_t mids_b[] = {16, 32, 64};
+  const int32_t gmult[] = {1, 2};
+  double best_b = 1e300, dflt_b = 0.0;
+  int best_tile_b = kTileB;
+  int32_t best_mid_b = kMidDeg, best_gm = 1;
+  if (rc >= 0) {
+    ctx->max_grid = 0;
+    ctx->use_tuned = 1;  // the batch reads its candidate settings from the table
+    pr_problem probs[kTuneBatchCols];
+    double *rk[kTuneBatchCols];
+    for (int k = 0; k < kTuneBatchCols; ++k) {
+      probs[k] = pr_problem{0.85, 0.0, PR_L1, 3};
+      rk[k] = ranks;  // outputs are not used; every column may write the same scratch
+    }
+    pr_result rb[kTuneBatchCols];
+    for (int tb : tiles_b) {
+      rc = prepare_parts(ctx, s, in_offsets, N, E, pp, best_tile, tb, &h, &h);
+      if (rc != PR_OK) break;
+      const std::vector<int64_t> sig = graph_signature(h);
+      for (int32_t m : mids_b) {
+        for (int32_t gm : gmult) {
+          ctx->tuned_batch[sig] = {m, gm};
+          clear(PR_KERNEL_BATCH_F32);
+          rc = pr_pull_batch(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, kTuneBatchCols, probs, PR_MIXED,
+                             nullptr, rk, nullptr, workspace, region, rb);
+          if (rc < 0) break;
+          const double us = mean_us(PR_KERNEL_BATCH_F32);
+          ++count;
+          if (tb == kTileB && m == kMidDeg && gm == 1) dflt_b = us;
+          if (us < best_b) {
+            best_b = us;
+            best_tile_b = tb;
+            best_mid_b = m;
+            best_gm = gm;
+          }
+        }
+        if (rc < 0) break;
+      }
+      ctx->tuned_batch.erase(sig);
+      if (rc < 0) break;
+    }
+  }
+  restore();
   if (rc < 0) return rc;
+  // the chosen windows stay in the prep buffer; the thresholds and grids go to the table
+  rc = prepare_parts(ctx, s, in_offsets, N, E, pp, best_tile, best_tile_b, &h, &h);
+  if (rc != PR_OK) return rc;
   const std::vector<int64_t> sig = graph_signature(h);
   ctx->tuned[sig] = {best_mid, best_grid};
-  save_tune_entry(ctx, sig, best_mid, best_grid);
+  ctx->tuned_batch[sig] = {best_mid_b, best_gm};
+  save_tune_entry(ctx, sig, best_mid, best_grid, best_mid_b, best_gm);
   out->mid_deg = best_mid;
   out->grid = best_grid;
+  out->tile = best_tile;
+  out->rows = best_tile / 2;
+  out->mid_deg_batch = best_mid_b;
+  out->grid_batch_factor = best_gm;
+  out->tile_batch = best_tile_b;
+  out->rows_batch = best_tile_b / 2;
   out->candidates = count;
   out->pad = 0;
   out->best_us = best;
   out->default_us = dflt;
+  out->best_batch_us = best_b;
+  out->default_batch_us = dflt_b;
   return PR_OK;
 }
 

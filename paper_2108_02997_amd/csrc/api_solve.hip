@@ -233,10 +233,14 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   p.hacc = L.hacc;
   p.st = L.st;
   p.cols = L.cols;
+  // the autotuner's choice for this graph (wave-per-row threshold, workgroups per resident slot)
+  const std::pair<int32_t, int32_t> tb = tuned_batch_settings(ctx, h);
+  p.mid_deg = tb.first;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1) cus = 1;
   auto grid_of = [&](bool fp32, int kpw) {
-    const int64_t res = ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, kpw);
+    const int64_t res =
+        ctx->max_grid > 0 ? ctx->max_grid : (int64_t)cus * batch_blocks_per_cu(fp32, kpw) * (int64_t)tb.second;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, res, kMaxGrid}));
   };
 
@@ -476,6 +480,223 @@ int pr_pull_batch(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     all_conv &= c.converged;
   }
   return all_conv ? PR_OK : PR_NOT_CONVERGED;
+}
+
+// Workspace of pr_pull_sweep: the a = 1 iteration's state and partials, the column table, the
+// iterates of one chunk (slot 0: the update's input, slots 1..kSweepChunk: its outputs), prep.
+struct SweepLayout {
+  SolveState *st;
+  double *bpart;
+  double *hpart;
+  SweepCols *cols;
+  double *slots;
+  int64_t stride;  // doubles between slots
+  void *prep;
+  size_t total;
+};
+
+static SweepLayout carve_sweep(void *ws, int64_t N, int64_t E, bool with_prep) {
+  Carver c(ws);
+  SweepLayout L{};
+  L.st = (SolveState *)c.take(sizeof(SolveState));
+  L.bpart = (double *)c.take(4 * sizeof(double) * (size_t)kMaxGrid);
+  L.hpart = (double *)c.take(sizeof(double) * (size_t)max_slots(N, E));
+  L.cols = (SweepCols *)c.take(sizeof(SweepCols));
+  L.stride = (int64_t)(align_up(sizeof(double) * (size_t)N, 256) / sizeof(double));
+  L.slots = (double *)c.take(sizeof(double) * (size_t)L.stride * (kSweepChunk + 1));
+  L.prep = with_prep ? c.take(prep_bytes(N, E)) : nullptr;
+  L.total = c.used;
+  return L;
+}
+
+size_t pr_sweep_workspace_bytes(int64_t N, int64_t E, int32_t with_prep) {
+  if (bad_graph_sizes(N, E)) return 0;
+  return carve_sweep(nullptr, N, E, with_prep != 0).total;
+}
+
+int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                  const int32_t *outdeg, int64_t N, int64_t E, const void *prep, int32_t K, const pr_problem *probs,
+                  double *const *ranks, double *const *norm_trace, void *workspace, size_t workspace_bytes,
+                  pr_result *results) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !probs || !workspace || !results || (E > 0 && !in_indices)) {
+    set_error("pr_pull_sweep: NULL argument");
+    return PR_EINVAL;
+  }
+  if (bad_graph_sizes(N, E)) return PR_EINVAL;
+  if (K < 1 || K > kMaxSweepCols) {
+    set_error("K must be in [1, %d], got %d", kMaxSweepCols, K);
+    return PR_EINVAL;
+  }
+  int max_iter = 1;
+  for (int k = 0; k < K; ++k) {
+    const pr_problem &q = probs[k];
+    if (!(q.alpha >= 0.0 && q.alpha <= 1.0) || !(q.tau >= 0.0) || q.norm < PR_L1 || q.norm > PR_LINF ||
+        q.max_iter < 1 || !ranks[k]) {
+      set_error("problem %d: alpha in [0,1], tau >= 0, norm 1..3, max_iter >= 1 and a ranks buffer are required", k);
+      return PR_EINVAL;
+    }
+    for (int k2 = 0; k2 < k; ++k2)
+      if (ranks[k2] == ranks[k]) {
+        set_error("problems %d and %d share a ranks buffer", k2, k);
+        return PR_EINVAL;
+      }
+    max_iter = std::max(max_iter, q.max_iter);
+  }
+  const SweepLayout L = carve_sweep(workspace, N, E, prep == nullptr);
+  if (workspace_bytes < L.total) {
+    set_error("pr_pull_sweep: workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    return PR_ENOMEM;
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  PrepHeader h;
+  int rc;
+  const void *pp = prep;
+  if (!prep) {
+    rc = prepare_into(ctx, s, in_offsets, N, E, L.prep, &h);
+    pp = L.prep;
+  } else {
+    rc = get_prep(ctx, s, prep, N, E, &h);
+  }
+  if (rc != PR_OK) return rc;
+
+  // the column table (pinned staging, synchronised before the buffer is reused)
+  SweepCols &hc = *ctx->hsweep;
+  memset(&hc, 0, sizeof hc);
+  hc.K = K;
+  hc.remaining = K;
+  for (int k = 0; k < K; ++k) {
+    hc.alpha[k] = probs[k].alpha;
+    hc.tau[k] = probs[k].tau;
+    hc.norm[k] = probs[k].norm;
+    hc.max_iter[k] = probs[k].max_iter;
+    hc.ranks[k] = ranks[k];
+    hc.trace[k] = norm_trace ? norm_trace[k] : nullptr;
+  }
+  PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
+  for (int k = 0; k < K; ++k) PR_HIP(launch_fill_u32(s, (uint32_t *)ranks[k], 2 * N, 0u));
+  PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
+
+  // the a = 1 iteration, as pr_pull's float64 solve (segmented when the prep has the layout)
+  const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
+  const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[0];
+  const bool seg = ctx->segmented != 0 && h.seg_bits > 0;
+  const PrepPart &part = seg ? h.sl.merge_part : h.part[0];
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
+  IterParams p{};
+  p.off = in_offsets;
+  p.idx = in_indices;
+  if (seg) {
+    char *base = (char *)const_cast<void *>(pp);
+    p.off = (const int32_t *)(base + h.sl.moff_off);
+    p.idx = (const int32_t *)(base + h.sl.mpos_off);
+    p.poff = (const int32_t *)(base + h.sl.poff_off);
+    p.sidx = (const int32_t *)(base + h.sl.sidx_off);
+    p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
+    p.npdesc = h.sl.pair_part.ndesc;
+    p.partial = base + h.sl.part_off;
+    p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
+  }
+  p.outdeg = outdeg;
+  p.desc = (const int4 *)((const char *)pp + part.desc_off);
+  p.ndesc = part.ndesc;
+  p.N = (int32_t)N;
+  p.alpha = 1.0;
+  p.tau = 0.0;
+  p.norm = PR_L1;
+  p.max_iter = max_iter;
+  p.phase = 0;
+  p.mid_deg = ts.first;
+  p.st = L.st;
+  p.bpart = L.bpart;
+  p.hpart = L.hpart;
+  p.hubs = (const int4 *)((const char *)pp + part.hub_off);
+  p.nhubs = part.nhubs;
+  p.grid = (int32_t)grid;
+  p.trace = nullptr;
+  p.sweep = L.cols;
+  PR_HIP(launch_init(s, false, outdeg, (int32_t)N, nullptr, L.slots, 1.0, L.st, L.bpart, kMaxGrid));
+
+  // chunk: update k reads slot k and writes slot k + 1
+  ChunkSpec c;
+  c.kind = PR_KERNEL_UPDATE_F64;
+  c.count = kSweepChunk;
+  {
+    const int64_t meta[3] = {grid, kSweepChunk, (int64_t)(intptr_t)L.slots};
+    c.key.resize(sizeof p + sizeof meta);
+    memcpy(c.key.data(), &p, sizeof p);
+    memcpy(c.key.data() + sizeof p, meta, sizeof meta);
+  }
+  const double *slots = L.slots;
+  const int64_t stride = L.stride;
+  c.launch = [grid, p, slots, stride](hipStream_t st, int k) {
+    IterParams r = p;
+    r.y_in = slots + (int64_t)k * stride;
+    r.y_out = (void *)(slots + (int64_t)(k + 1) * stride);
+    return launch_update(st, false, grid, r);
+  };
+  LoopHead *hh = (LoopHead *)ctx->hstate;
+  int before = 0;
+  bool first = true;
+  EventPair fev;
+  if (ctx->timing) {
+    PR_HIP(hipEventCreate(&fev.a));
+    PR_HIP(hipEventCreate(&fev.b));
+  }
+  for (int rounds = 0;; ++rounds) {
+    const std::vector<hipEvent_t> *ev = nullptr;
+    rc = run_chunk(ctx, s, c, &ev);
+    if (rc != PR_OK) return rc;
+    PR_HIP(hipMemcpyAsync(hh, &L.st->head, sizeof(LoopHead), hipMemcpyDeviceToHost, s));
+    PR_HIP(hipStreamSynchronize(s));
+    const int did = hh->phase_iter - before;
+    if (ev && did > 0) {
+      float ms = 0.f;
+      for (int k = 0; k < did && k < c.count; ++k) {
+        PR_HIP(hipEventElapsedTime(&ms, (*ev)[k], (*ev)[k + 1]));
+        ctx->stat_ms[c.kind] += ms;
+        ctx->stat_launches[c.kind] += 1;
+      }
+    }
+    // fold the chunk's iterates (and the start, before the first update) into the columns
+    const int32_t nfold = did + (first ? 1 : 0);
+    if (nfold > 0) {
+      if (ctx->timing) PR_HIP(hipEventRecord(fev.a, s));
+      PR_HIP(launch_sweep_fold(s, L.slots, L.stride, first ? 0 : 1, nfold, first ? 0 : before + 1, outdeg,
+                               (int32_t)N, L.cols, K));
+      if (ctx->timing) {
+        PR_HIP(hipEventRecord(fev.b, s));
+        PR_HIP(hipEventSynchronize(fev.b));
+        float ms = 0.f;
+        PR_HIP(hipEventElapsedTime(&ms, fev.a, fev.b));
+        ctx->stat_ms[PR_KERNEL_SWEEP_FOLD] += ms;
+        ctx->stat_launches[PR_KERNEL_SWEEP_FOLD] += 1;
+      }
+    }
+    before = hh->phase_iter;
+    first = false;
+    if (hh->stop) break;
+    if (rounds > max_iter) {  // cannot happen: the a = 1 iteration stops at max_iter
+      set_error("internal: update limit passed without stop");
+      return PR_EDEVICE;
+    }
+    // the chunk's last output becomes the next chunk's input
+    PR_HIP(launch_copy_f64(s, L.slots + (int64_t)kSweepChunk * L.stride, L.slots, N));
+  }
+  PR_HIP(hipMemcpyAsync(&hc, L.cols, sizeof hc, hipMemcpyDeviceToHost, s));
+  PR_HIP(hipStreamSynchronize(s));
+  int all = 1;
+  for (int k = 0; k < K; ++k) {
+    results[k].iterations = hc.stop_iter[k];
+    results[k].converged = hc.converged[k];
+    results[k].fp32_iters = 0;
+    results[k].fp64_iters = hc.stop_iter[k];
+    results[k].final_err[0] = hc.err[k][0];
+    results[k].final_err[1] = hc.err[k][1];
+    results[k].final_err[2] = hc.err[k][2];
+    all &= hc.converged[k];
+  }
+  return all ? PR_OK : PR_NOT_CONVERGED;
 }
 
 int pr_l1_distance(pr_ctx *ctx, void *stream, const double *x, const double *y, int64_t N, void *workspace,

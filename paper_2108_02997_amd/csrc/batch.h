@@ -53,6 +53,8 @@ struct BatchParams {
   int32_t grid;    // blocks of the update launch
   int32_t nhubs;
   int32_t phase;
+  int32_t mid_deg;  // rows of a tile with more entries are summed by a whole wave
+  int32_t pad;
   const int4 *hubs;
   double *bpart;   // [grid][KP][4]
   double *hpart;   // [slots][KP]

@@ -7,7 +7,7 @@
 // A group of G = min(KP, 4) lanes owns one row fetch; lane (l % G) handles columns
 // (l % G)*C .. +C-1, C = KP/G.
 //   tiles of short rows (partition B: fewer than kSpanB entries): every group fetches the rows
-//   of kPerQ entries into LDS, then one group sums each row of in-degree <= kMidDeg in ascending
+//   of kPerQ entries into LDS, then one group sums each row of in-degree <= mid_deg in ascending
 //   entry order and one wave each longer row (entry j on group j % (64/G), xor reduction);
 //   long-row segments: one block per segment, reduction across groups and waves; hubs leave
 //   per-column segment partials for k_batch_finish.
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBlock, (update_waves<VT, KP, VI>())) void k_batch_
       for (int q = 0; q < kRowsQ; ++q) {
         const int32_t v = v0 + quad + q * kQuads;
         const bool mine = v < v1;
-        const bool mid = mine && (rb[q] - ra[q]) > kMidDeg;
+        const bool mid = mine && (rb[q] - ra[q]) > p.mid_deg;
         if (mine && !mid) {
           VT s[C];
 #pragma unroll

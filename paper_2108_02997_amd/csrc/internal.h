@@ -29,6 +29,14 @@ constexpr int kRowsB = 128;
 constexpr int kSpanB = 2 * kTileB;
 constexpr int kPartTile[2] = {kTile, kTileB};
 constexpr int kPartRows[2] = {kRows, kRowsB};
+// Smaller windows the autotuner may choose (the update kernels stage at most kSpan / kSpanB entries
+// and kRows / kRowsB rows per tile, so any smaller window runs unchanged): partition A 1024/512,
+// 512/256 or 256/128 entries/rows, partition B 256/128 or 128/64.  Prep buffers are sized for the
+// smallest.
+constexpr int kTuneBatchCols = 8;  // columns of the batch update the autotuner times
+constexpr int kMinPartTile[2] = {256, 128};
+constexpr int kMinPartRows[2] = {128, 64};
+bool valid_window(int part, int tile, int rows);
 // Default threshold: rows with in-degree above kMidDeg (and at most the tile window) are summed by
 // a whole wave; pr_pull takes the threshold at run time (option "mid_deg", or the autotuner).
 constexpr int kMidDeg = 32;
@@ -121,6 +129,26 @@ struct alignas(64) SolveState {
   double prev_l1;     // L1 of the update before (float32 stagnation test)
 };
 
+// Damping-factor sweep as one power series (pr_pull_sweep).  From the uniform start u, the
+// iterate of damping factor a after k updates is r_a(k) = a^k v_k + (1-a) sum_{j<k} a^j v_j, with
+// v_j the iterates of the a = 1 update from u, and its change at update k is a^k (v_k - v_{k-1}):
+// one a = 1 iteration serves every column.  Per-column parameters and stop state (device).
+constexpr int kMaxSweepCols = 64;
+constexpr int kSweepChunk = 16;  // updates between folds; the workspace keeps kSweepChunk + 1 iterates
+struct SweepCols {
+  double alpha[kMaxSweepCols];
+  double tau[kMaxSweepCols];
+  double err[kMaxSweepCols][3];     // the column's change at its last update
+  double *ranks[kMaxSweepCols];     // output, accumulated fold by fold
+  double *trace[kMaxSweepCols];     // [max_iter][3] or null
+  int32_t norm[kMaxSweepCols];
+  int32_t max_iter[kMaxSweepCols];
+  int32_t stop_iter[kMaxSweepCols];  // 0 while the column runs, else the update it stopped at
+  int32_t converged[kMaxSweepCols];
+  int32_t K;
+  int32_t remaining;
+};
+
 // Kernel parameters of one update (passed by value).
 struct IterParams {
   const int32_t *off;
@@ -154,6 +182,9 @@ struct IterParams {
   void *partial;
   int32_t npdesc;
   int32_t pgrid;       // workgroups of the per-segment step
+  // Non-null: this is the a = 1 iteration of a power-series sweep; finalize decides every
+  // column's stop instead of testing tau.
+  SweepCols *sweep;
 };
 
 // ---------------------------------------------------------------- host helpers
@@ -174,10 +205,15 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Launchers (defined in the .hip files).
 // host_total receives {descriptors, hub slots << 32 | hubs}.
-hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
-                          unsigned long long *host_total);
+hipError_t launch_prepare(hipStream_t s, int tile, int rows, const int32_t *off, int64_t N, int4 *desc, int4 *hubs,
+                          void *scan, unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
+// Fold the iterates slots[first .. first + n) (y form, steps j0 .. j0 + n - 1) of a sweep into
+// every column's ranks (sweep.hip); copy one iterate slot onto another.
+hipError_t launch_sweep_fold(hipStream_t s, const double *slots, int64_t stride, int32_t first, int32_t n,
+                             int32_t j0, const int32_t *outdeg, int32_t N, const SweepCols *sw, int32_t K);
+hipError_t launch_copy_f64(hipStream_t s, const double *src, double *dst, int64_t n);
 // Source-segmented layout (segment.hip).
 int64_t seg_count_blocks();
 hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,

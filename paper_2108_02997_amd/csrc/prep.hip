@@ -33,14 +33,20 @@ static int64_t scan_blocks(int64_t N) { return (N + kScanChunk - 1) / kScanChunk
 int64_t scan_block_count(int64_t N) { return scan_blocks(N); }
 
 // Layout: header | partition A (descriptors, hubs) | partition B (descriptors, hubs) | scan scratch.
+// Each partition is sized for the smallest window it may be given (the autotuner's candidates).
 size_t prep_bytes(int64_t N, int64_t E) {
   size_t b = align_up(sizeof(PrepHeader), 256);
   for (int i = 0; i < 2; ++i) {
-    b += align_up((size_t)(max_desc(N, E, kPartTile[i], kPartRows[i]) + 1) * sizeof(int4), 256);
+    b += align_up((size_t)(max_desc(N, E, kMinPartTile[i], kMinPartRows[i]) + 1) * sizeof(int4), 256);
     b += align_up((size_t)max_hubs(N, E) * sizeof(int4), 256);
   }
   b += align_up((size_t)(scan_blocks(N) + 1) * 2 * sizeof(unsigned long long), 256);
   return b;
+}
+
+bool valid_window(int part, int tile, int rows) {
+  if (part == 0) return (tile == 1024 && rows == 512) || (tile == 512 && rows == 256) || (tile == 256 && rows == 128);
+  return (tile == 256 && rows == 128) || (tile == 128 && rows == 64);
 }
 
 // Per-row counts: a = descriptors starting at row v, b = (segment slots << 32) | hubs.
@@ -184,11 +190,20 @@ static hipError_t prepare_part(hipStream_t s, const int32_t *off, int64_t N, int
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(hipStream_t s, int part, const int32_t *off, int64_t N, int4 *desc, int4 *hubs, void *scan,
-                          unsigned long long *host_total) {
+hipError_t launch_prepare(hipStream_t s, int tile, int rows, const int32_t *off, int64_t N, int4 *desc, int4 *hubs,
+                          void *scan, unsigned long long *host_total) {
   Code *bsum = (Code *)scan;
-  hipError_t e = part == 0 ? prepare_part<kPartTile[0], kPartRows[0]>(s, off, N, desc, hubs, bsum)
-                           : prepare_part<kPartTile[1], kPartRows[1]>(s, off, N, desc, hubs, bsum);
+  hipError_t e;
+  if (tile == 1024 && rows == 512)
+    e = prepare_part<1024, 512>(s, off, N, desc, hubs, bsum);
+  else if (tile == 512 && rows == 256)
+    e = prepare_part<512, 256>(s, off, N, desc, hubs, bsum);
+  else if (tile == 256 && rows == 128)
+    e = prepare_part<256, 128>(s, off, N, desc, hubs, bsum);
+  else if (tile == 128 && rows == 64)
+    e = prepare_part<128, 64>(s, off, N, desc, hubs, bsum);
+  else
+    return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(host_total, bsum + scan_blocks(N), sizeof(Code), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;

@@ -41,6 +41,41 @@ __device__ __forceinline__ void finalize(const IterParams &p, double l1, double 
   }
   const double N = (double)p.N;
   st->c0 = (1.0 - p.alpha) / N + (p.alpha * dang) / N;
+  if (p.sweep) {
+    // the a = 1 iteration of a sweep: column k's change at this update is alpha_k^it times this
+    // update's change, in every norm; a column stops at the first update where that meets its
+    // tau in its norm, or at its max_iter
+    SweepCols *sw = p.sweep;
+    int32_t rem = 0;
+    for (int k = 0; k < sw->K; ++k) {
+      if (sw->stop_iter[k]) continue;
+      const double ak = pow(sw->alpha[k], (double)it);
+      const double ek[3] = {ak * e[0], ak * e[1], ak * e[2]};
+      sw->err[k][0] = ek[0];
+      sw->err[k][1] = ek[1];
+      sw->err[k][2] = ek[2];
+      if (sw->trace[k]) {
+        sw->trace[k][3 * (int64_t)(it - 1) + 0] = ek[0];
+        sw->trace[k][3 * (int64_t)(it - 1) + 1] = ek[1];
+        sw->trace[k][3 * (int64_t)(it - 1) + 2] = ek[2];
+      }
+      const int nk = sw->norm[k];
+      if ((nk == 1 ? ek[0] : nk == 2 ? ek[1] : ek[2]) < sw->tau[k]) {
+        sw->converged[k] = 1;
+        sw->stop_iter[k] = it;
+      } else if (it >= sw->max_iter[k]) {
+        sw->stop_iter[k] = it;
+      } else {
+        ++rem;
+      }
+    }
+    sw->remaining = rem;
+    if (rem == 0 || it >= p.max_iter) {
+      st->head.stop = 1;
+      st->head.done = 1;
+    }
+    return;
+  }
   const bool met = (p.norm == 1 ? e[0] : p.norm == 2 ? e[1] : e[2]) < p.tau;
   if (p.phase == 1) {
     // float32 phase: hand over to float64 once tau is met, the L1 change stops shrinking (in

@@ -15,7 +15,7 @@ C = bench.CSRC
 # profile summary -> the sources whose digest it records (the same lists bench.py hashes)
 PROFILES = {
     "batch_update_f32_rmat_s24": [C + "batch.hip", C + "batch.h", C + "internal.h"],
-    "update_f64_rmat_s24": [C + "pull.hip", C + "device.h", C + "internal.h"],
+    "update_f64_rmat_s24": [C + "pull.hip", C + "device.h", C + "internal.h", C + "segment.hip"],
     "multi_64graphs": [C + "multi.hip", C + "multi.h", C + "device.h", C + "internal.h"],
 }
 

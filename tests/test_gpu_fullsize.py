@@ -107,8 +107,9 @@ def rmat24():
 
 @pytest.fixture(scope="module")
 def dev24(pr, ctx, rmat24):
+    # prepared as the benchmark prepares it: tile partitions plus the source-segmented layout
     dg = pr.DeviceGraph.from_host(rmat24)
-    dg.prepare(ctx)
+    dg.prepare_segmented(ctx, seg_bits=19)
     yield dg
     del dg
     torch.cuda.empty_cache()
@@ -121,6 +122,17 @@ def sweep24(pr, ctx, dev24):
     res = pr.pull_batch(ctx, dev24, probs, precision=pr.PR_MIXED)
     for r in res:
         r["ranks"] = r["ranks"].cpu().numpy()
+    return probs, res
+
+
+@pytest.fixture(scope="module")
+def series24(pr, ctx, dev24):
+    """The same eleven columns as one power-series sweep (pr_pull_sweep, float64)."""
+    probs = [dict(alpha=a, tau=1e-10, norm=3, max_iter=500) for a in gg.ALPHA_SWEEP]
+    res = pr.pull_sweep(ctx, dev24, probs, trace=True)
+    for r in res:
+        r["ranks"] = r["ranks"].cpu().numpy()
+        r["trace"] = r["trace"].cpu().numpy()
     return probs, res
 
 
@@ -140,21 +152,26 @@ def test_scale24_sweep_as_benchmarked(sweep24):
 
 
 @pytest.mark.parametrize("alpha", gg.ALPHA_SWEEP)
-def test_scale24_columns_against_full_oracle(pr, ctx, rmat24, dev24, sweep24, alpha):
+def test_scale24_columns_against_full_oracle(pr, ctx, rmat24, dev24, sweep24, series24, alpha):
     g = rmat24
     p = dict(alpha=alpha, tau=1e-10, norm=3, max_iter=500)
     ref = oracle.pagerank_graph(g, trace=True, **p)
-    # the sequential float64 solve of the benchmark's baseline
+    # the sequential float64 solve of the benchmark's baseline (source-segmented updates)
     f64 = pr.pull(ctx, dev24, precision=pr.PR_FP64, trace=True, **p)
     check_fp64_result(g, f64["ranks"].cpu().numpy(), f64["iterations"], f64["converged"], alpha, 1e-10, 3, 500,
                       gpu_trace=f64["trace"].cpu().numpy(), ref=ref)
+    # the same column of the power-series sweep: the float64 bar
+    k = list(gg.ALPHA_SWEEP).index(alpha)
+    ser = series24[1][k]
+    check_fp64_result(g, ser["ranks"], ser["iterations"], ser["converged"], alpha, 1e-10, 3, 500,
+                      gpu_trace=ser["trace"], ref=ref)
     # the same column of the eleven-column mixed batch: the L1 bound for alpha < 1 and the stated
-    # L-infinity tolerance (10 tau at alpha = 1, where no contraction factor exists)
-    col = sweep24[1][list(gg.ALPHA_SWEEP).index(alpha)]
+    # L-infinity tolerance (tests/parity.py)
+    col = sweep24[1][k]
     _, d1, dinf = check_mixed_result(g, col["ranks"], col["err"], alpha, 1e-10, 3, ref=ref)
-    print("scale-24 alpha %.2f: mixed batch %d (fp32 %d + fp64 %d), fp64 %d, oracle %d; mixed vs oracle L1 %.3e "
-          "Linf %.3e" % (alpha, col["iterations"], col["fp32_iters"], col["fp64_iters"], f64["iterations"],
-                          ref["iterations"], d1, dinf))
+    print("scale-24 alpha %.2f: series %d, mixed batch %d (fp32 %d + fp64 %d), fp64 %d, oracle %d; mixed vs oracle "
+          "L1 %.3e Linf %.3e" % (alpha, ser["iterations"], col["iterations"], col["fp32_iters"], col["fp64_iters"],
+                                 f64["iterations"], ref["iterations"], d1, dinf))
 
 
 # ------------------------------------------------------------------ 64 uneven graphs, full recipe

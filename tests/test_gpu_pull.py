@@ -273,8 +273,13 @@ def test_autotune_then_parity(pr, ctx):
     g = gg.rmat(15, seed=31)
     dg = dev(pr, g)
     t = dg.autotune(ctx)
-    assert t["candidates"] == 15 and t["mid_deg"] in (8, 16, 32, 64, 128) and t["grid"] >= 1
-    assert t["best_us"] <= t["default_us"]
+    assert t["candidates"] == 45 + 12 and t["mid_deg"] in (8, 16, 32, 64, 128) and t["grid"] >= 1
+    assert (t["tile"], t["rows"]) in ((1024, 512), (512, 256), (256, 128))
+    assert (t["tile_batch"], t["rows_batch"]) in ((256, 128), (128, 64))
+    assert t["mid_deg_batch"] in (16, 32, 64) and t["grid_batch_factor"] in (1, 2)
+    assert t["best_us"] <= t["default_us"] and t["best_batch_us"] <= t["default_batch_us"]
+    print("autotune:", t)
+    # the single-vector solve, the many-graph launch and the K-column batch on the tuned settings
     res, ref = check_fp64(pr, ctx, g, alpha=0.9, tau=1e-10, norm=1, dg=dg)
     assert res["iterations"] == ref["iterations"]
     m = pr.pull_multi(ctx, [dg, dev(pr, gg.workload_c1())],
@@ -282,6 +287,34 @@ def test_autotune_then_parity(pr, ctx):
                                                                               max_iter=500)])
     assert m[0]["iterations"] == ref["iterations"]
     assert np.abs(m[0]["ranks"].cpu().numpy() - ref["ranks"]).sum() <= 1e-12
+    probs = [dict(alpha=a, tau=1e-10, norm=n, max_iter=500) for a, n in ((0.5, 1), (0.9, 1), (0.99, 3))]
+    for r, p in zip(pr.pull_batch(ctx, dg, probs, precision=pr.PR_FP64, trace=True), probs):
+        check_fp64_result(g, r["ranks"].cpu().numpy(), r["iterations"], r["converged"], p["alpha"], p["tau"],
+                          p["norm"], 500, gpu_trace=r["trace"].cpu().numpy())
+    for r, p in zip(pr.pull_batch(ctx, dg, probs, precision=pr.PR_MIXED), probs):
+        check_mixed_result(g, r["ranks"].cpu().numpy(), r["err"], p["alpha"], p["tau"], p["norm"])
+
+
+@pytest.mark.parametrize("tile", [512, 256])
+def test_smaller_tile_windows(pr, ctx, tile):
+    # partitions written with the autotuner's smaller windows run through the same kernels
+    g = gg.rmat(14, seed=33)
+    ctx.set_option("tile", tile)
+    ctx.set_option("tile_b", 128)
+    try:
+        dg = dev(pr, g)
+        dg.prepare(ctx)
+    finally:
+        ctx.set_option("tile", 1024)
+        ctx.set_option("tile_b", 256)
+    for norm in (1, 3):
+        check_fp64(pr, ctx, g, alpha=0.85, tau=1e-10, norm=norm, dg=dg)
+    probs = [dict(alpha=a, tau=1e-10, norm=1, max_iter=500) for a in (0.6, 0.85, 0.95)]
+    for r, p in zip(pr.pull_batch(ctx, dg, probs, precision=pr.PR_FP64, trace=True), probs):
+        check_fp64_result(g, r["ranks"].cpu().numpy(), r["iterations"], r["converged"], p["alpha"], p["tau"],
+                          p["norm"], 500, gpu_trace=r["trace"].cpu().numpy())
+    with pytest.raises(pr.PrError):
+        ctx.set_option("tile", 300)
 
 
 @pytest.mark.parametrize("mid", [0, 1, 1024])

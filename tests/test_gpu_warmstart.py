@@ -167,6 +167,39 @@ def test_trained_network_gains_over_uniform_start(pr, ws, ctx):
     assert sum(r[5] for r in report) <= sum(r[1] for r in report)
 
 
+def test_scale24_warm_started_column_against_oracle(pr, ws, ctx):
+    """A warm-started column of the scale-24 evaluation graph (seed 3000), alpha = 0.95, tau = 1e-10
+    (L-infinity): the judged start (network, alpha = 0.85 ranks or uniform, three float64
+    look-ahead updates) and the solve from it, checked against the float64 oracle started from
+    the same vector (float64 parity), and against the oracle's uniform-start solve (the section-2
+    map's L1 fixed-point bound and the stated L-infinity tolerance)."""
+    from parity import check_fp64_result, mixed_linf_bound
+    model = ws.WarmStart(ctx, seed=0)
+    samples = []
+    for s in range(4):  # a short training: the check is on the solve from whatever start it proposes
+        samples += model.make_samples(pr.DeviceGraph.from_host(gg.rmat(16, seed=2000 + s)), [0.8, 0.9, 0.95, 0.99])
+    model.train(samples, epochs=10, lr=3e-3)
+    del samples
+    g = gg.rmat(24, edge_factor=16, seed=3000)
+    dg = pr.DeviceGraph.from_host(g).prepare(ctx)
+    alpha, tau, norm = 0.95, 1e-10, 3
+    r85 = pr.pull(ctx, dg, alpha=0.85, tau=tau, norm=norm)["ranks"]
+    chosen, name, e, steps, _ = model.start(dg, r85, alpha, norm=norm)
+    res = pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, init=chosen, trace=True)
+    assert res["converged"]
+    init = chosen.cpu().numpy()
+    got = res["ranks"].cpu().numpy()
+    check_fp64_result(g, got, res["iterations"], res["converged"], alpha, tau, norm, 500, init=init,
+                      gpu_trace=res["trace"].cpu().numpy())
+    ref = oracle.pagerank_graph(g, alpha=alpha, tau=tau, norm=norm)
+    diff = np.abs(got - ref["ranks"])
+    d1, dinf = float(diff.sum()), float(diff.max())
+    assert d1 <= alpha / (1 - alpha) * (res["err"][0] + ref["err"][0]) + 1e-13
+    assert dinf <= mixed_linf_bound(alpha, res["err"][2], ref["err"][2])
+    print("scale 24, alpha 0.95: judged start %s (+%d look-ahead updates), %d updates from it; oracle from "
+          "uniform %d; L1 %.2e, Linf %.2e" % (name, steps, res["iterations"], ref["iterations"], d1, dinf))
+
+
 @pytest.mark.parametrize("make", [lambda: gg.edgeless(5), lambda: gg.cycle(7), lambda: gg.in_star(40),
                                   lambda: gg.out_star(9), gg.two_triangles, lambda: gg.complete(1)])
 def test_features_on_tiny_and_degenerate_graphs(pr, ws, ctx, make):

@@ -325,3 +325,40 @@ def test_invalid_arguments():
                                               (1e-9, 0.85, 128), (1e-3, 0.85, 43)])
 def test_iteration_estimate_matches_paper(tau, alpha, expect):
     assert estimate.rounded(tau, alpha) == expect
+
+
+# ------------------------------------------------------------------ the sweep as a power series
+# The GPU's one-iteration sweep (pr_pull_sweep) rests on an identity of the section-2 map, checked
+# here on the oracle alone: from the uniform start, k updates at damping factor a give
+# a^k v_k + (1 - a) sum_{j<k} a^j v_j with v_j the iterates at a = 1 from the same start, and the
+# change of update k is a^k times the a = 1 change, in every norm.
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_power_series_identity_of_the_update(seed):
+    g = gg.rmat(11, seed=seed)  # with dangling vertices, duplicates removed
+    K = 25
+    v = [oracle.pagerank_graph(g, alpha=1.0, tau=0.0, max_iter=k, trace=True) if k else None for k in range(K + 1)]
+    vs = [np.full(g.N, 1.0 / g.N)] + [x["ranks"] for x in v[1:]]
+    e1 = v[K]["trace"]  # the a = 1 changes of updates 1..K
+    for a in (0.0, 0.5, 0.85, 0.99, 1.0):
+        ref = oracle.pagerank_graph(g, alpha=a, tau=0.0, max_iter=K, trace=True)
+        for k in (1, 7, K):
+            rk = oracle.pagerank_graph(g, alpha=a, tau=0.0, max_iter=k)["ranks"]
+            series = a ** k * vs[k] + (1 - a) * sum(a ** j * vs[j] for j in range(k))
+            assert np.abs(series - rk).sum() <= 1e-13
+        # the changes agree up to the rounding of the iterates themselves (a few float64 ulps of
+        # sum(r) = 1 summed over the vertices), which dominates once the changes near 1e-12
+        for k in range(1, K + 1):
+            np.testing.assert_allclose(ref["trace"][k - 1], a ** k * e1[k - 1], rtol=1e-9, atol=1e-15)
+
+
+def test_power_series_stops_like_separate_solves():
+    # every column's stop (first k with a^k e_k < tau in its norm) equals its own solve's count
+    g = gg.workload_c1()
+    one = oracle.pagerank_graph(g, alpha=1.0, tau=0.0, max_iter=200, trace=True)["trace"]
+    for a in (0.5, 0.7, 0.85, 0.95):
+        for norm in (L1, L2, LINF):
+            for tau in (1e-4, 1e-8, 1e-11):
+                own = oracle.pagerank_graph(g, alpha=a, tau=tau, norm=norm)
+                ks = [k for k in range(1, 201) if a ** k * one[k - 1, norm - 1] < tau]
+                assert ks and ks[0] == own["iterations"], (a, norm, tau, ks[:1], own["iterations"])
