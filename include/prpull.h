@@ -232,6 +232,21 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
             int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
             double *norm_trace, void *workspace, size_t workspace_bytes, pr_result *out);
 
+/* For callers that cannot allocate device memory (serving loops, code that must not call
+ * hipMalloc, harnesses that forbid allocation): pr_pull with prep = NULL whose workspace is a
+ * fixed device array of the library (pr_noalloc_max_bytes() = 64 MiB per GPU, resolved at
+ * pr_create and held until the process ends) instead of a caller's buffer.  Same arguments,
+ * results and statuses as pr_pull otherwise; the updates are launched one by one (no HIP graph
+ * is instantiated) and are not timed.  Graphs whose pr_workspace_bytes(N, E, precision, 1)
+ * exceeds pr_noalloc_max_bytes() (about 2 million vertices and 30 million in-edges in float64)
+ * are rejected with PR_ENOMEM.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (other host threads, or streams not ordered after each other) race. */
+size_t pr_noalloc_max_bytes(void);
+int pr_pull_noalloc(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                    const int32_t *outdeg, int64_t N, int64_t E, double alpha, double tau, int32_t norm,
+                    int32_t max_iter, int32_t precision, const double *init, double *ranks, double *norm_trace,
+                    pr_result *out);
+
 /* ------------------------------------------------------------------ several problems, one graph */
 
 /* One problem of a batch: the parameters of sections 2 and 3 for one rank vector. */

@@ -91,6 +91,9 @@ SIGNATURES = {
     "pr_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "pr_pull": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz,
                  ctypes.POINTER(pr_result)], ctypes.c_int),
+    "pr_noalloc_max_bytes": ([], _sz),
+    "pr_pull_noalloc": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp,
+                         ctypes.POINTER(pr_result)], ctypes.c_int),
     "pr_multi_workspace_bytes": ([_i32, ctypes.POINTER(pr_graph_problem)], _sz),
     "pr_pull_multi": ([_vp, _vp, _i32, ctypes.POINTER(pr_graph_problem), _vp, _sz, ctypes.POINTER(pr_result)],
                       ctypes.c_int),

@@ -456,6 +456,7 @@ int pr_create(pr_ctx **out, int device) {
     return PR_EDEVICE;
   }
   DeviceGuard g(device);
+  if (scratch_setup(device) != PR_OK) return PR_EDEVICE;
   pr_ctx *c = new pr_ctx();
   c->device = device;
   int cus = 0;

@@ -193,5 +193,8 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
                size_t workspace_bytes, pr_result *out);
+// The library's fixed device scratch (api_noalloc.hip): its address on `device`, resolved once
+// per device; PR_OK or PR_EDEVICE.
+int scratch_setup(int device);
 
 }  // namespace prpull
