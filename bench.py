@@ -734,11 +734,15 @@ def run_multi(args, pr, gg, np, torch):
     ws = torch.empty(ctx.lib.pr_multi_workspace_bytes(len(graphs), pr.multi_problems(ctx, graphs, probs)[0]),
                      dtype=torch.uint8, device="cuda")
 
+    # outputs allocated once, as a caller reusing its buffers would
+    ranks_m = [torch.empty(h.N, dtype=torch.float64, device="cuda") for h in hosts]
+    ranks_q = [torch.empty(h.N, dtype=torch.float64, device="cuda") for h in hosts]
+
     def one_launch():
-        return pr.pull_multi(ctx, graphs, probs, workspace=ws)
+        return pr.pull_multi(ctx, graphs, probs, workspace=ws, ranks=ranks_m)
 
     def sequential():
-        return [pr.pull(ctx, dg, **p) for dg, p in zip(graphs, probs)]
+        return [pr.pull(ctx, dg, ranks=r, **p) for dg, p, r in zip(graphs, probs, ranks_q)]
 
     sequential()
     seq_ts, seq_res = timed(sequential, max(1, args.seq_reps), "64 sequential solves")

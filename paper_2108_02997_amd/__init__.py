@@ -329,17 +329,22 @@ def pull_sweep(ctx: Context, g: DeviceGraph, problems, trace: bool = False, rank
     return out
 
 
-def multi_problems(ctx: Context, graphs, problems, inits=None, trace: bool = False):
-    """The pr_graph_problem array of a many-graph call, with fresh rank (and trace) tensors."""
+def multi_problems(ctx: Context, graphs, problems, inits=None, trace: bool = False, ranks=None):
+    """The pr_graph_problem array of a many-graph call, with the given (or fresh) rank tensors and
+    fresh trace tensors."""
     G = len(graphs)
     if G != len(problems) or G < 1:
         raise ValueError("one problem per graph is required")
+    if ranks is not None and (len(ranks) != G or any(r.dtype != torch.float64 or r.numel() != g.N or
+                                                     not r.is_contiguous() for r, g in zip(ranks, graphs))):
+        raise ValueError("one contiguous float64 rank tensor of N elements per graph is required")
+    given = ranks
     arr = (pr_graph_problem * G)()
     ranks, traces = [], []
     for k, (g, p) in enumerate(zip(graphs, problems)):
         if g.prep is None:
             g.prepare(ctx)
-        r = torch.empty(g.N, dtype=torch.float64, device=g.off.device)
+        r = given[k] if given is not None else torch.empty(g.N, dtype=torch.float64, device=g.off.device)
         tr = torch.full((int(p["max_iter"]), 3), float("nan"), dtype=torch.float64, device=g.off.device) if trace \
             else None
         ini = inits[k] if inits is not None else None
@@ -351,13 +356,14 @@ def multi_problems(ctx: Context, graphs, problems, inits=None, trace: bool = Fal
     return arr, ranks, traces
 
 
-def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, workspace=None) -> list:
+def pull_multi(ctx: Context, graphs, problems, inits=None, trace: bool = False, workspace=None, ranks=None) -> list:
     """Many graphs, each with its own problem, in one persistent launch (pr_pull_multi, float64).
 
     graphs: DeviceGraph list (prepared here if needed); problems: dicts with alpha, tau, norm,
-    max_iter.  Returns one dict per graph (ranks, iterations, converged, err, trace)."""
+    max_iter; ranks: optional output tensors (one per graph).  Returns one dict per graph (ranks,
+    iterations, converged, err, trace)."""
     G = len(graphs)
-    arr, ranks, traces = multi_problems(ctx, graphs, problems, inits, trace)
+    arr, ranks, traces = multi_problems(ctx, graphs, problems, inits, trace, ranks)
     nbytes = ctx.lib.pr_multi_workspace_bytes(G, arr)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=graphs[0].off.device)
