@@ -342,8 +342,11 @@ def run_sweep(args, pr, gg, np, torch):
         roof = roofline(name64, b64, msu / nu * 1e-3, nu, traffic64)
         roof["frac_of_stream"] = round(roof["achieved"] / copy_gbs, 4)
         add_ceiling(roof, dg, 8)
+        # value counts every column's edge updates; the iteration itself gathers E edges per update
+        # of the slowest column (its edge rate beside: gathered_edges_gteps)
         extra = {"updates_per_step": round(nu / stat_steps, 2), "update_us": round(1e3 * msu / nu, 1),
-                 "folds_per_step": round(nf / stat_steps, 2), "fold_us": round(1e3 * msf / nf, 1) if nf else None}
+                 "folds_per_step": round(nf / stat_steps, 2), "fold_us": round(1e3 * msf / nf, 1) if nf else None,
+                 "gathered_edges_gteps": round(nu / stat_steps * E / step_s / 1e9, 2)}
         dtype = "f64"
         how = ("float64, one iteration for all columns (PageRank as a power series in the damping factor: the a = 1 "
                "iterates v_j, column a's change a^k (v_k - v_{k-1}), ranks a^k v_k + (1-a) sum_{j<k} a^j v_j)")
