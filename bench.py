@@ -12,7 +12,7 @@ change a^k times theirs), each column stopping exactly where its own iteration w
 mixed-precision sweep (pr_pull_batch: float32 gather with float64 norms, teleport terms and final
 float64 updates) is timed beside it (--path batch_mixed makes it the headline).  The graph is
 synthetic: the paper's SuiteSparse graphs are not available; it is prepared with the
-source-segmented layout (--seg-bits, default 2^19 ids per segment).
+source-segmented layout (--seg-len, default 2^19 ids per segment).
 
 Reported:
   value            column-edge updates per second of the timed sweep (sum over the eleven columns
@@ -256,15 +256,15 @@ def run_sweep(args, pr, gg, np, torch):
     ctx = pr.Context(0)
     dg = pr.DeviceGraph.from_host(g, 0)
     t = time.time()
-    if args.seg_bits:
+    if args.seg_len:
         # tile partitions plus the source-segmented layout: single-vector updates (the sequential
         # float64 solves, the power-series sweep) run as per-segment partial sums and a merge
-        dg.prepare_segmented(ctx, seg_bits=args.seg_bits)
+        dg.prepare_segmented(ctx, seg_len=args.seg_len)
     else:
         dg.prepare(ctx)
     torch.cuda.synchronize()
     prep_ms = (time.time() - t) * 1e3
-    log("prepared in %.1f ms (segment bits %d, %d pairs)" % (prep_ms, args.seg_bits, dg.seg_pairs))
+    log("prepared in %.1f ms (segments of %d ids, %d pairs)" % (prep_ms, args.seg_len, dg.seg_pairs))
 
     alphas = gg.ALPHA_SWEEP
     tau, norm, max_iter = 1e-10, pr.PR_LINF, 500
@@ -299,7 +299,7 @@ def run_sweep(args, pr, gg, np, torch):
     n64, ms64 = ctx.stats(pr._lib.PR_KERNEL_UPDATE_F64)
     # the same float64 update without the segmented layout (one solve, event-timed), for comparison
     plain64_us = None
-    if args.seg_bits:
+    if args.seg_len:
         ctx.set_option("segmented", 0)
         ctx.reset_stats()
         ctx.set_option("timing", 1)
@@ -332,7 +332,7 @@ def run_sweep(args, pr, gg, np, torch):
     traffic64 = read_traffic("update_f64_rmat_s%d" % scale, d64)
     b64 = single_update_bytes(N, E, 8)
     name64 = ("segmented float64 update (k_seg_gather<double> + k_update<double> merge + k_finish<double>)"
-              if args.seg_bits else "k_update<double>")
+              if args.seg_len else "k_update<double>")
 
     extra = {}
     if args.path == "series":
@@ -372,8 +372,8 @@ def run_sweep(args, pr, gg, np, torch):
         line["plain_fp64_gather"] = roofline(name64, b64, ms64 / n64 * 1e-3, n64, traffic64)
         line["plain_fp64_gather"]["gteps_per_update"] = round(E / (ms64 / n64 * 1e-3) / 1e9, 2)
         line["plain_fp64_gather"]["frac_of_stream"] = round(line["plain_fp64_gather"]["achieved"] / copy_gbs, 4)
-        if args.seg_bits:
-            line["plain_fp64_gather"]["segment_bits"] = args.seg_bits
+        if args.seg_len:
+            line["plain_fp64_gather"]["segment_len"] = args.seg_len
             line["plain_fp64_gather"]["pairs"] = dg.seg_pairs
             line["plain_fp64_gather"]["unsegmented_update_us"] = round(plain64_us, 1) if plain64_us else None
             if plain64_us:
@@ -512,8 +512,8 @@ def relabelled_sweep(args, pr, ctx, dg, problems, path, tau, norm, max_iter, N, 
     dh, perm = dg.relabelled(ctx)
     torch.cuda.synchronize()
     relabel_ms = (time.perf_counter() - t0) * 1e3
-    if args.seg_bits:
-        dh.prepare_segmented(ctx, seg_bits=args.seg_bits)
+    if args.seg_len:
+        dh.prepare_segmented(ctx, seg_len=args.seg_len)
     else:
         dh.prepare(ctx)
     log("relabelled by out-degree in %.1f ms" % relabel_ms)
@@ -1016,8 +1016,8 @@ def main():
     ap.add_argument("--seq-reps", type=int, default=2, help="timed repetitions of the sequential FP64 baseline")
     ap.add_argument("--epochs", type=int, default=20, help="training epochs of the warm-start network")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started sweep")
-    ap.add_argument("--seg-bits", type=int, default=19, help="source segments of 2^bits ids for the single-vector "
-                    "solves of the sweep workload (0: the plain update)")
+    ap.add_argument("--seg-len", type=int, default=1 << 19, help="source ids per segment of the source-segmented "
+                    "layout used by the sweep workload's single-vector updates (0: the plain update)")
     ap.add_argument("--warm-graphs", type=int, default=8, help="training graphs of the warm-started sweep's network")
     args = ap.parse_args()
 

@@ -160,15 +160,15 @@ int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, 
 
 /* Source-segmented layout, a locality preprocessing for the pull gather of section 2 (the sum of
  * each row is formed as per-segment partial sums, then their sum; the terms are the same).
- * Source ids are cut into segments of 2^seg_bits consecutive ids (seg_bits in [8, 30]), chosen so
- * that one segment's slice of the iterate (8 * 2^seg_bits bytes in float64) fits an XCD's L2.  A
+ * Source ids are cut into segments of seg_len consecutive ids (seg_len >= 256), chosen so that
+ * one segment's slice of the iterate (8 * seg_len bytes in float64) fits an XCD's L2.  A
  * "pair" is a run of one row's entries whose sources lie in one segment, cut every 1024 entries of
  * the row.  pr_pull, given a prep buffer written by pr_prepare_segmented (and option "segmented"
  * at its default 1), runs each update as a per-segment step over the pairs listed segment by
  * segment, writing one partial sum per pair, then a merge step that sums every row's partials
  * in segment order and applies the update's epilogue.  Needs E <= 2^31 - 2.
  *
- * pr_segment_count: the number of pairs of the graph at seg_bits, into *pairs (host).  Reads
+ * pr_segment_count: the number of pairs of the graph at seg_len, into *pairs (host).  Reads
  * in_offsets and in_indices (device); workspace: device, >= 8200 bytes.  Synchronises the stream.
  * pr_segment_bytes: bytes of a prep buffer holding the plain tile partitions of pr_prepare and the
  * segmented layout with `pairs` pairs (construction scratch included); 0 for bad arguments.
@@ -178,10 +178,10 @@ int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, 
  * partial sums of the solve that uses it: solves sharing one segmented prep buffer must not run
  * concurrently.  Synchronises the stream.  A graph without edges gets the plain partitions only. */
 int pr_segment_count(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
-                     int64_t E, int32_t seg_bits, void *workspace, size_t workspace_bytes, int64_t *pairs);
-size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_bits, int64_t pairs);
+                     int64_t E, int32_t seg_len, void *workspace, size_t workspace_bytes, int64_t *pairs);
+size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_len, int64_t pairs);
 int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
-                         int64_t E, int32_t seg_bits, int64_t pairs, void *prep, size_t prep_bytes);
+                         int64_t E, int32_t seg_len, int64_t pairs, void *prep, size_t prep_bytes);
 
 /* Degree ordering of the vertices, a locality preprocessing for the pull gather (the ranks of the
  * relabelled graph are those of the original, renamed): perm[v] = new id of v, vertices by

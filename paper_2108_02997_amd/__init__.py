@@ -97,9 +97,9 @@ class DeviceGraph:
                                                     self.prep.data_ptr(), nbytes))
         return self
 
-    def prepare_segmented(self, ctx: Context, seg_bits: int = 18):
+    def prepare_segmented(self, ctx: Context, seg_len: int = 1 << 19):
         """pr_segment_count + pr_prepare_segmented: the tile partitions plus the source-segmented
-        layout (segments of 2^seg_bits source ids), kept on the object; pr_pull then runs its
+        layout (segments of seg_len source ids), kept on the object; pr_pull then runs its
         updates in two steps (per-segment partial sums, then the merge)."""
         dev = self.off.device
         if self.E == 0:
@@ -107,14 +107,14 @@ class DeviceGraph:
         cnt_ws = torch.empty(16384, dtype=torch.uint8, device=dev)
         pairs = ctypes.c_int64()
         _lib.check("pr_segment_count", ctx.lib.pr_segment_count(
-            ctx.handle, ctx.stream, self.off.data_ptr(), self.idx.data_ptr(), self.N, self.E, int(seg_bits),
+            ctx.handle, ctx.stream, self.off.data_ptr(), self.idx.data_ptr(), self.N, self.E, int(seg_len),
             cnt_ws.data_ptr(), cnt_ws.numel(), ctypes.byref(pairs)))
-        nbytes = ctx.lib.pr_segment_bytes(ctx.handle, self.N, self.E, int(seg_bits), pairs.value)
+        nbytes = ctx.lib.pr_segment_bytes(ctx.handle, self.N, self.E, int(seg_len), pairs.value)
         if nbytes == 0:
             raise PrError("pr_segment_bytes", _lib.PR_EINVAL, _lib.last_error())
         self.prep = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         _lib.check("pr_prepare_segmented", ctx.lib.pr_prepare_segmented(
-            ctx.handle, ctx.stream, self.off.data_ptr(), self.idx.data_ptr(), self.N, self.E, int(seg_bits),
+            ctx.handle, ctx.stream, self.off.data_ptr(), self.idx.data_ptr(), self.N, self.E, int(seg_len),
             pairs.value, self.prep.data_ptr(), nbytes))
         self.seg_pairs = pairs.value
         return self

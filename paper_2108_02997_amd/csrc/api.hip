@@ -126,8 +126,8 @@ int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &
 }
 
 // Key bits of the segment sort: enough for every segment id of N sources (at least 1).
-int seg_key_bits(int64_t N, int bits) {
-  const int64_t S = ((N - 1) >> bits) + 1;
+int seg_key_bits(int64_t N, int32_t seg_len) {
+  const int64_t S = (N - 1) / seg_len + 1;
   int k = 1;
   while (k < 31 && ((int64_t)1 << k) < S) ++k;
   return k;
@@ -135,9 +135,9 @@ int seg_key_bits(int64_t N, int bits) {
 
 // Layout of the source-segmented part of a prep buffer with P pairs, after the plain prep;
 // false when a hipCUB size query fails.
-bool seg_layout(int64_t N, int64_t E, int bits, int64_t P, SegLayout *sl) {
+bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl) {
   size_t sort_b = 0, scan_e = 0, scan_p = 0;
-  if (seg_sort_temp_bytes(P, seg_key_bits(N, bits), &sort_b) != hipSuccess ||
+  if (seg_sort_temp_bytes(P, seg_key_bits(N, seg_len), &sort_b) != hipSuccess ||
       seg_scan_temp_bytes(E + 1, &scan_e) != hipSuccess || seg_scan_temp_bytes(P + 1, &scan_p) != hipSuccess)
     return false;
   SegLayout L{};
@@ -642,26 +642,26 @@ int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, 
   return prepare_into(ctx, (hipStream_t)stream, in_offsets, N, E, prep, &h);
 }
 
-static bool bad_seg_args(int64_t N, int64_t E, int32_t seg_bits) {
+static bool bad_seg_args(int64_t N, int64_t E, int32_t seg_len) {
   if (bad_graph_sizes(N, E)) return true;
   if (E > 2147483646LL) {
     set_error("the source-segmented layout needs E <= 2^31-2, got %lld", (long long)E);
     return true;
   }
-  if (seg_bits < kMinSegBits || seg_bits > 30) {
-    set_error("seg_bits must be in [%d, 30], got %d", kMinSegBits, seg_bits);
+  if (seg_len < kMinSegLen) {
+    set_error("seg_len must be at least %d, got %d", kMinSegLen, seg_len);
     return true;
   }
   return false;
 }
 
 int pr_segment_count(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
-                     int64_t E, int32_t seg_bits, void *workspace, size_t workspace_bytes, int64_t *pairs) {
+                     int64_t E, int32_t seg_len, void *workspace, size_t workspace_bytes, int64_t *pairs) {
   if (!ctx || !in_offsets || !workspace || !pairs || (E > 0 && !in_indices)) {
     set_error("pr_segment_count: NULL argument");
     return PR_EINVAL;
   }
-  if (bad_seg_args(N, E, seg_bits)) return PR_EINVAL;
+  if (bad_seg_args(N, E, seg_len)) return PR_EINVAL;
   const size_t need = (size_t)(seg_count_blocks() + 1) * sizeof(unsigned long long);
   if (workspace_bytes < need) {
     set_error("pr_segment_count: workspace has %zu bytes, needs %zu", workspace_bytes, need);
@@ -670,18 +670,18 @@ int pr_segment_count(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const
   *pairs = 0;
   if (E == 0) return PR_OK;
   DeviceGuard g(ctx->device);
-  PR_HIP(launch_seg_count((hipStream_t)stream, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits,
+  PR_HIP(launch_seg_count((hipStream_t)stream, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_len,
                           (unsigned long long *)workspace, ctx->hscratch));
   *pairs = (int64_t)ctx->hscratch[0];
   return PR_OK;
 }
 
-size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_bits, int64_t pairs) {
-  if (!ctx || bad_seg_args(N, E, seg_bits) || pairs < 0 || pairs > E || (E > 0 && pairs < 1)) return 0;
+size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_len, int64_t pairs) {
+  if (!ctx || bad_seg_args(N, E, seg_len) || pairs < 0 || pairs > E || (E > 0 && pairs < 1)) return 0;
   if (E == 0) return prep_bytes(N, E);
   DeviceGuard g(ctx->device);
   SegLayout sl;
-  if (!seg_layout(N, E, seg_bits, pairs, &sl)) {
+  if (!seg_layout(N, E, seg_len, pairs, &sl)) {
     set_error("pr_segment_bytes: hipCUB size query failed");
     return 0;
   }
@@ -689,17 +689,17 @@ size_t pr_segment_bytes(pr_ctx *ctx, int64_t N, int64_t E, int32_t seg_bits, int
 }
 
 int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, int64_t N,
-                         int64_t E, int32_t seg_bits, int64_t pairs, void *prep, size_t prep_bytes_) {
+                         int64_t E, int32_t seg_len, int64_t pairs, void *prep, size_t prep_bytes_) {
   if (!ctx || !in_offsets || !prep || (E > 0 && !in_indices)) {
     set_error("pr_prepare_segmented: NULL argument");
     return PR_EINVAL;
   }
-  if (bad_seg_args(N, E, seg_bits)) return PR_EINVAL;
+  if (bad_seg_args(N, E, seg_len)) return PR_EINVAL;
   if (pairs < 0 || pairs > E || (E > 0 && pairs < 1)) {
     set_error("pr_prepare_segmented: pairs %lld out of range (use pr_segment_count)", (long long)pairs);
     return PR_EINVAL;
   }
-  const size_t need = pr_segment_bytes(ctx, N, E, seg_bits, pairs);
+  const size_t need = pr_segment_bytes(ctx, N, E, seg_len, pairs);
   if (need == 0) return PR_EINVAL;
   if (prep_bytes_ < need) {
     set_error("pr_prepare_segmented: prep buffer has %zu bytes, needs %zu", prep_bytes_, need);
@@ -711,20 +711,20 @@ int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, c
   int rc = prepare_into(ctx, s, in_offsets, N, E, prep, &h);
   if (rc != PR_OK || E == 0) return rc;  // no edges: the plain partitions alone
   SegLayout sl;
-  if (!seg_layout(N, E, seg_bits, pairs, &sl)) {
+  if (!seg_layout(N, E, seg_len, pairs, &sl)) {
     set_error("pr_prepare_segmented: hipCUB size query failed");
     return PR_EDEVICE;
   }
   char *base = (char *)prep;
   // the count again, so that a stale or mistyped `pairs` cannot overrun the layout
-  PR_HIP(launch_seg_count(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits,
+  PR_HIP(launch_seg_count(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_len,
                           (unsigned long long *)(base + sl.cub_off), ctx->hscratch));
   if ((int64_t)ctx->hscratch[0] != pairs) {
-    set_error("pr_prepare_segmented: the graph has %llu pairs at seg_bits %d, %lld given", ctx->hscratch[0], seg_bits,
+    set_error("pr_prepare_segmented: the graph has %llu pairs at seg_len %d, %lld given", ctx->hscratch[0], seg_len,
               (long long)pairs);
     return PR_EINVAL;
   }
-  PR_HIP(launch_seg_build(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_bits, seg_key_bits(N, seg_bits),
+  PR_HIP(launch_seg_build(s, in_offsets, in_indices, (int32_t)N, (int32_t)E, seg_len, seg_key_bits(N, seg_len),
                           pairs, base, sl));
   // tile partitions of the pair CSR (P rows over E entries) and of the merge CSR (N rows over P)
   struct {
@@ -751,7 +751,7 @@ int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, c
     set_error("internal: a pair longer than one tile window");
     return PR_EDEVICE;
   }
-  h.seg_bits = seg_bits;
+  h.seg_len = seg_len;
   h.sl = sl;
   return write_prep_header(ctx, s, prep, h);
 }

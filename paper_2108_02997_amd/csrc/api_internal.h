@@ -173,8 +173,8 @@ int get_prep(pr_ctx *ctx, hipStream_t s, const void *prep, int64_t N, int64_t E,
 int prepare_parts(pr_ctx *ctx, hipStream_t s, const int32_t *off, int64_t N, int64_t E, void *prep, int tile_a,
                   int tile_b, PrepHeader *hin, PrepHeader *out);
 int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &h);
-int seg_key_bits(int64_t N, int bits);
-bool seg_layout(int64_t N, int64_t E, int bits, int64_t P, SegLayout *sl);
+int seg_key_bits(int64_t N, int32_t seg_len);
+bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl);
 int make_events(std::vector<hipEvent_t> &ev, size_t n);
 int run_chunk(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const std::vector<hipEvent_t> **events);
 int run_until_stop(pr_ctx *ctx, hipStream_t s, const ChunkSpec &c, const LoopHead *head, int max_updates,

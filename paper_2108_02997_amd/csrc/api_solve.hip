@@ -79,7 +79,7 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[precision == PR_FP64 ? 0 : 1];
   // a prep with the source-segmented layout: the merge step's tiles take the place of the plain
   // update's, the per-segment step runs before it
-  const bool seg = ctx->segmented != 0 && h.seg_bits > 0;
+  const bool seg = ctx->segmented != 0 && h.seg_len > 0;
   const PrepPart &part = seg ? h.sl.merge_part : h.part[0];
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
 
@@ -580,7 +580,7 @@ int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   // the a = 1 iteration, as pr_pull's float64 solve (segmented when the prep has the layout)
   const std::pair<int32_t, int64_t> ts = tuned_settings(ctx, h);
   const int64_t gcap = ts.second > 0 ? ts.second : ctx->resident[0];
-  const bool seg = ctx->segmented != 0 && h.seg_bits > 0;
+  const bool seg = ctx->segmented != 0 && h.seg_len > 0;
   const PrepPart &part = seg ? h.sl.merge_part : h.part[0];
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>({(int64_t)part.ndesc, gcap, kMaxGrid}));
   IterParams p{};

@@ -67,7 +67,7 @@ struct PrepPart {
 };
 
 // Source-segmented layout (pr_prepare_segmented), in the same buffer after the plain prep's
-// regions.  Source ids are cut into segments of 2^bits consecutive ids; a pair is a run of one
+// regions.  Source ids are cut into segments of seg_len consecutive ids; a pair is a run of one
 // row's entries whose sources lie in one segment (at most kPairMax entries: longer runs are cut
 // at row-relative multiples of kPairMax).  Pairs are listed segment by segment, rows ascending
 // within a segment (the pair CSR: poff[P+1] over the permuted indices sidx[E]); the merge CSR
@@ -88,7 +88,7 @@ struct SegLayout {
   PrepPart merge_part;  // tiles over the merge CSR
 };
 constexpr int32_t kPairMax = kTile;
-constexpr int32_t kMinSegBits = 8;
+constexpr int32_t kMinSegLen = 256;
 
 struct PrepHeader {
   int32_t magic;
@@ -98,7 +98,7 @@ struct PrepHeader {
   int32_t seg, pad;
   int64_t scan_off;   // byte offset of the scan scratch
   PrepPart part[2];
-  int32_t seg_bits;   // 0: no source-segmented layout, else 2^seg_bits source ids per segment
+  int32_t seg_len;    // 0: no source-segmented layout, else source ids per segment
   int32_t pad2;
   SegLayout sl;
 };
@@ -216,11 +216,11 @@ hipError_t launch_sweep_fold(hipStream_t s, const double *slots, int64_t stride,
 hipError_t launch_copy_f64(hipStream_t s, const double *src, double *dst, int64_t n);
 // Source-segmented layout (segment.hip).
 int64_t seg_count_blocks();
-hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
-                            unsigned long long *block_counts, unsigned long long *host_total);
+hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,
+                            int32_t seg_len, unsigned long long *block_counts, unsigned long long *host_total);
 hipError_t seg_sort_temp_bytes(int64_t P, int key_bits, size_t *bytes);
 hipError_t seg_scan_temp_bytes(int64_t n, size_t *bytes);
-hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
-                            int key_bits, int64_t P, char *base, const SegLayout &sl);
+hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,
+                            int32_t seg_len, int key_bits, int64_t P, char *base, const SegLayout &sl);
 
 }  // namespace prpull

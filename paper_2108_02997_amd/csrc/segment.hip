@@ -2,7 +2,7 @@
 // pull gather (it reorders the additions of each row's sum of section 2 into per-segment
 // partial sums; the terms summed are the same).
 //
-// Source ids are cut into segments of 2^bits consecutive ids, sized so that one segment's slice
+// Source ids are cut into segments of seg_len consecutive ids, sized so that one segment's slice
 // of the iterate stays resident in an XCD's L2 while its entries are gathered.  A pair is a run
 // of one row's entries whose sources lie in one segment, cut at row-relative multiples of
 // kPairMax entries (so no pair needs more than one tile).  The update then runs in two steps:
@@ -43,19 +43,19 @@ __device__ __forceinline__ int32_t row_of(const int32_t *__restrict__ off, int32
 }
 
 __device__ __forceinline__ int32_t pair_start(const int32_t *__restrict__ off, const int32_t *__restrict__ idx,
-                                              int32_t N, int bits, int32_t j) {
+                                              int32_t N, int32_t seg_len, int32_t j) {
   const int32_t rel = j - off[row_of(off, N, j)];
   if (rel % kPairMax == 0) return 1;
-  return (idx[j] >> bits) != (idx[j - 1] >> bits) ? 1 : 0;
+  return idx[j] / seg_len != idx[j - 1] / seg_len ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_count(const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ idx, int32_t N, int32_t E,
-                                                      int bits, unsigned long long *__restrict__ part) {
+                                                      int32_t seg_len, unsigned long long *__restrict__ part) {
   __shared__ unsigned long long red[kWaves];
   unsigned long long n = 0;
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < E; j += (int64_t)gridDim.x * kBlock)
-    n += (unsigned long long)pair_start(off, idx, N, bits, (int32_t)j);
+    n += (unsigned long long)pair_start(off, idx, N, seg_len, (int32_t)j);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = n;
@@ -75,9 +75,9 @@ __global__ void k_seg_count_total(unsigned long long *part, int32_t nb) {
   }
 }
 
-hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
-                            unsigned long long *block_counts, unsigned long long *host_total) {
-  hipLaunchKernelGGL(k_seg_count, dim3(kSegCountBlocks), dim3(kBlock), 0, s, off, idx, N, E, bits, block_counts);
+hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,
+                            int32_t seg_len, unsigned long long *block_counts, unsigned long long *host_total) {
+  hipLaunchKernelGGL(k_seg_count, dim3(kSegCountBlocks), dim3(kBlock), 0, s, off, idx, N, E, seg_len, block_counts);
   hipLaunchKernelGGL(k_seg_count_total, dim3(1), dim3(64), 0, s, block_counts, (int32_t)kSegCountBlocks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -90,14 +90,14 @@ hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *id
 // Step 1: F[j] for j < E, F[E] = 0.
 __global__ __launch_bounds__(kBlock) void k_seg_flags(const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ idx, int32_t N, int32_t E,
-                                                      int bits, int32_t *__restrict__ F) {
+                                                      int32_t seg_len, int32_t *__restrict__ F) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j <= E; j += (int64_t)gridDim.x * kBlock)
-    F[j] = j < E ? pair_start(off, idx, N, bits, (int32_t)j) : 0;
+    F[j] = j < E ? pair_start(off, idx, N, seg_len, (int32_t)j) : 0;
 }
 
 // Step 2: per pair in row order; pstart[P] = E.
 __global__ __launch_bounds__(kBlock) void k_seg_pairs(const int32_t *__restrict__ idx, const int32_t *__restrict__ F,
-                                                      const int32_t *__restrict__ X, int32_t E, int bits,
+                                                      const int32_t *__restrict__ X, int32_t E, int32_t seg_len,
                                                       int32_t *__restrict__ pstart, int32_t *__restrict__ pseg,
                                                       int32_t *__restrict__ pq) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j <= E; j += (int64_t)gridDim.x * kBlock) {
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_pairs(const int32_t *__restrict_
     } else if (F[j]) {
       const int32_t q = X[j];
       pstart[q] = (int32_t)j;
-      pseg[q] = idx[j] >> bits;
+      pseg[q] = idx[j] / seg_len;
       pq[q] = q;
     }
   }
@@ -168,8 +168,8 @@ hipError_t seg_scan_temp_bytes(int64_t n, size_t *bytes) {
 // Construction scratch: F aliases sidx (E + 1 values), the sort's inputs alias part (2P values);
 // X, pstart, the sort keys' output (later the pair lengths), perm and hipCUB's storage sit at
 // temp_off.
-hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E, int bits,
-                            int key_bits, int64_t P, char *base, const SegLayout &sl) {
+hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,
+                            int32_t seg_len, int key_bits, int64_t P, char *base, const SegLayout &sl) {
   int32_t *poff = (int32_t *)(base + sl.poff_off);
   int32_t *moff = (int32_t *)(base + sl.moff_off);
   int32_t *mpos = (int32_t *)(base + sl.mpos_off);
@@ -192,10 +192,10 @@ hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *id
   if (e == hipSuccess) e = seg_scan_temp_bytes(P + 1, &scan_p);
   if (e != hipSuccess) return e;
 
-  hipLaunchKernelGGL(k_seg_flags, dim3(grid_n(E + 1)), dim3(kBlock), 0, s, off, idx, N, E, bits, F);
+  hipLaunchKernelGGL(k_seg_flags, dim3(grid_n(E + 1)), dim3(kBlock), 0, s, off, idx, N, E, seg_len, F);
   e = hipcub::DeviceScan::ExclusiveSum(cub, scan_e, F, X, (int)(E + 1), s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_seg_pairs, dim3(grid_n(E + 1)), dim3(kBlock), 0, s, idx, F, X, E, bits, pstart, pseg, pq);
+  hipLaunchKernelGGL(k_seg_pairs, dim3(grid_n(E + 1)), dim3(kBlock), 0, s, idx, F, X, E, seg_len, pstart, pseg, pq);
   hipLaunchKernelGGL(k_seg_moff, dim3(grid_n((int64_t)N + 1)), dim3(kBlock), 0, s, off, X, N, moff);
   e = hipcub::DeviceRadixSort::SortPairs(cub, sort_b, pseg, kout, pq, perm, (int)P, 0, key_bits, s);
   if (e != hipSuccess) return e;

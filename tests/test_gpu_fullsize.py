@@ -109,7 +109,7 @@ def rmat24():
 def dev24(pr, ctx, rmat24):
     # prepared as the benchmark prepares it: tile partitions plus the source-segmented layout
     dg = pr.DeviceGraph.from_host(rmat24)
-    dg.prepare_segmented(ctx, seg_bits=19)
+    dg.prepare_segmented(ctx, seg_len=1 << 19)
     yield dg
     del dg
     torch.cuda.empty_cache()

@@ -2,7 +2,7 @@
 the C ABI.
 
 * The layout is integer work and is compared bit for bit with a plain numpy construction from its
-  definition (pairs = runs of one row's entries whose sources share a segment of 2^bits ids, cut
+  definition (pairs = runs of one row's entries whose sources share a segment of seg_len ids, cut
   every 1024 entries of the row; pair CSR listed segment by segment, rows ascending; merge CSR
   listing every row's pairs in segment order).
 * Solves on it keep the float64 bar of tests/parity.py against the oracle (1e-12 L1 after the
@@ -55,17 +55,17 @@ class PrepHeader(ctypes.Structure):
     """The library's prep header as laid out in the buffer (internal.h)."""
     _fields_ = [("magic", ctypes.c_int32), ("version", ctypes.c_int32), ("N", ctypes.c_int64), ("E", ctypes.c_int64),
                 ("seg", ctypes.c_int32), ("pad", ctypes.c_int32), ("scan_off", ctypes.c_int64),
-                ("part", PrepPart * 2), ("seg_bits", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sl", SegLayout)]
+                ("part", PrepPart * 2), ("seg_len", ctypes.c_int32), ("pad2", ctypes.c_int32), ("sl", SegLayout)]
 
 
-def expected_layout(g, bits):
+def expected_layout(g, seg_len):
     """The segmented layout from its definition (numpy, row order first)."""
     off = g.off.astype(np.int64)
     idx = g.idx.astype(np.int64)
     E = g.E
     rows = np.repeat(np.arange(g.N, dtype=np.int64), np.diff(off))
     rel = np.arange(E, dtype=np.int64) - off[rows]
-    seg = idx >> bits
+    seg = idx // seg_len
     start = (rel % PAIR_MAX == 0)
     start[1:] |= seg[1:] != seg[:-1]
     q_start = np.flatnonzero(start)                     # row-order pairs
@@ -100,9 +100,9 @@ def read_layout(dg):
     return h, P, arr(sl.poff_off, P + 1), arr(sl.sidx_off, dg.E), arr(sl.moff_off, dg.N + 1), arr(sl.mpos_off, P)
 
 
-def segmented(pr, ctx, g, bits):
+def segmented(pr, ctx, g, seg_len):
     dg = pr.DeviceGraph.from_host(g)
-    dg.prepare_segmented(ctx, seg_bits=bits)
+    dg.prepare_segmented(ctx, seg_len=seg_len)
     return dg
 
 
@@ -124,14 +124,15 @@ GRAPHS = {
 }
 
 
-@pytest.mark.parametrize("name,bits", [("rmat13", 8), ("rmat13", 10), ("rmat13", 13), ("er_c1", 9),
-                                       ("hubs", 8), ("hubs", 12)])
-def test_layout_matches_definition(pr, ctx, name, bits):
+@pytest.mark.parametrize("name,seg_len", [("rmat13", 256), ("rmat13", 1024), ("rmat13", 3 * 1024 + 7),
+                                          ("rmat13", 8192), ("er_c1", 512), ("er_c1", 3000), ("hubs", 256),
+                                          ("hubs", 4096)])
+def test_layout_matches_definition(pr, ctx, name, seg_len):
     g = GRAPHS[name]()
-    dg = segmented(pr, ctx, g, bits)
-    P, poff, sidx, moff, mpos = expected_layout(g, bits)
+    dg = segmented(pr, ctx, g, seg_len)
+    P, poff, sidx, moff, mpos = expected_layout(g, seg_len)
     h, Pd, poff_d, sidx_d, moff_d, mpos_d = read_layout(dg)
-    assert h.seg_bits == bits and Pd == P == dg.seg_pairs
+    assert h.seg_len == seg_len and Pd == P == dg.seg_pairs
     np.testing.assert_array_equal(poff_d, poff)
     np.testing.assert_array_equal(sidx_d, sidx)
     np.testing.assert_array_equal(moff_d, moff)
@@ -139,10 +140,11 @@ def test_layout_matches_definition(pr, ctx, name, bits):
     assert h.sl.pair_part.nhubs == 0 and int(np.diff(poff).max()) <= PAIR_MAX
 
 
-@pytest.mark.parametrize("name,bits", [("rmat13", 8), ("rmat13", 11), ("er_c1", 10), ("hubs", 9)])
-def test_fp64_parity_every_norm(pr, ctx, name, bits):
+@pytest.mark.parametrize("name,seg_len", [("rmat13", 256), ("rmat13", 2048), ("rmat13", 1500), ("er_c1", 1024),
+                                          ("hubs", 512)])
+def test_fp64_parity_every_norm(pr, ctx, name, seg_len):
     g = GRAPHS[name]()
-    dg = segmented(pr, ctx, g, bits)
+    dg = segmented(pr, ctx, g, seg_len)
     for norm in (1, 2, 3):
         for alpha, tau in ((0.85, 1e-10), (0.5, 1e-6), (0.99, 1e-8)):
             res = pr.pull(ctx, dg, alpha=alpha, tau=tau, norm=norm, max_iter=500, trace=True)
@@ -152,7 +154,7 @@ def test_fp64_parity_every_norm(pr, ctx, name, bits):
 
 def test_alpha_one_and_zero(pr, ctx):
     g = gg.rmat(12, seed=5)
-    dg = segmented(pr, ctx, g, 8)
+    dg = segmented(pr, ctx, g, 256)
     for alpha in (0.0, 1.0):
         res = pr.pull(ctx, dg, alpha=alpha, tau=1e-9, norm=1, max_iter=300, trace=True)
         check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], alpha, 1e-9, 1, 300,
@@ -161,7 +163,7 @@ def test_alpha_one_and_zero(pr, ctx):
 
 def test_mixed_and_fp32_only(pr, ctx):
     g = gg.rmat(14, seed=8)
-    dg = segmented(pr, ctx, g, 10)
+    dg = segmented(pr, ctx, g, 1024)
     for norm in (1, 3):
         res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=norm, max_iter=500, precision=pr.PR_MIXED)
         assert res["converged"] and res["fp32_iters"] >= 1
@@ -172,7 +174,7 @@ def test_mixed_and_fp32_only(pr, ctx):
 
 def test_bitwise_repeatable_and_plain_switch(pr, ctx):
     g = gg.rmat(14, seed=9)
-    dg = segmented(pr, ctx, g, 9)
+    dg = segmented(pr, ctx, g, 512)
     a = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)
     b = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1)
     assert torch.equal(a["ranks"], b["ranks"]) and a["iterations"] == b["iterations"]
@@ -187,7 +189,7 @@ def test_bitwise_repeatable_and_plain_switch(pr, ctx):
 
 def test_given_start_and_edgeless(pr, ctx):
     g = gg.rmat(12, seed=12)
-    dg = segmented(pr, ctx, g, 8)
+    dg = segmented(pr, ctx, g, 256)
     rng = np.random.default_rng(3)
     init = rng.random(g.N)
     init /= init.sum()
@@ -196,7 +198,7 @@ def test_given_start_and_edgeless(pr, ctx):
                       init=init, gpu_trace=res["trace"].cpu().numpy())
     # no edges: the plain partitions alone (every vertex dangling, 1/N after one update)
     e = gg.from_edges(50, [], [])
-    de = segmented(pr, ctx, e, 8)
+    de = segmented(pr, ctx, e, 256)
     r = pr.pull(ctx, de, alpha=0.85, tau=1e-12, norm=1)
     assert r["iterations"] == 1 and float((r["ranks"] - 1.0 / 50).abs().max()) < 1e-17
 
@@ -207,29 +209,29 @@ def test_count_and_arguments(pr, ctx):
     ws = torch.empty(16384, dtype=torch.uint8, device="cuda")
     pairs = ctypes.c_int64()
     lib = ctx.lib
-    for bits in (8, 10, 20):
-        assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, bits,
+    for seg_len in (256, 1000, 1 << 20):
+        assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, seg_len,
                                     ws.data_ptr(), ws.numel(), ctypes.byref(pairs)) == 0
-        assert pairs.value == expected_layout(g, bits)[0]
-    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 7,
+        assert pairs.value == expected_layout(g, seg_len)[0]
+    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 255,
                                 ws.data_ptr(), ws.numel(), ctypes.byref(pairs)) == pr._lib.PR_EINVAL
-    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+    assert lib.pr_segment_count(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 1024,
                                 ws.data_ptr(), 100, ctypes.byref(pairs)) == pr._lib.PR_ENOMEM
-    P = expected_layout(g, 10)[0]
-    nbytes = lib.pr_segment_bytes(ctx.handle, g.N, g.E, 10, P)
+    P = expected_layout(g, 1024)[0]
+    nbytes = lib.pr_segment_bytes(ctx.handle, g.N, g.E, 1024, P)
     assert nbytes > lib.pr_prep_bytes(g.N, g.E)
-    assert lib.pr_segment_bytes(ctx.handle, g.N, g.E, 10, g.E + 1) == 0
+    assert lib.pr_segment_bytes(ctx.handle, g.N, g.E, 1024, g.E + 1) == 0
     buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     # a pair count that is not the graph's is refused before the layout is built
-    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 1024,
                                     P - 1, buf.data_ptr(), nbytes) == pr._lib.PR_EINVAL
-    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 10,
+    assert lib.pr_prepare_segmented(ctx.handle, ctx.stream, dg.off.data_ptr(), dg.idx.data_ptr(), g.N, g.E, 1024,
                                     P, buf.data_ptr(), nbytes - 1) == pr._lib.PR_ENOMEM
 
 
 def test_scale22_fp64_against_oracle(pr, ctx):
     g = gg.rmat(22, edge_factor=16, seed=22)
-    dg = segmented(pr, ctx, g, 18)
+    dg = segmented(pr, ctx, g, 1 << 18)
     print("scale 22: N %d E %d pairs %d (%.3f E)" % (g.N, g.E, dg.seg_pairs, dg.seg_pairs / g.E), flush=True)
     res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1, max_iter=500, trace=True)
     ref = check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, 1, 500,

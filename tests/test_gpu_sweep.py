@@ -91,7 +91,7 @@ def test_one_and_sixty_four_columns_and_hubs(pr, ctx):
 def test_segmented_prep_and_repeatable(pr, ctx):
     g = gg.rmat(14, seed=63)
     dg = pr.DeviceGraph.from_host(g)
-    dg.prepare_segmented(ctx, seg_bits=10)
+    dg.prepare_segmented(ctx, seg_len=1 << 10)
     a = check_sweep(pr, ctx, g, sweep_problems(), dg=dg)
     b = pr.pull_sweep(ctx, dg, sweep_problems())
     assert all(torch.equal(x["ranks"], y["ranks"]) and x["iterations"] == y["iterations"] for x, y in zip(a, b))
@@ -139,6 +139,6 @@ def test_argument_errors(pr, ctx):
 def test_scale22_sweep_against_oracle(pr, ctx):
     g = gg.rmat(22, edge_factor=16, seed=22)
     dg = pr.DeviceGraph.from_host(g)
-    dg.prepare_segmented(ctx, seg_bits=19)
+    dg.prepare_segmented(ctx, seg_len=1 << 19)
     res = check_sweep(pr, ctx, g, sweep_problems(), dg=dg)
     print("scale 22 sweep iterations:", [r["iterations"] for r in res])
