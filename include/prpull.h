@@ -111,6 +111,9 @@ const char *pr_version(void);
  *             (default 5000); a wait that passes it ends the launch with PR_EDEVICE
  *   "segmented": 1 (default) = pr_pull runs source-segmented updates when its prep buffer has the
  *             layout of pr_prepare_segmented; 0 = the plain update on the same buffer
+ *   "merge_xcd": 1 (default) = the merge step of a source-segmented update gives each of the 8
+ *             XCDs a contiguous range of row tiles (their pairs' partial sums then share lines
+ *             in that XCD's L2); 0 = tiles dealt round-robin over all workgroups
  *   "narrow": 1 (default) = one or two columns of pr_pull_batch run on rows of one or two values;
  *             0 = rows hold at least four values (the row layouts keep every column's sums in
  *             the same order, so with a pinned grid compaction then leaves results bitwise equal)

@@ -568,6 +568,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->segmented = value;
+  } else if (!strcmp(key, "merge_xcd")) {
+    if (value != 0 && value != 1) {
+      set_error("merge_xcd must be 0 or 1");
+      return PR_EINVAL;
+    }
+    ctx->merge_xcd = value;
   } else if (!strcmp(key, "narrow")) {
     if (value != 0 && value != 1) {
       set_error("narrow must be 0 or 1");

@@ -31,6 +31,21 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
 namespace prpull {
 
 // pr_pull after its NULL checks (also the body of the entry point that allocates nothing).
+// The source-segmented update's arrays (per-segment step over the pair CSR, merge step over the
+// merge CSR in place of the plain tiles) from a prep buffer that holds the layout.
+static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp, int64_t gcap, IterParams &p) {
+  char *base = (char *)const_cast<void *>(pp);
+  p.off = (const int32_t *)(base + h.sl.moff_off);
+  p.idx = (const int32_t *)(base + h.sl.mpos_off);
+  p.poff = (const int32_t *)(base + h.sl.poff_off);
+  p.sidx = (const int32_t *)(base + h.sl.sidx_off);
+  p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
+  p.npdesc = h.sl.pair_part.ndesc;
+  p.partial = base + h.sl.part_off;
+  p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
+  p.merge_xcd = (int32_t)ctx->merge_xcd;
+}
+
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
@@ -86,17 +101,7 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
-  if (seg) {
-    char *base = (char *)const_cast<void *>(pp);
-    p.off = (const int32_t *)(base + h.sl.moff_off);
-    p.idx = (const int32_t *)(base + h.sl.mpos_off);
-    p.poff = (const int32_t *)(base + h.sl.poff_off);
-    p.sidx = (const int32_t *)(base + h.sl.sidx_off);
-    p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
-    p.npdesc = h.sl.pair_part.ndesc;
-    p.partial = base + h.sl.part_off;
-    p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
-  }
+  if (seg) set_segmented(ctx, h, pp, gcap, p);
   p.outdeg = outdeg;
   p.desc = (const int4 *)((const char *)pp + part.desc_off);
   p.ndesc = part.ndesc;
@@ -586,17 +591,7 @@ int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
-  if (seg) {
-    char *base = (char *)const_cast<void *>(pp);
-    p.off = (const int32_t *)(base + h.sl.moff_off);
-    p.idx = (const int32_t *)(base + h.sl.mpos_off);
-    p.poff = (const int32_t *)(base + h.sl.poff_off);
-    p.sidx = (const int32_t *)(base + h.sl.sidx_off);
-    p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
-    p.npdesc = h.sl.pair_part.ndesc;
-    p.partial = base + h.sl.part_off;
-    p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
-  }
+  if (seg) set_segmented(ctx, h, pp, gcap, p);
   p.outdeg = outdeg;
   p.desc = (const int4 *)((const char *)pp + part.desc_off);
   p.ndesc = part.ndesc;

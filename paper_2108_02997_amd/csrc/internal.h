@@ -182,6 +182,8 @@ struct IterParams {
   void *partial;
   int32_t npdesc;
   int32_t pgrid;       // workgroups of the per-segment step
+  int32_t merge_xcd;   // 1: the merge step gives each XCD a contiguous range of tiles
+  int32_t pad3;
   // Non-null: this is the a = 1 iteration of a power-series sweep; finalize decides every
   // column's stop instead of testing tau.
   SweepCols *sweep;

@@ -123,7 +123,18 @@ __global__ __launch_bounds__(kBlock) void k_update(IterParams p) {
   c.mid_deg = p.mid_deg;
   const int t = threadIdx.x;
   Acc a = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t i = blockIdx.x; i < p.ndesc; i += gridDim.x) update_tile<VT>(c, p.desc[i], p.desc[i + 1], a, vals, red);
+  if (p.partial && p.merge_xcd && (gridDim.x & 7) == 0) {
+    // merge step: workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b % 8),
+    // so XCD x takes the x-th eighth of the tiles; neighbouring tiles read neighbouring partial
+    // sums of every segment, which then share lines in that XCD's L2
+    const int32_t x = blockIdx.x & 7, nx = gridDim.x >> 3;
+    const int32_t lo = (int32_t)((int64_t)p.ndesc * x / 8), hi = (int32_t)((int64_t)p.ndesc * (x + 1) / 8);
+    for (int32_t i = lo + (int32_t)(blockIdx.x >> 3); i < hi; i += nx)
+      update_tile<VT>(c, p.desc[i], p.desc[i + 1], a, vals, red);
+  } else {
+    for (int32_t i = blockIdx.x; i < p.ndesc; i += gridDim.x)
+      update_tile<VT>(c, p.desc[i], p.desc[i + 1], a, vals, red);
+  }
 
   const double l1 = block_sum_n<kBlock>(a.l1, red);
   const double sq = block_sum_n<kBlock>(a.sq, red);

@@ -187,6 +187,26 @@ def test_bitwise_repeatable_and_plain_switch(pr, ctx):
     assert pr.l1_distance(ctx, a["ranks"], c["ranks"]) <= 1e-12
 
 
+def test_merge_tiles_per_xcd_or_round_robin(pr, ctx):
+    # the merge step's tile order only regroups the norm partials: same ranks bit for bit after a
+    # fixed number of updates, norms equal up to the order of their sums, and oracle parity
+    g = gg.rmat(15, seed=10)
+    dg = segmented(pr, ctx, g, 1024)
+    runs = {}
+    for mx in (1, 0):
+        ctx.set_option("merge_xcd", mx)
+        try:
+            runs[mx] = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=25, trace=True)
+        finally:
+            ctx.set_option("merge_xcd", 1)
+    assert torch.equal(runs[0]["ranks"], runs[1]["ranks"])
+    np.testing.assert_allclose(runs[0]["trace"].cpu().numpy(), runs[1]["trace"].cpu().numpy(), rtol=1e-13, atol=0)
+    check_fp64_result(g, runs[0]["ranks"].cpu().numpy(), 25, False, 0.85, 0.0, 1, 25,
+                      gpu_trace=runs[0]["trace"].cpu().numpy())
+    with pytest.raises(pr.PrError):
+        ctx.set_option("merge_xcd", 2)
+
+
 def test_given_start_and_edgeless(pr, ctx):
     g = gg.rmat(12, seed=12)
     dg = segmented(pr, ctx, g, 256)
