@@ -111,9 +111,14 @@ const char *pr_version(void);
  *             (default 5000); a wait that passes it ends the launch with PR_EDEVICE
  *   "segmented": 1 (default) = pr_pull runs source-segmented updates when its prep buffer has the
  *             layout of pr_prepare_segmented; 0 = the plain update on the same buffer
- *   "merge_xcd": 1 (default) = the merge step of a source-segmented update gives each of the 8
- *             XCDs a contiguous range of row tiles (their pairs' partial sums then share lines
- *             in that XCD's L2); 0 = tiles dealt round-robin over all workgroups
+ *   "seg_xcd": 1 (default) = the per-segment step of a source-segmented update gives each of the
+ *             8 XCDs a contiguous eighth of its tiles (each XCD then walks a few segments of its
+ *             own, and a segment's slice of the iterate is fetched into one XCD's L2 only);
+ *             0 = tiles dealt round-robin over all workgroups.  Bitwise the same results
+ *   "merge_xcd": 1 = the same for the merge step (neighbouring tiles read neighbouring partial
+ *             sums, which then share lines in one XCD's L2: pays for short segments, with many
+ *             pairs); 0 (default) = round-robin.  The ranks are bitwise the same; the norms'
+ *             partial sums are grouped differently
  *   "narrow": 1 (default) = one or two columns of pr_pull_batch run on rows of one or two values;
  *             0 = rows hold at least four values (the row layouts keep every column's sums in
  *             the same order, so with a pinned grid compaction then leaves results bitwise equal)
@@ -299,7 +304,7 @@ size_t pr_sweep_workspace_bytes(int64_t N, int64_t E, int32_t with_prep);
  * is a^k times the change of the a = 1 iteration's update k.  pr_pull_sweep runs the a = 1
  * iteration (the float64 update of pr_pull, source-segmented when prep has that layout); after
  * every update each problem's change a_k^k e_k decides its stop exactly as its own iteration
- * would (same tolerance test, same count), and every 16 updates the iterates are added with the
+ * would (same tolerance test, same count), and every 32 updates the iterates are added with the
  * weights above into each problem's ranks.  Each result (ranks, iterations, converged, final
  * errors, trace rows) is that of problem k's own power iteration up to float64 rounding; the
  * iteration runs until the last problem stops.
@@ -307,7 +312,7 @@ size_t pr_sweep_workspace_bytes(int64_t N, int64_t E, int32_t with_prep);
  *   probs      : host, K problems (any alpha in [0, 1], tau >= 0, norm, max_iter >= 1)
  *   ranks      : host array of K distinct device pointers (N float64 each, out)
  *   norm_trace : host array of K device pointers (max_iter x 3 float64 each) or NULL
- *   workspace  : device, >= pr_sweep_workspace_bytes(N, E, prep == NULL) (holds 17 iterates)
+ *   workspace  : device, >= pr_sweep_workspace_bytes(N, E, prep == NULL) (holds 33 iterates)
  *   results    : host, K entries (fp32_iters = 0)
  * Returns PR_OK when every problem converged, PR_NOT_CONVERGED when at least one stopped at its
  * max_iter, or a negative status. */

@@ -568,12 +568,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->segmented = value;
-  } else if (!strcmp(key, "merge_xcd")) {
+  } else if (!strcmp(key, "seg_xcd") || !strcmp(key, "merge_xcd")) {
     if (value != 0 && value != 1) {
-      set_error("merge_xcd must be 0 or 1");
+      set_error("%s must be 0 or 1", key);
       return PR_EINVAL;
     }
-    ctx->merge_xcd = value;
+    (key[0] == 's' ? ctx->seg_xcd : ctx->merge_xcd) = value;
   } else if (!strcmp(key, "narrow")) {
     if (value != 0 && value != 1) {
       set_error("narrow must be 0 or 1");

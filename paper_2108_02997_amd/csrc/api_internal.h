@@ -96,7 +96,8 @@ struct pr_ctx {
   int64_t narrow = 1;       // 1: one or two columns run on rows of one or two values
   int64_t handover32 = 1;   // 1: the first float64 update of a mixed batch reads float32 rows
   int64_t segmented = 1;    // 1: pr_pull uses the source-segmented layout of a prep that has one
-  int64_t merge_xcd = 1;    // 1: the merge step gives each XCD a contiguous range of tiles
+  int64_t seg_xcd = 1;      // 1: the per-segment step gives each XCD a contiguous range of tiles
+  int64_t merge_xcd = 0;    // 1: the merge step does too
   int64_t window_tile[2] = {kTile, kTileB};  // tile windows of new partitions A and B (entries)
   int64_t window_rows[2] = {kRows, kRowsB};
   int64_t barrier_ms = 5000;  // time limit of a grid-barrier wait in pr_pull_multi

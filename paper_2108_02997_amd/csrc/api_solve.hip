@@ -43,6 +43,7 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
   p.npdesc = h.sl.pair_part.ndesc;
   p.partial = base + h.sl.part_off;
   p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
+  p.seg_xcd = (int32_t)ctx->seg_xcd;
   p.merge_xcd = (int32_t)ctx->merge_xcd;
 }
 
@@ -579,7 +580,7 @@ int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     hc.trace[k] = norm_trace ? norm_trace[k] : nullptr;
   }
   PR_HIP(hipMemcpyAsync(L.cols, &hc, sizeof hc, hipMemcpyHostToDevice, s));
-  for (int k = 0; k < K; ++k) PR_HIP(launch_fill_u32(s, (uint32_t *)ranks[k], 2 * N, 0u));
+  // (the ranks need no clearing: the first fold writes every column)
   PR_HIP(launch_fill_u32(s, (uint32_t *)L.st, sizeof(SolveState) / 4, 0u));
 
   // the a = 1 iteration, as pr_pull's float64 solve (segmented when the prep has the layout)

@@ -134,7 +134,7 @@ struct alignas(64) SolveState {
 // v_j the iterates of the a = 1 update from u, and its change at update k is a^k (v_k - v_{k-1}):
 // one a = 1 iteration serves every column.  Per-column parameters and stop state (device).
 constexpr int kMaxSweepCols = 64;
-constexpr int kSweepChunk = 16;  // updates between folds; the workspace keeps kSweepChunk + 1 iterates
+constexpr int kSweepChunk = 32;  // updates between folds; the workspace keeps kSweepChunk + 1 iterates
 struct SweepCols {
   double alpha[kMaxSweepCols];
   double tau[kMaxSweepCols];
@@ -182,7 +182,8 @@ struct IterParams {
   void *partial;
   int32_t npdesc;
   int32_t pgrid;       // workgroups of the per-segment step
-  int32_t merge_xcd;   // 1: the merge step gives each XCD a contiguous range of tiles
+  int32_t seg_xcd;     // 1: the per-segment step gives each XCD a contiguous range of tiles
+  int32_t merge_xcd;   // 1: the merge step does
   int32_t pad3;
   // Non-null: this is the a = 1 iteration of a power-series sweep; finalize decides every
   // column's stop instead of testing tau.

@@ -164,8 +164,18 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(IterParams p) {
   c.part = (VT *)p.partial;
   c.mid_deg = p.mid_deg;
   Acc a = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t i = blockIdx.x; i < p.npdesc; i += gridDim.x)
-    update_tile<VT, true>(c, p.pdesc[i], p.pdesc[i + 1], a, vals, red);
+  if (p.seg_xcd && (gridDim.x & 7) == 0) {
+    // workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b % 8), so XCD x
+    // takes the x-th eighth of the tiles: each XCD walks a few segments of its own, and every
+    // segment's slice of the iterate is fetched into one XCD's L2 instead of all eight
+    const int32_t x = blockIdx.x & 7, nx = gridDim.x >> 3;
+    const int32_t lo = (int32_t)((int64_t)p.npdesc * x / 8), hi = (int32_t)((int64_t)p.npdesc * (x + 1) / 8);
+    for (int32_t i = lo + (int32_t)(blockIdx.x >> 3); i < hi; i += nx)
+      update_tile<VT, true>(c, p.pdesc[i], p.pdesc[i + 1], a, vals, red);
+  } else {
+    for (int32_t i = blockIdx.x; i < p.npdesc; i += gridDim.x)
+      update_tile<VT, true>(c, p.pdesc[i], p.pdesc[i + 1], a, vals, red);
+  }
 }
 
 // One block: hub rows (segment partials combined in segment order, then the epilogue), the

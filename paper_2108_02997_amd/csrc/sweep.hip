@@ -23,7 +23,8 @@ constexpr int kFoldBlock = 256;
 constexpr int kMaxFoldSlots = kSweepChunk + 1;
 
 // ranks_k[x] += sum_i c_k(j0 + i) r_i[x] over the slots i < n (ascending i), r_i[x] = y_i[x] d_x
-// (y_i[x] for a dangling x), for every column k still collecting at these steps.
+// (y_i[x] for a dangling x), for every column k still collecting at these steps; the first fold
+// (j0 = 0, every column collecting) writes ranks_k[x] = that sum instead.
 __global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restrict__ slots, int64_t stride,
                                                            int32_t first, int32_t n, int32_t j0,
                                                            const int32_t *__restrict__ outdeg, int32_t N,
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restr
     for (int q = 0; q < m; ++q) {
       const int k = cols[q];
       double *__restrict__ out = sw->ranks[k];
-      double acc = out[x];
+      double acc = j0 == 0 ? 0.0 : out[x];
 #pragma unroll
       for (int i = 0; i < kMaxFoldSlots; ++i)
         if (i < n) acc += coef[k][i] * r[i];

@@ -187,24 +187,32 @@ def test_bitwise_repeatable_and_plain_switch(pr, ctx):
     assert pr.l1_distance(ctx, a["ranks"], c["ranks"]) <= 1e-12
 
 
-def test_merge_tiles_per_xcd_or_round_robin(pr, ctx):
-    # the merge step's tile order only regroups the norm partials: same ranks bit for bit after a
-    # fixed number of updates, norms equal up to the order of their sums, and oracle parity
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tiles_per_xcd_or_round_robin(pr, ctx, precision):
+    # the tile order of either step only regroups the norm partials: the same ranks bit for bit
+    # after a fixed number of updates, norms equal up to the order of their sums, oracle parity
     g = gg.rmat(15, seed=10)
     dg = segmented(pr, ctx, g, 1024)
+    prec = pr.PR_FP64 if precision == "fp64" else pr.PR_FP32
+    its = 25 if precision == "fp64" else 12  # float32: well above its rounding floor
     runs = {}
-    for mx in (1, 0):
+    for sx, mx in ((1, 1), (0, 1), (1, 0), (0, 0)):
+        ctx.set_option("seg_xcd", sx)
         ctx.set_option("merge_xcd", mx)
         try:
-            runs[mx] = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=25, trace=True)
+            runs[sx, mx] = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=its, trace=True, precision=prec)
         finally:
-            ctx.set_option("merge_xcd", 1)
-    assert torch.equal(runs[0]["ranks"], runs[1]["ranks"])
-    np.testing.assert_allclose(runs[0]["trace"].cpu().numpy(), runs[1]["trace"].cpu().numpy(), rtol=1e-13, atol=0)
-    check_fp64_result(g, runs[0]["ranks"].cpu().numpy(), 25, False, 0.85, 0.0, 1, 25,
-                      gpu_trace=runs[0]["trace"].cpu().numpy())
-    with pytest.raises(pr.PrError):
-        ctx.set_option("merge_xcd", 2)
+            ctx.set_option("seg_xcd", 1)
+            ctx.set_option("merge_xcd", 0)
+    for key, r in runs.items():
+        assert r["iterations"] == its and torch.equal(r["ranks"], runs[1, 1]["ranks"]), key
+        np.testing.assert_allclose(r["trace"].cpu().numpy(), runs[1, 1]["trace"].cpu().numpy(), rtol=1e-6, atol=0)
+    if precision == "fp64":
+        check_fp64_result(g, runs[1, 1]["ranks"].cpu().numpy(), 25, False, 0.85, 0.0, 1, 25,
+                          gpu_trace=runs[1, 1]["trace"].cpu().numpy())
+    for key in ("seg_xcd", "merge_xcd"):
+        with pytest.raises(pr.PrError):
+            ctx.set_option(key, 2)
 
 
 def test_given_start_and_edgeless(pr, ctx):
