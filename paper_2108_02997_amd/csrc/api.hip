@@ -568,6 +568,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->segmented = value;
+  } else if (!strcmp(key, "seg_grid")) {
+    if (value < 0 || value > kMaxGrid) {
+      set_error("seg_grid must be in [0, %d]", kMaxGrid);
+      return PR_EINVAL;
+    }
+    ctx->seg_grid = value;
   } else if (!strcmp(key, "seg_xcd") || !strcmp(key, "merge_xcd")) {
     if (value != 0 && value != 1) {
       set_error("%s must be 0 or 1", key);

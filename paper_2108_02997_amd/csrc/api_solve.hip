@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "api_internal.h"
+#include "sweep.h"
 
 extern "C" {
 
@@ -33,7 +34,7 @@ namespace prpull {
 // pr_pull after its NULL checks (also the body of the entry point that allocates nothing).
 // The source-segmented update's arrays (per-segment step over the pair CSR, merge step over the
 // merge CSR in place of the plain tiles) from a prep buffer that holds the layout.
-static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp, int64_t gcap, IterParams &p) {
+static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp, bool fp32, IterParams &p) {
   char *base = (char *)const_cast<void *>(pp);
   p.off = (const int32_t *)(base + h.sl.moff_off);
   p.idx = (const int32_t *)(base + h.sl.mpos_off);
@@ -42,7 +43,11 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
   p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
   p.npdesc = h.sl.pair_part.ndesc;
   p.partial = base + h.sl.part_off;
-  p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, gcap, kMaxGrid}));
+  // the update kernel's resident count (7 workgroups per CU in float64): measured faster than
+  // the per-segment step's own full occupancy of 8, whose extra tiles in flight crowd the
+  // segment's slice in L2 (R-MAT scale 24: 1.77 against 1.81 ms per update)
+  const int64_t sg = ctx->seg_grid > 0 ? ctx->seg_grid : ctx->resident[fp32 ? 1 : 0];
+  p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, sg, kMaxGrid}));
   p.seg_xcd = (int32_t)ctx->seg_xcd;
   p.merge_xcd = (int32_t)ctx->merge_xcd;
 }
@@ -102,7 +107,7 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
-  if (seg) set_segmented(ctx, h, pp, gcap, p);
+  if (seg) set_segmented(ctx, h, pp, precision != PR_FP64, p);
   p.outdeg = outdeg;
   p.desc = (const int4 *)((const char *)pp + part.desc_off);
   p.ndesc = part.ndesc;
@@ -495,6 +500,7 @@ struct SweepLayout {
   double *bpart;
   double *hpart;
   SweepCols *cols;
+  FoldTable *fold;
   double *slots;
   int64_t stride;  // doubles between slots
   void *prep;
@@ -508,6 +514,7 @@ static SweepLayout carve_sweep(void *ws, int64_t N, int64_t E, bool with_prep) {
   L.bpart = (double *)c.take(4 * sizeof(double) * (size_t)kMaxGrid);
   L.hpart = (double *)c.take(sizeof(double) * (size_t)max_slots(N, E));
   L.cols = (SweepCols *)c.take(sizeof(SweepCols));
+  L.fold = (FoldTable *)c.take(sizeof(FoldTable));
   L.stride = (int64_t)(align_up(sizeof(double) * (size_t)N, 256) / sizeof(double));
   L.slots = (double *)c.take(sizeof(double) * (size_t)L.stride * (kSweepChunk + 1));
   L.prep = with_prep ? c.take(prep_bytes(N, E)) : nullptr;
@@ -592,7 +599,7 @@ int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
   IterParams p{};
   p.off = in_offsets;
   p.idx = in_indices;
-  if (seg) set_segmented(ctx, h, pp, gcap, p);
+  if (seg) set_segmented(ctx, h, pp, false, p);
   p.outdeg = outdeg;
   p.desc = (const int4 *)((const char *)pp + part.desc_off);
   p.ndesc = part.ndesc;
@@ -659,7 +666,7 @@ int pr_pull_sweep(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const in
     if (nfold > 0) {
       if (ctx->timing) PR_HIP(hipEventRecord(fev.a, s));
       PR_HIP(launch_sweep_fold(s, L.slots, L.stride, first ? 0 : 1, nfold, first ? 0 : before + 1, outdeg,
-                               (int32_t)N, L.cols, K));
+                               (int32_t)N, L.cols, K, L.fold));
       if (ctx->timing) {
         PR_HIP(hipEventRecord(fev.b, s));
         PR_HIP(hipEventSynchronize(fev.b));

@@ -212,11 +212,7 @@ hipError_t launch_prepare(hipStream_t s, int tile, int rows, const int32_t *off,
                           void *scan, unsigned long long *host_total);
 int64_t scan_block_count(int64_t N);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
-// Fold the iterates slots[first .. first + n) (y form, steps j0 .. j0 + n - 1) of a sweep into
-// every column's ranks (sweep.hip); copy one iterate slot onto another.
-hipError_t launch_sweep_fold(hipStream_t s, const double *slots, int64_t stride, int32_t first, int32_t n,
-                             int32_t j0, const int32_t *outdeg, int32_t N, const SweepCols *sw, int32_t K);
-hipError_t launch_copy_f64(hipStream_t s, const double *src, double *dst, int64_t n);
+// The power-series sweep's fold and copy launchers: sweep.h.
 // Source-segmented layout (segment.hip).
 int64_t seg_count_blocks();
 hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,

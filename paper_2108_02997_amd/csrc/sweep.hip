@@ -15,27 +15,39 @@
 //     c_k(j) v_j,  c_k(j) = (1-alpha_k) alpha_k^j for j < s_k, alpha_k^s_k for j = s_k, 0 after,
 // to ranks_k (s_k: the update column k stopped at, not yet known while it runs).  All weights are
 // non-negative and every v_j is, so the sums lose nothing to cancellation.
-#include "internal.h"
+#include "sweep.h"
 
 namespace prpull {
 
 constexpr int kFoldBlock = 256;
 constexpr int kMaxFoldSlots = kSweepChunk + 1;
 
-// ranks_k[x] += sum_i c_k(j0 + i) r_i[x] over the slots i < n (ascending i), r_i[x] = y_i[x] d_x
-// (y_i[x] for a dangling x), for every column k still collecting at these steps; the first fold
-// (j0 = 0, every column collecting) writes ranks_k[x] = that sum instead.
-__global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restrict__ slots, int64_t stride,
-                                                           int32_t first, int32_t n, int32_t j0,
-                                                           const int32_t *__restrict__ outdeg, int32_t N,
-                                                           const SweepCols *__restrict__ sw, int32_t K) {
+// The fold's weights: for every column k still collecting at updates j0 .. j0 + n - 1 (not stopped,
+// or stopped at one of them), c_k(j) = (1 - alpha_k) alpha_k^j for j < s_k, alpha_k^s_k at j = s_k
+// and 0 after (s_k = 0 while column k runs).  One block.
+__global__ __launch_bounds__(kFoldBlock) void k_sweep_coef(const SweepCols *__restrict__ sw, int32_t K, int32_t n,
+                                                           int32_t j0, FoldTable *__restrict__ ft) {
 #pragma clang fp contract(off)
-  __shared__ double coef[kMaxSweepCols][kMaxFoldSlots];
   __shared__ int32_t cols[kMaxSweepCols];
   __shared__ int32_t ncols;
   const int t = threadIdx.x;
-  for (int q = t; q < K * n; q += kFoldBlock) {
-    const int k = q / n, i = q % n;
+  if (t == 0) {
+    int32_t m = 0;
+    for (int k = 0; k < K; ++k) {
+      const int32_t sk = sw->stop_iter[k];
+      if (sk == 0 || sk >= j0) {
+        cols[m] = k;
+        ft->out[m] = sw->ranks[k];
+        ++m;
+      }
+    }
+    ncols = m;
+    ft->m = m;
+  }
+  __syncthreads();
+  for (int q = t; q < ncols * n; q += kFoldBlock) {
+    const int r = q / n, i = q % n;
+    const int k = cols[r];
     const int32_t j = j0 + i;
     const int32_t sk = sw->stop_iter[k];
     const double a = sw->alpha[k];
@@ -44,18 +56,29 @@ __global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restr
       c = (1.0 - a) * pow(a, (double)j);
     else if (j == sk)
       c = pow(a, (double)j);
-    coef[k][i] = c;
+    ft->coef[r][i] = c;
   }
-  if (t == 0) {
-    int32_t m = 0;
-    for (int k = 0; k < K; ++k) {
-      const int32_t sk = sw->stop_iter[k];
-      if (sk == 0 || sk >= j0) cols[m++] = k;
-    }
-    ncols = m;
+}
+
+// ranks_k[x] += sum_i c_k(j0 + i) r_i[x] over the slots i < n (ascending i), r_i[x] = y_i[x] d_x
+// (y_i[x] for a dangling x), for every column k still collecting at these steps; the first fold
+// (j0 = 0, every column collecting) writes ranks_k[x] = that sum instead.
+// (register budget capped for 5 waves per SIMD: the 33 slot values per lane otherwise take 110
+// VGPRs, 4 waves)
+__global__ __launch_bounds__(kFoldBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sweep_fold(
+    const double *__restrict__ slots, int64_t stride, int32_t first, int32_t n, int32_t j0,
+    const int32_t *__restrict__ outdeg, int32_t N, const FoldTable *__restrict__ ft) {
+#pragma clang fp contract(off)
+  __shared__ double coef[kMaxSweepCols][kMaxFoldSlots];
+  __shared__ double *outs[kMaxSweepCols];
+  const int t = threadIdx.x;
+  const int32_t m = ft->m;
+  for (int q = t; q < m * kMaxFoldSlots; q += kFoldBlock) {
+    const int r = q / kMaxFoldSlots, i = q % kMaxFoldSlots;
+    coef[r][i] = i < n ? ft->coef[r][i] : 0.0;
   }
+  for (int q = t; q < m; q += kFoldBlock) outs[q] = ft->out[q];
   __syncthreads();
-  const int32_t m = ncols;
   for (int64_t x = (int64_t)blockIdx.x * kFoldBlock + t; x < N; x += (int64_t)gridDim.x * kFoldBlock) {
     const int32_t dx = outdeg[x];
     const double scale = dx > 0 ? (double)dx : 1.0;
@@ -64,12 +87,11 @@ __global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restr
     for (int i = 0; i < kMaxFoldSlots; ++i)
       r[i] = i < n ? __builtin_nontemporal_load(slots + (int64_t)(first + i) * stride + x) * scale : 0.0;
     for (int q = 0; q < m; ++q) {
-      const int k = cols[q];
-      double *__restrict__ out = sw->ranks[k];
+      double *__restrict__ out = outs[q];
       double acc = j0 == 0 ? 0.0 : out[x];
 #pragma unroll
       for (int i = 0; i < kMaxFoldSlots; ++i)
-        if (i < n) acc += coef[k][i] * r[i];
+        if (i < n) acc += coef[q][i] * r[i];
       out[x] = acc;
     }
   }
@@ -87,10 +109,12 @@ static unsigned fold_grid(int64_t n) {
 }
 
 hipError_t launch_sweep_fold(hipStream_t s, const double *slots, int64_t stride, int32_t first, int32_t n,
-                             int32_t j0, const int32_t *outdeg, int32_t N, const SweepCols *sw, int32_t K) {
+                             int32_t j0, const int32_t *outdeg, int32_t N, const SweepCols *sw, int32_t K,
+                             FoldTable *ft) {
   if (n < 1 || n > kMaxFoldSlots || K < 1 || K > kMaxSweepCols) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sweep_coef, dim3(1), dim3(kFoldBlock), 0, s, sw, K, n, j0, ft);
   hipLaunchKernelGGL(k_sweep_fold, dim3(fold_grid(N)), dim3(kFoldBlock), 0, s, slots, stride, first, n, j0, outdeg,
-                     N, sw, K);
+                     N, (const FoldTable *)ft);
   return hipGetLastError();
 }
 

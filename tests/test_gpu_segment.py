@@ -213,6 +213,17 @@ def test_tiles_per_xcd_or_round_robin(pr, ctx, precision):
     for key in ("seg_xcd", "merge_xcd"):
         with pytest.raises(pr.PrError):
             ctx.set_option(key, 2)
+    # any grid of the per-segment step (a multiple of 8 or not) gives the same partial sums
+    for grid in (8, 1000, 24):
+        ctx.set_option("seg_grid", grid)
+        try:
+            r = pr.pull(ctx, dg, alpha=0.85, tau=0.0, norm=1, max_iter=its, precision=prec)
+        finally:
+            ctx.set_option("seg_grid", 0)
+        assert torch.equal(r["ranks"], runs[1, 1]["ranks"]), grid
+    for bad in (-1, 16385):
+        with pytest.raises(pr.PrError):
+            ctx.set_option("seg_grid", bad)
 
 
 def test_given_start_and_edgeless(pr, ctx):
