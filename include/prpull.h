@@ -111,6 +111,8 @@ const char *pr_version(void);
  *             (default 5000); a wait that passes it ends the launch with PR_EDEVICE
  *   "segmented": 1 (default) = pr_pull runs source-segmented updates when its prep buffer has the
  *             layout of pr_prepare_segmented; 0 = the plain update on the same buffer
+ *   "pair_mid_deg": pairs of the per-segment step with more entries than this are summed by a
+ *             whole wave64, shorter ones by one lane, 0..1024 (default 256)
  *   "seg_grid": workgroups of the per-segment step of a source-segmented update, 1..16384; 0
  *             (default) = as many as the compute units hold of the update kernel at once
  *   "seg_xcd": 1 (default) = the per-segment step of a source-segmented update gives each of the

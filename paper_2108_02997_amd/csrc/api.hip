@@ -568,6 +568,12 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->segmented = value;
+  } else if (!strcmp(key, "pair_mid_deg")) {
+    if (value < 0 || value > kPairMax) {
+      set_error("pair_mid_deg must be in [0, %d]", kPairMax);
+      return PR_EINVAL;
+    }
+    ctx->pair_mid_deg = value;
   } else if (!strcmp(key, "seg_grid")) {
     if (value < 0 || value > kMaxGrid) {
       set_error("seg_grid must be in [0, %d]", kMaxGrid);

@@ -82,6 +82,7 @@ struct pr_ctx {
   int64_t max_grid = 0;     // 0: one workgroup per resident slot (compute units x occupancy)
   int64_t resident[2] = {1, 1};  // resident update workgroups: [float64, float32]
   int64_t seg_grid = 0;     // workgroups of the per-segment step; 0: the update's resident count
+  int64_t pair_mid_deg = kPairMidDeg;  // wave-per-pair threshold of the per-segment step
   int64_t chunk = 16;
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
   int64_t timing = 0;     // 1: bracket every update launch with HIP events

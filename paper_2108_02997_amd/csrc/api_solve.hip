@@ -50,6 +50,7 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
   p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, sg, kMaxGrid}));
   p.seg_xcd = (int32_t)ctx->seg_xcd;
   p.merge_xcd = (int32_t)ctx->merge_xcd;
+  p.pair_mid_deg = (int32_t)ctx->pair_mid_deg;
 }
 
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,

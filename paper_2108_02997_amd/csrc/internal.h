@@ -40,6 +40,11 @@ bool valid_window(int part, int tile, int rows);
 // Default threshold: rows with in-degree above kMidDeg (and at most the tile window) are summed by
 // a whole wave; pr_pull takes the threshold at run time (option "mid_deg", or the autotuner).
 constexpr int kMidDeg = 32;
+// The same for the pairs of the per-segment step (option "pair_mid_deg"): pairs are short (six
+// entries on average on R-MAT scale 24 at 2^19-id segments) and a lane sums up to 256 of them
+// faster than a wave pass does (1.73 against 1.77 ms per float64 update; 1024, never a wave:
+// 1.97 ms).
+constexpr int kPairMidDeg = 256;
 // Upper bound of the update grid (blocks loop over tiles in a fixed round-robin order).
 constexpr int kMaxGrid = 16384;
 // Graphs of one many-graph batch.
@@ -184,7 +189,7 @@ struct IterParams {
   int32_t pgrid;       // workgroups of the per-segment step
   int32_t seg_xcd;     // 1: the per-segment step gives each XCD a contiguous range of tiles
   int32_t merge_xcd;   // 1: the merge step does
-  int32_t pad3;
+  int32_t pair_mid_deg;  // pairs with more entries are summed by a whole wave (per-segment step)
   // Non-null: this is the a = 1 iteration of a power-series sweep; finalize decides every
   // column's stop instead of testing tau.
   SweepCols *sweep;

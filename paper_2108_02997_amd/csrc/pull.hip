@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(IterParams p) {
   c.idx = p.sidx;
   c.xs = (const VT *)p.y_in;
   c.part = (VT *)p.partial;
-  c.mid_deg = p.mid_deg;
+  c.mid_deg = p.pair_mid_deg;
   Acc a = {0.0, 0.0, 0.0, 0.0};
   if (p.seg_xcd && (gridDim.x & 7) == 0) {
     // workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b % 8), so XCD x

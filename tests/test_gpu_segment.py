@@ -226,6 +226,22 @@ def test_tiles_per_xcd_or_round_robin(pr, ctx, precision):
             ctx.set_option("seg_grid", bad)
 
 
+@pytest.mark.parametrize("pair_mid_deg", [0, 8, 1024])
+def test_pair_threshold(pr, ctx, pair_mid_deg):
+    # every pair summed by a wave (0), mixed (8), every pair by one lane (1024): oracle parity
+    g = hub_graph()
+    dg = segmented(pr, ctx, g, 512)
+    ctx.set_option("pair_mid_deg", pair_mid_deg)
+    try:
+        res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=2, max_iter=500, trace=True)
+    finally:
+        ctx.set_option("pair_mid_deg", 256)
+    check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, 2, 500,
+                      gpu_trace=res["trace"].cpu().numpy())
+    with pytest.raises(pr.PrError):
+        ctx.set_option("pair_mid_deg", 1025)
+
+
 def test_given_start_and_edgeless(pr, ctx):
     g = gg.rmat(12, seed=12)
     dg = segmented(pr, ctx, g, 256)
