@@ -31,7 +31,6 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
 
 namespace prpull {
 
-// pr_pull after its NULL checks (also the body of the entry point that allocates nothing).
 // The source-segmented update's arrays (per-segment step over the pair CSR, merge step over the
 // merge CSR in place of the plain tiles) from a prep buffer that holds the layout.
 static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp, bool fp32, IterParams &p) {
@@ -53,6 +52,7 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
   p.pair_mid_deg = (int32_t)ctx->pair_mid_deg;
 }
 
+// pr_pull after its NULL checks (also the body of the entry point that allocates nothing).
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
