@@ -604,7 +604,10 @@ def run_tau(args, pr, gg, np, torch):
     N, E = g.N, g.E
     ctx = pr.Context(0)
     dg = pr.DeviceGraph.from_host(g, 0)
-    dg.prepare(ctx)
+    if args.seg_len:
+        dg.prepare_segmented(ctx, seg_len=args.seg_len)
+    else:
+        dg.prepare(ctx)
     rows = []
     total = {pr.PR_FP64: 0.0, pr.PR_MIXED: 0.0}
     for norm in (pr.PR_L1, pr.PR_L2, pr.PR_LINF):
@@ -665,19 +668,27 @@ def run_tau(args, pr, gg, np, torch):
                      "GTEPS", args, t_ref * 1e3, "f64 | f32+f64",
                      {"workload": "R-MAT scale %d, edge factor 16, (.57,.19,.19,.05), seed %d, alpha=0.85, "
                                   "tau=1e-3..1e-10 x {L1,L2,Linf}, max_iter 500" % (scale, seed), "N": N, "E": E})
-    line["roofline"] = roofline("k_update<double>", single_update_bytes(N, E, 8), ms64 / n64 * 1e-3, n64, None)
-    line["fp32_update"] = roofline("k_update<float>", single_update_bytes(N, E, 4), ms32 / n32 * 1e-3, n32, None)
+    seg = bool(args.seg_len)
+    line["config"]["layout"] = ("source-segmented, %d ids per segment" % args.seg_len) if seg else "plain"
+    line["roofline"] = roofline("segmented float64 update" if seg else "k_update<double>",
+                                single_update_bytes(N, E, 8), ms64 / n64 * 1e-3, n64, None)
+    line["fp32_update"] = roofline("segmented float32 update" if seg else "k_update<float>",
+                                   single_update_bytes(N, E, 4), ms32 / n32 * 1e-3, n32, None)
     line["readout"] = rows
     line["fp32_only_below_1e-10"] = extra
     line["iteration_checks"] = checks
-    # locality: the same graph as generated, under a seeded random relabelling (the stress case) and
-    # in out-degree order (hot sources contiguous); update times of one float64 (L1) and one mixed
-    # (Linf) solve each, and the float64 ranks mapped back to the generated ids
+    # locality of the plain update (no segmented layout): the same graph as generated, under a
+    # seeded random relabelling (the stress case) and in out-degree order (hot sources
+    # contiguous); update times of one float64 (L1) and one mixed (Linf) solve each, and the
+    # float64 ranks mapped back to the generated ids
     locality = {}
+    dplain = dg
+    if seg:
+        dplain = pr.DeviceGraph.from_host(g, 0).prepare(ctx)
     for name in ("as_generated", "random_relabel", "degree_order"):
         relabel_ms = None
         if name == "as_generated":
-            perm, dh = None, dg
+            perm, dh = None, dplain
         elif name == "random_relabel":
             perm = gg.permutation(N, seed + 7)
             dh = pr.DeviceGraph.from_host(gg.relabel(g, perm), 0).prepare(ctx)
@@ -1017,7 +1028,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=20, help="training epochs of the warm-start network")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started sweep")
     ap.add_argument("--seg-len", type=int, default=1 << 19, help="source ids per segment of the source-segmented "
-                    "layout used by the sweep workload's single-vector updates (0: the plain update)")
+                    "layout used by the sweep and tau workloads' single-vector updates (0: the plain update)")
     ap.add_argument("--warm-graphs", type=int, default=8, help="training graphs of the warm-started sweep's network")
     args = ap.parse_args()
 
