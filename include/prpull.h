@@ -371,6 +371,13 @@ typedef struct {
   double default_us;         /* the same with the defaults (1024/512, threshold 32, one workgroup per slot) */
   double best_batch_us;      /* mean 8-column float32 update time of the batch choice */
   double default_batch_us;   /* the same with the defaults (256/128, threshold 32, one workgroup per slot) */
+  /* source-segmented update (only when the prep buffer holds that layout; else zeros) */
+  int32_t pair_mid_deg;      /* per-segment step: lane-per-pair / wave-per-pair threshold */
+  int32_t seg_grid;          /* per-segment step: workgroups */
+  int32_t merge_xcd;         /* merge step: 1 = each XCD a contiguous range of tiles */
+  int32_t seg_candidates;    /* configurations of the segmented update timed */
+  double best_seg_us;        /* mean segmented float64 update time of the choice */
+  double default_seg_us;     /* the same with the defaults (256, one workgroup per slot, round-robin) */
 } pr_tune_result;
 
 /* Device workspace bytes of pr_autotune (0 for out-of-range sizes); with_prep as for pr_pull. */
@@ -383,11 +390,15 @@ size_t pr_tune_workspace_bytes(int64_t N, int64_t E, int32_t with_prep);
  *     threshold 8/16/32/64/128 x 1/2/4 workgroups per resident slot, four updates each, timed on
  *     the plain (unsegmented) update;
  *   K-column float32 update (pr_pull_batch): partition B window 256/128 or 128/64 x group/wave
- *     threshold 16/32/64 x 1/2 workgroups per resident slot, three updates of 8 columns each.
+ *     threshold 16/32/64 x 1/2 workgroups per resident slot, three updates of 8 columns each;
+ *   when the prep buffer holds a source-segmented layout, the segmented float64 update:
+ *     lane/wave threshold of the pairs 64/128/256/512 x 1/2 workgroups per resident slot for
+ *     the per-segment step x merge tiles round-robin / per XCD, four updates each.
  * The chosen windows are written into the prep buffer (prep != NULL: re-partitioned in place; a
  * source-segmented layout in it is kept), and the thresholds and grids are kept in the context's
- * table, keyed by the graph's size, tile counts and windows; pr_pull, pr_pull_multi and
- * pr_pull_batch then use them for graphs with that signature unless "grid" / "mid_deg" were set
+ * table, keyed by the graph's size, tile counts and windows (and segment length); pr_pull,
+ * pr_pull_multi, pr_pull_batch and pr_pull_sweep then use them for graphs with that signature
+ * unless the options ("grid", "mid_deg", "pair_mid_deg", "seg_grid", "merge_xcd") were set
  * explicitly or "tuned" is 0.  With the environment variable PRPULL_TUNE_FILE set, the table is
  * read at pr_create and every choice is appended to that file.  ranks: device scratch of N
  * values; workspace: device, >= pr_tune_workspace_bytes(N, E, prep == NULL).  Statistics of

@@ -60,7 +60,9 @@ class pr_tune_result(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("mid_deg", "grid", "tile", "rows", "mid_deg_batch",
                                               "grid_batch_factor", "tile_batch", "rows_batch", "candidates",
                                               "pad")] + \
-               [(n, ctypes.c_double) for n in ("best_us", "default_us", "best_batch_us", "default_batch_us")]
+               [(n, ctypes.c_double) for n in ("best_us", "default_us", "best_batch_us", "default_batch_us")] + \
+               [(n, ctypes.c_int32) for n in ("pair_mid_deg", "seg_grid", "merge_xcd", "seg_candidates")] + \
+               [(n, ctypes.c_double) for n in ("best_seg_us", "default_seg_us")]
 
 
 class PrError(RuntimeError):

@@ -396,6 +396,13 @@ std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h) {
   return {mid, grid};
 }
 
+// Key of the segmented-update settings: the graph signature and the layout's segment length.
+std::vector<int64_t> seg_signature(const PrepHeader &h) {
+  std::vector<int64_t> s = graph_signature(h);
+  s.push_back(h.seg_len);
+  return s;
+}
+
 // (wave-per-row threshold, workgroups per resident slot) of pr_pull_batch for a graph: the
 // autotuner's table, else the defaults.
 std::pair<int32_t, int32_t> tuned_batch_settings(pr_ctx *ctx, const PrepHeader &h) {
@@ -407,21 +414,39 @@ std::pair<int32_t, int32_t> tuned_batch_settings(pr_ctx *ctx, const PrepHeader &
 }
 
 // Tune file lines: the graph signature (8 numbers), then mid_deg, grid, batch mid_deg, batch
-// workgroups per resident slot.
+// workgroups per resident slot; or "seg", the graph signature, the segment length, then the
+// segmented update's pair threshold, per-segment grid and merge tile order.  Other lines are
+// skipped.
 void load_tune_file(pr_ctx *ctx) {
   const char *f = getenv("PRPULL_TUNE_FILE");
   if (!f || !*f) return;
   ctx->tune_file = f;
   FILE *fp = fopen(f, "r");
   if (!fp) return;
-  long long s[8];
-  int m, g, mb, gb;
-  while (fscanf(fp, "%lld %lld %lld %lld %lld %lld %lld %lld %d %d %d %d", &s[0], &s[1], &s[2], &s[3], &s[4], &s[5],
-                &s[6], &s[7], &m, &g, &mb, &gb) == 12) {
-    const std::vector<int64_t> sig(s, s + 8);
-    ctx->tuned[sig] = {m, g};
-    ctx->tuned_batch[sig] = {mb, gb};
+  char line[512];
+  while (fgets(line, sizeof line, fp)) {
+    long long s[9];
+    int m, g, mb, gb;
+    if (sscanf(line, "seg %lld %lld %lld %lld %lld %lld %lld %lld %lld %d %d %d", &s[0], &s[1], &s[2], &s[3], &s[4],
+               &s[5], &s[6], &s[7], &s[8], &m, &g, &mb) == 12) {
+      ctx->tuned_seg[std::vector<int64_t>(s, s + 9)] = SegTune{m, g, mb};
+    } else if (sscanf(line, "%lld %lld %lld %lld %lld %lld %lld %lld %d %d %d %d", &s[0], &s[1], &s[2], &s[3], &s[4],
+                      &s[5], &s[6], &s[7], &m, &g, &mb, &gb) == 12) {
+      const std::vector<int64_t> sig(s, s + 8);
+      ctx->tuned[sig] = {m, g};
+      ctx->tuned_batch[sig] = {mb, gb};
+    }
   }
+  fclose(fp);
+}
+
+void save_tune_seg_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, const SegTune &t) {
+  if (ctx->tune_file.empty()) return;
+  FILE *fp = fopen(ctx->tune_file.c_str(), "a");
+  if (!fp) return;
+  fprintf(fp, "seg");
+  for (int64_t x : sig) fprintf(fp, " %lld", (long long)x);
+  fprintf(fp, " %d %d %d\n", t.pair_mid_deg, t.seg_grid, t.merge_xcd);
   fclose(fp);
 }
 
@@ -574,18 +599,25 @@ int pr_set_option(pr_ctx *ctx, const char *key, int64_t value) {
       return PR_EINVAL;
     }
     ctx->pair_mid_deg = value;
+    ctx->pair_mid_deg_set = true;
   } else if (!strcmp(key, "seg_grid")) {
     if (value < 0 || value > kMaxGrid) {
       set_error("seg_grid must be in [0, %d]", kMaxGrid);
       return PR_EINVAL;
     }
     ctx->seg_grid = value;
+    ctx->seg_grid_set = value != 0;
   } else if (!strcmp(key, "seg_xcd") || !strcmp(key, "merge_xcd")) {
     if (value != 0 && value != 1) {
       set_error("%s must be 0 or 1", key);
       return PR_EINVAL;
     }
-    (key[0] == 's' ? ctx->seg_xcd : ctx->merge_xcd) = value;
+    if (key[0] == 's') {
+      ctx->seg_xcd = value;
+    } else {
+      ctx->merge_xcd = value;
+      ctx->merge_xcd_set = true;
+    }
   } else if (!strcmp(key, "narrow")) {
     if (value != 0 && value != 1) {
       set_error("narrow must be 0 or 1");

@@ -65,6 +65,11 @@ struct ChunkSpec {
 
 using namespace prpull;
 
+// The autotuner's choice for a graph's source-segmented update.
+struct SegTune {
+  int32_t pair_mid_deg, seg_grid, merge_xcd;
+};
+
 struct pr_ctx {
   int device = 0;
   hipStream_t capture = nullptr;  // private stream used only for graph capture
@@ -83,6 +88,9 @@ struct pr_ctx {
   int64_t resident[2] = {1, 1};  // resident update workgroups: [float64, float32]
   int64_t seg_grid = 0;     // workgroups of the per-segment step; 0: the update's resident count
   int64_t pair_mid_deg = kPairMidDeg;  // wave-per-pair threshold of the per-segment step
+  bool pair_mid_deg_set = false, seg_grid_set = false, merge_xcd_set = false;  // set explicitly
+  // (graph signature, segment length) -> the autotuner's segmented-update settings
+  std::map<std::vector<int64_t>, SegTune> tuned_seg;
   int64_t chunk = 16;
   int64_t loop_mode = 0;  // 0: HIP-graph chunks, 1: direct launches
   int64_t timing = 0;     // 1: bracket every update launch with HIP events
@@ -189,10 +197,12 @@ BatchLayout carve_batch(void *ws, int64_t N, int64_t E, int32_t K, int32_t preci
 ChunkSpec batch_chunk(pr_ctx *ctx, bool fp32, int kp, unsigned grid, const BatchParams &p, void *b0, void *b1);
 std::vector<int64_t> graph_signature(const PrepHeader &h);
 std::pair<int32_t, int64_t> tuned_settings(pr_ctx *ctx, const PrepHeader &h);
+std::vector<int64_t> seg_signature(const PrepHeader &h);
 std::pair<int32_t, int32_t> tuned_batch_settings(pr_ctx *ctx, const PrepHeader &h);
 void load_tune_file(pr_ctx *ctx);
 void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid, int32_t mid_b,
                      int32_t grid_b);
+void save_tune_seg_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, const SegTune &t);
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,

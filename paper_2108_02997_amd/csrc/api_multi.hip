@@ -258,7 +258,9 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
   // saved settings; the candidates run with the autotuner's table off and explicit settings on
   const int64_t save_grid = ctx->max_grid, save_mid = ctx->mid_deg, save_timing = ctx->timing;
   const int64_t save_tuned = ctx->use_tuned, save_seg = ctx->segmented;
-  const bool save_set = ctx->mid_deg_set;
+  const int64_t save_pair = ctx->pair_mid_deg, save_sgrid = ctx->seg_grid, save_mxcd = ctx->merge_xcd;
+  const bool save_set = ctx->mid_deg_set, save_pair_set = ctx->pair_mid_deg_set,
+             save_sgrid_set = ctx->seg_grid_set, save_mxcd_set = ctx->merge_xcd_set;
   int64_t save_launch[PR_KERNEL_KINDS];
   double save_ms[PR_KERNEL_KINDS];
   memcpy(save_launch, ctx->stat_launches, sizeof save_launch);
@@ -270,6 +272,12 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
     ctx->timing = save_timing;
     ctx->use_tuned = save_tuned;
     ctx->segmented = save_seg;
+    ctx->pair_mid_deg = save_pair;
+    ctx->seg_grid = save_sgrid;
+    ctx->merge_xcd = save_mxcd;
+    ctx->pair_mid_deg_set = save_pair_set;
+    ctx->seg_grid_set = save_sgrid_set;
+    ctx->merge_xcd_set = save_mxcd_set;
     memcpy(ctx->stat_launches, save_launch, sizeof save_launch);
     memcpy(ctx->stat_ms, save_ms, sizeof save_ms);
   };
@@ -367,11 +375,57 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
       if (rc < 0) break;
     }
   }
+  // ---- the source-segmented update, when the prep buffer holds that layout: pair threshold x
+  // workgroups of the per-segment step x merge tile order (the merge on the single-vector
+  // update's chosen threshold and grid, as it will run)
+  const int32_t pmids[] = {64, 128, 256, 512};
+  const int64_t sgrids[] = {res, 2 * res};
+  SegTune best_st{kPairMidDeg, 0, 0};
+  double best_s = 0.0, dflt_s = 0.0;
+  int count_s = 0;
+  if (rc >= 0 && h.seg_len > 0) {
+    best_s = 1e300;
+    ctx->segmented = 1;
+    ctx->use_tuned = 0;
+    ctx->max_grid = best_grid;
+    ctx->mid_deg = best_mid;
+    ctx->mid_deg_set = true;
+    ctx->pair_mid_deg_set = ctx->seg_grid_set = ctx->merge_xcd_set = true;
+    for (int32_t pm : pmids) {
+      for (int64_t sg : sgrids) {
+        if (sg > kMaxGrid) continue;
+        for (int mx = 0; mx < 2; ++mx) {
+          ctx->pair_mid_deg = pm;
+          ctx->seg_grid = sg;
+          ctx->merge_xcd = mx;
+          clear(PR_KERNEL_UPDATE_F64);
+          pr_result r;
+          rc = pr_pull(ctx, stream, in_offsets, in_indices, outdeg, N, E, pp, 0.85, 0.0, PR_L1, kReps, PR_FP64,
+                       nullptr, ranks, nullptr, workspace, region, &r);
+          if (rc < 0) break;
+          const double us = mean_us(PR_KERNEL_UPDATE_F64);
+          ++count_s;
+          if (pm == kPairMidDeg && sg == res && mx == 0) dflt_s = us;
+          if (us < best_s) {
+            best_s = us;
+            best_st = SegTune{pm, (int32_t)sg, mx};
+          }
+        }
+        if (rc < 0) break;
+      }
+      if (rc < 0) break;
+    }
+  }
   restore();
   if (rc < 0) return rc;
   // the chosen windows stay in the prep buffer; the thresholds and grids go to the table
   rc = prepare_parts(ctx, s, in_offsets, N, E, pp, best_tile, best_tile_b, &h, &h);
   if (rc != PR_OK) return rc;
+  if (h.seg_len > 0) {
+    const std::vector<int64_t> ssig = seg_signature(h);
+    ctx->tuned_seg[ssig] = best_st;
+    save_tune_seg_entry(ctx, ssig, best_st);
+  }
   const std::vector<int64_t> sig = graph_signature(h);
   ctx->tuned[sig] = {best_mid, best_grid};
   ctx->tuned_batch[sig] = {best_mid_b, best_gm};
@@ -390,6 +444,12 @@ int pr_autotune(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int3
   out->default_us = dflt;
   out->best_batch_us = best_b;
   out->default_batch_us = dflt_b;
+  out->pair_mid_deg = h.seg_len > 0 ? best_st.pair_mid_deg : 0;
+  out->seg_grid = h.seg_len > 0 ? best_st.seg_grid : 0;
+  out->merge_xcd = h.seg_len > 0 ? best_st.merge_xcd : 0;
+  out->seg_candidates = count_s;
+  out->best_seg_us = best_s;
+  out->default_seg_us = dflt_s;
   return PR_OK;
 }
 

@@ -42,14 +42,24 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
   p.pdesc = (const int4 *)(base + h.sl.pair_part.desc_off);
   p.npdesc = h.sl.pair_part.ndesc;
   p.partial = base + h.sl.part_off;
-  // the update kernel's resident count (7 workgroups per CU in float64): measured faster than
-  // the per-segment step's own full occupancy of 8, whose extra tiles in flight crowd the
-  // segment's slice in L2 (R-MAT scale 24: 1.77 against 1.81 ms per update)
-  const int64_t sg = ctx->seg_grid > 0 ? ctx->seg_grid : ctx->resident[fp32 ? 1 : 0];
+  // explicit options first, then the autotuner's table, then the defaults
+  int64_t pair_mid = ctx->pair_mid_deg, seg_grid = ctx->seg_grid, merge_xcd = ctx->merge_xcd;
+  if (ctx->use_tuned) {
+    auto it = ctx->tuned_seg.find(seg_signature(h));
+    if (it != ctx->tuned_seg.end()) {
+      if (!ctx->pair_mid_deg_set) pair_mid = it->second.pair_mid_deg;
+      if (!ctx->seg_grid_set) seg_grid = it->second.seg_grid;
+      if (!ctx->merge_xcd_set) merge_xcd = it->second.merge_xcd;
+    }
+  }
+  // by default the update kernel's resident count (7 workgroups per CU in float64): measured
+  // faster than the per-segment step's own full occupancy of 8, whose extra tiles in flight
+  // crowd the segment's slice in L2 (R-MAT scale 24: 1.77 against 1.81 ms per update)
+  const int64_t sg = seg_grid > 0 ? seg_grid : ctx->resident[fp32 ? 1 : 0];
   p.pgrid = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)p.npdesc, sg, kMaxGrid}));
   p.seg_xcd = (int32_t)ctx->seg_xcd;
-  p.merge_xcd = (int32_t)ctx->merge_xcd;
-  p.pair_mid_deg = (int32_t)ctx->pair_mid_deg;
+  p.merge_xcd = (int32_t)merge_xcd;
+  p.pair_mid_deg = (int32_t)pair_mid;
 }
 
 // pr_pull after its NULL checks (also the body of the entry point that allocates nothing).

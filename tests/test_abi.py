@@ -79,3 +79,33 @@ def test_every_option_key_is_documented():
     accepted = set(re.findall(r'strcmp\(key, "([a-z_0-9]+)"\)', code))
     documented = set(re.findall(r'^ \*   "([a-z_0-9]+)"', header, flags=re.M))
     assert accepted and accepted == documented, (sorted(accepted - documented), sorted(documented - accepted))
+
+
+def test_struct_mirrors_match_the_header(tmp_path):
+    # every ctypes mirror of a header struct has the header's size and field offsets, compiled
+    # from include/prpull.h by the host C compiler
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    mirrors = [_lib.pr_result, _lib.pr_problem, _lib.pr_graph_problem, _lib.pr_tune_result]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "prpull.h"', "int main(void) {"]
+    for m in mirrors:
+        name = m.__name__
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in m._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([cc, "-I", os.path.join(root, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for m in mirrors:
+        name = m.__name__
+        assert int(got[name]) == ctypes.sizeof(m), name
+        for f, _ in m._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(m, f).offset, (name, f)

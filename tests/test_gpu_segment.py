@@ -292,3 +292,48 @@ def test_scale22_fp64_against_oracle(pr, ctx):
     ref = check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, 1, 500,
                             gpu_trace=res["trace"].cpu().numpy())
     print("scale 22 segmented: %d updates (oracle %d)" % (res["iterations"], ref["iterations"]), flush=True)
+
+
+def test_autotune_segmented_layout(pr, tmp_path):
+    # with the segmented layout in the prep buffer the autotuner also times the segmented update
+    # (pair threshold x per-segment grid x merge tile order), keeps its choice for the graph and
+    # writes it to the tune file; solves on the tuned settings keep oracle parity
+    import os
+    tune = tmp_path / "tune.txt"
+    os.environ["PRPULL_TUNE_FILE"] = str(tune)
+    try:
+        c = pr.Context(0)
+    finally:
+        del os.environ["PRPULL_TUNE_FILE"]
+    try:
+        g = gg.rmat(15, seed=41)
+        dg = segmented(pr, c, g, 2048)
+        t = dg.autotune(c)
+        assert t["seg_candidates"] == 16
+        assert t["pair_mid_deg"] in (64, 128, 256, 512) and t["seg_grid"] > 0 and t["merge_xcd"] in (0, 1)
+        assert 0.0 < t["best_seg_us"] <= t["default_seg_us"]
+        seg_lines = [ln.split() for ln in tune.read_text().splitlines() if ln.startswith("seg ")]
+        assert len(seg_lines) == 1 and seg_lines[0][9] == "2048"
+        assert [int(x) for x in seg_lines[0][10:]] == [t["pair_mid_deg"], t["seg_grid"], t["merge_xcd"]]
+        for norm in (1, 3):
+            res = pr.pull(c, dg, alpha=0.85, tau=1e-10, norm=norm, trace=True)
+            check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, norm,
+                              500, gpu_trace=res["trace"].cpu().numpy())
+        # a context reading the file solves the same way
+        os.environ["PRPULL_TUNE_FILE"] = str(tune)
+        try:
+            c2 = pr.Context(0)
+        finally:
+            del os.environ["PRPULL_TUNE_FILE"]
+        try:
+            a = pr.pull(c, dg, alpha=0.85, tau=0.0, norm=1, max_iter=20)
+            b = pr.pull(c2, dg, alpha=0.85, tau=0.0, norm=1, max_iter=20)
+            assert torch.equal(a["ranks"], b["ranks"])
+        finally:
+            c2.close()
+        # a plain prep has no segmented stage
+        dp = pr.DeviceGraph.from_host(g).prepare(c)
+        t2 = dp.autotune(c)
+        assert t2["seg_candidates"] == 0 and t2["pair_mid_deg"] == 0 and t2["best_seg_us"] == 0.0
+    finally:
+        c.close()
