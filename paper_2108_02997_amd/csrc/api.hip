@@ -125,7 +125,8 @@ int write_prep_header(pr_ctx *ctx, hipStream_t s, void *prep, const PrepHeader &
   return PR_OK;
 }
 
-// Key bits of the segment sort: enough for every segment id of N sources (at least 1).
+// Key bits of the segment sort: enough for every segment id of N sources (at least 1); with
+// seg_len 1, for every source id.
 int seg_key_bits(int64_t N, int32_t seg_len) {
   const int64_t S = (N - 1) / seg_len + 1;
   int k = 1;
@@ -136,9 +137,10 @@ int seg_key_bits(int64_t N, int32_t seg_len) {
 // Layout of the source-segmented part of a prep buffer with P pairs, after the plain prep;
 // false when a hipCUB size query fails.
 bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl) {
-  size_t sort_b = 0, scan_e = 0, scan_p = 0;
+  size_t sort_b = 0, scan_e = 0, scan_p = 0, tile_b = 0;
   if (seg_sort_temp_bytes(P, seg_key_bits(N, seg_len), &sort_b) != hipSuccess ||
-      seg_scan_temp_bytes(E + 1, &scan_e) != hipSuccess || seg_scan_temp_bytes(P + 1, &scan_p) != hipSuccess)
+      seg_scan_temp_bytes(E + 1, &scan_e) != hipSuccess || seg_scan_temp_bytes(P + 1, &scan_p) != hipSuccess ||
+      seg_tile_sort_temp_bytes(E, max_desc(P, E, kTile, kRows), seg_key_bits(N, 1), &tile_b) != hipSuccess)
     return false;
   SegLayout L{};
   L.pairs = P;
@@ -163,11 +165,18 @@ bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl)
   L.merge_part.hub_off = take((size_t)max_hubs(N, P) * sizeof(int4));
   L.scan_off = take((size_t)(scan_block_count(std::max<int64_t>(N, P)) + 1) * 2 * sizeof(unsigned long long));
   L.temp_off = take(4 * (size_t)(E + 1));
+  const size_t tail = o;
   take(4 * (size_t)(P + 1));
   take(4 * (size_t)(P + 1));
   take(4 * (size_t)P);
   // hipCUB's storage; first the pair count's block sums
   L.cub_off = take(std::max({sort_b, scan_e, scan_p, (size_t)(seg_count_blocks() + 1) * sizeof(unsigned long long)}));
+  // the tiles' sort runs after the build and reuses the scratch behind temp
+  const size_t tiles = (size_t)max_desc(P, E, kTile, kRows);
+  const size_t tsort = seg_tile_sort_scratch(E, (int64_t)tiles, tile_b);
+  L.tsort_off = (int64_t)tail;
+  o = std::max(o, tail + tsort);
+  L.tsort_bytes = (int64_t)(o - tail);
   L.total = (int64_t)o;
   *sl = L;
   return true;
@@ -801,6 +810,8 @@ int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, c
     set_error("internal: a pair longer than one tile window");
     return PR_EDEVICE;
   }
+  PR_HIP(launch_seg_tile_sort(s, (int4 *)(base + sl.pair_part.desc_off), sl.pair_part.ndesc, (int32_t)E,
+                              seg_key_bits(N, 1), base, sl));
   h.seg_len = seg_len;
   h.sl = sl;
   return write_prep_header(ctx, s, prep, h);

@@ -96,7 +96,9 @@ __device__ __forceinline__ double block_max_n(double v, double *lds) {
 // step of the source-segmented update it is the array of per-segment partial sums, idx listing a
 // row's partial sums in segment order.  yin (the row's own current value) and yout serve the
 // epilogue.  With Part = true a row's sum is stored as it is into part[row] (the per-segment
-// step of the source-segmented update: rows are then (segment, row) pairs, no epilogue).
+// step of the source-segmented update: rows are then (segment, row) pairs, no epilogue; a tile's
+// indices may come in source order, packed with the pair-order position each gathered value is
+// staged at, so every pair is summed in its own order).
 template <typename VT>
 struct TileCtx {
   const int32_t *off;
@@ -128,11 +130,20 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
     // One round trip for the index stream and the rows' own data, one for the gather.
     const int32_t v0 = d.x, v1 = dn.x;
     const int32_t n = e1 - e0;
-    int32_t u[kPer];
+    // Part: a tile with d.w >= 0 lists its entries in source order, each word packing the
+    // source less d.w and the entry's pair-order position (where its value is staged)
+    const int32_t base = Part ? d.w : -1;
+    int32_t u[kPer], pk[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int j = t + k * kBlock;
       u[k] = j < n ? __builtin_nontemporal_load(idx + e0 + j) : -1;
+      pk[k] = j;
+      if (Part && base >= 0 && j < n) {
+        const uint32_t w = (uint32_t)u[k];
+        u[k] = base + (int32_t)(w >> kPosBits);
+        pk[k] = (int32_t)(w & ((1u << kPosBits) - 1));
+      }
     }
     int32_t ra[kRowsPerLane], rb[kRowsPerLane], dv[kRowsPerLane];
     VT yo[kRowsPerLane];
@@ -157,7 +168,7 @@ __device__ __forceinline__ void update_tile(const TileCtx<VT> &c, const int4 d, 
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int j = t + k * kBlock;
-      if (j < n) vals[j] = x[k];
+      if (j < n) vals[pk[k]] = x[k];
     }
     __syncthreads();
 #pragma unroll

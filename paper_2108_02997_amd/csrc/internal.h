@@ -91,8 +91,18 @@ struct SegLayout {
   int64_t total;     // bytes of the whole buffer
   PrepPart pair_part;   // tiles over the pair CSR (no long rows)
   PrepPart merge_part;  // tiles over the merge CSR
+  int64_t tsort_off;    // construction scratch of the tiles' sort (tile offsets, positions, hipCUB)
+  int64_t tsort_bytes;
 };
+// Within a tile of the pair partition whose sources span fewer than 2^kRelBits ids, the entries
+// are sorted by source and each sidx word packs (source - base) << kPosBits | position, position
+// being the entry's place in the tile's pair order and base (the tile's smallest source) sitting
+// in the tile descriptor's w; other tiles keep plain sources in pair order and w = -1.  The
+// per-segment step then gathers in source order (neighbouring lanes share cache lines) and stages
+// each value at its pair-order position, so every pair is still summed in its own order.
 constexpr int32_t kPairMax = kTile;
+constexpr int kPosBits = 11;
+constexpr int kRelBits = 32 - kPosBits;
 constexpr int32_t kMinSegLen = 256;
 
 struct PrepHeader {
@@ -108,7 +118,7 @@ struct PrepHeader {
   SegLayout sl;
 };
 constexpr int32_t kPrepMagic = 0x50525032;  // "PRP2"
-constexpr int32_t kPrepVersion = 3;
+constexpr int32_t kPrepVersion = 4;
 
 size_t prep_bytes(int64_t N, int64_t E);
 int64_t max_desc(int64_t N, int64_t E, int tile, int rows);
@@ -224,6 +234,11 @@ hipError_t launch_seg_count(hipStream_t s, const int32_t *off, const int32_t *id
                             int32_t seg_len, unsigned long long *block_counts, unsigned long long *host_total);
 hipError_t seg_sort_temp_bytes(int64_t P, int key_bits, size_t *bytes);
 hipError_t seg_scan_temp_bytes(int64_t n, size_t *bytes);
+// Sort the entries of every pair tile by source and pack them with their pair-order positions.
+hipError_t seg_tile_sort_temp_bytes(int64_t E, int64_t tiles, int key_bits, size_t *bytes);
+size_t seg_tile_sort_scratch(int64_t E, int64_t tiles, size_t sort_bytes);
+hipError_t launch_seg_tile_sort(hipStream_t s, int4 *pdesc, int32_t ndesc, int32_t E, int key_bits, char *base,
+                                const SegLayout &sl);
 hipError_t launch_seg_build(hipStream_t s, const int32_t *off, const int32_t *idx, int32_t N, int32_t E,
                             int32_t seg_len, int key_bits, int64_t P, char *base, const SegLayout &sl);
 

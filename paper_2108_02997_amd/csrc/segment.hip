@@ -19,6 +19,8 @@
 //   3. a stable radix sort of the pairs by segment (hipCUB) gives perm[p] = q, the row-order
 //      pair at segment-major position p; mpos[q] = p; pair lengths in segment-major order;
 //   4. poff = exclusive scan of the lengths; every entry is copied to its place in sidx.
+#include <algorithm>
+
 #include <hipcub/hipcub.hpp>
 
 #include "internal.h"
@@ -162,6 +164,91 @@ hipError_t seg_scan_temp_bytes(int64_t n, size_t *bytes) {
   *bytes = 0;
   return hipcub::DeviceScan::ExclusiveSum(nullptr, *bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
                                           (int)(n > 0 ? n : 1), (hipStream_t)0);
+}
+
+// ---- tile order (after the pair partition is built): every pair tile's entries sorted by source
+// (hipCUB's segmented radix sort over the tiles, carrying each entry's pair-order position), then
+// packed: a tile whose sources span fewer than 2^kRelBits ids keeps, per entry, the source less
+// the tile's smallest source (high bits) and the entry's pair-order position (low kPosBits bits),
+// and its descriptor's w holds that smallest source; any other tile keeps its pair order, w = -1.
+static_assert(kSpan <= (1 << kPosBits), "tile positions fit the packed word");
+
+__global__ __launch_bounds__(kBlock) void k_tile_offsets(const int4 *__restrict__ pdesc, int32_t ndesc,
+                                                         int32_t *__restrict__ toff) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= ndesc; i += (int64_t)gridDim.x * kBlock)
+    toff[i] = pdesc[i].y;
+}
+
+// Pair-order position of every entry within its tile (one workgroup per tile; tiles hold fewer
+// than kSpan entries).
+__global__ __launch_bounds__(kBlock) void k_tile_positions(const int32_t *__restrict__ toff, int32_t ndesc,
+                                                           uint16_t *__restrict__ pos) {
+  for (int32_t i = blockIdx.x; i < ndesc; i += gridDim.x) {
+    const int32_t e0 = toff[i], e1 = toff[i + 1];
+    for (int32_t j = e0 + threadIdx.x; j < e1; j += kBlock) pos[j] = (uint16_t)(j - e0);
+  }
+}
+
+// keys / pos: the tiles sorted by source with their positions; writes sidx and pdesc[i].w.
+__global__ __launch_bounds__(kBlock) void k_tile_pack(const int32_t *__restrict__ toff, int32_t ndesc,
+                                                      const int32_t *__restrict__ keys,
+                                                      const uint16_t *__restrict__ pos, int32_t *__restrict__ sidx,
+                                                      int4 *__restrict__ pdesc) {
+  for (int32_t i = blockIdx.x; i < ndesc; i += gridDim.x) {
+    const int32_t e0 = toff[i], e1 = toff[i + 1];
+    if (e1 <= e0) {
+      if (threadIdx.x == 0) pdesc[i].w = -1;
+      continue;
+    }
+    const int32_t lo = keys[e0];
+    const bool packed = keys[e1 - 1] - lo < (1 << kRelBits);
+    for (int32_t j = e0 + threadIdx.x; j < e1; j += kBlock) {
+      if (packed)
+        sidx[j] = (int32_t)(((uint32_t)(keys[j] - lo) << kPosBits) | (uint32_t)pos[j]);
+      else
+        sidx[e0 + pos[j]] = keys[j];
+    }
+    if (threadIdx.x == 0) pdesc[i].w = packed ? lo : -1;
+  }
+}
+
+hipError_t seg_tile_sort_temp_bytes(int64_t E, int64_t tiles, int key_bits, size_t *bytes) {
+  *bytes = 0;
+  return hipcub::DeviceSegmentedRadixSort::SortPairs(
+      nullptr, *bytes, (const int32_t *)nullptr, (int32_t *)nullptr, (const uint16_t *)nullptr, (uint16_t *)nullptr,
+      (int)(E > 0 ? E : 1), (int)(tiles > 0 ? tiles : 1), (const int32_t *)nullptr, (const int32_t *)nullptr, 0,
+      key_bits, (hipStream_t)0);
+}
+
+size_t seg_tile_sort_scratch(int64_t E, int64_t tiles, size_t sort_bytes) {
+  return align_up(4 * (size_t)(tiles + 1), 256) + 2 * align_up(2 * (size_t)E, 256) + align_up(sort_bytes, 256);
+}
+
+// The sorted keys pass through the construction scratch temp (E + 1 values); tile offsets,
+// positions and the sort's storage sit in the scratch at sl.tsort_off.
+hipError_t launch_seg_tile_sort(hipStream_t s, int4 *pdesc, int32_t ndesc, int32_t E, int key_bits, char *base,
+                                const SegLayout &sl) {
+  int32_t *sidx = (int32_t *)(base + sl.sidx_off);
+  int32_t *keys = (int32_t *)(base + sl.temp_off);
+  char *t = base + sl.tsort_off;
+  int32_t *toff = (int32_t *)t;
+  t += align_up(4 * (size_t)(ndesc + 1), 256);
+  uint16_t *pos_in = (uint16_t *)t;
+  t += align_up(2 * (size_t)E, 256);
+  uint16_t *pos = (uint16_t *)t;
+  t += align_up(2 * (size_t)E, 256);
+  size_t bytes = 0;
+  hipError_t e = seg_tile_sort_temp_bytes(E, ndesc, key_bits, &bytes);
+  if (e != hipSuccess) return e;
+  if ((int64_t)(t - base) + (int64_t)bytes > sl.tsort_off + sl.tsort_bytes) return hipErrorInvalidValue;
+  const unsigned tiles_grid = (unsigned)std::min<int32_t>(std::max<int32_t>(ndesc, 1), 16384);
+  hipLaunchKernelGGL(k_tile_offsets, dim3(grid_n((int64_t)ndesc + 1)), dim3(kBlock), 0, s, pdesc, ndesc, toff);
+  hipLaunchKernelGGL(k_tile_positions, dim3(tiles_grid), dim3(kBlock), 0, s, toff, ndesc, pos_in);
+  e = hipcub::DeviceSegmentedRadixSort::SortPairs((void *)t, bytes, sidx, keys, pos_in, pos, (int)E, (int)ndesc, toff,
+                                                  toff + 1, 0, key_bits, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_pack, dim3(tiles_grid), dim3(kBlock), 0, s, toff, ndesc, keys, pos, sidx, pdesc);
+  return hipGetLastError();
 }
 
 // The whole build into the buffer at `base` (layout sl, sizes checked by the caller; P > 0).

@@ -48,7 +48,8 @@ class PrepPart(ctypes.Structure):
 class SegLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("pairs", "poff_off", "moff_off", "mpos_off", "sidx_off", "part_off",
                                               "scan_off", "temp_off", "cub_off", "total")] + \
-               [("pair_part", PrepPart), ("merge_part", PrepPart)]
+               [("pair_part", PrepPart), ("merge_part", PrepPart), ("tsort_off", ctypes.c_int64),
+                ("tsort_bytes", ctypes.c_int64)]
 
 
 class PrepHeader(ctypes.Structure):
@@ -100,6 +101,31 @@ def read_layout(dg):
     return h, P, arr(sl.poff_off, P + 1), arr(sl.sidx_off, dg.E), arr(sl.moff_off, dg.N + 1), arr(sl.mpos_off, P)
 
 
+POS_BITS = 11
+
+
+def read_tiles(dg):
+    """The pair partition's tiles: entry starts (ndesc + 1 of them), each tile's base (descriptor w,
+    -1 for a tile in pair order) and the raw index words."""
+    raw = dg.prep.cpu().numpy()
+    h = PrepHeader.from_buffer_copy(raw[:ctypes.sizeof(PrepHeader)].tobytes())
+    sl = h.sl
+    nd = sl.pair_part.ndesc
+    desc = raw[sl.pair_part.desc_off:sl.pair_part.desc_off + 16 * (nd + 1)].view(np.int32).reshape(nd + 1, 4)
+    words = raw[sl.sidx_off:sl.sidx_off + 4 * dg.E].view(np.uint32).astype(np.int64)
+    return desc[:, 1].astype(np.int64), desc[:nd, 3].astype(np.int64), words
+
+
+def unpack_tiles(starts, base, words):
+    """Per entry: its tile, its source and its position in the tile's pair order."""
+    tile = np.repeat(np.arange(starts.size - 1), np.diff(starts))
+    b = base[tile]
+    packed = b >= 0
+    src = np.where(packed, b + (words >> POS_BITS), words)
+    pos = np.where(packed, words & ((1 << POS_BITS) - 1), np.arange(words.size) - starts[tile])
+    return tile, src, pos
+
+
 def segmented(pr, ctx, g, seg_len):
     dg = pr.DeviceGraph.from_host(g)
     dg.prepare_segmented(ctx, seg_len=seg_len)
@@ -129,15 +155,49 @@ GRAPHS = {
                                           ("hubs", 4096)])
 def test_layout_matches_definition(pr, ctx, name, seg_len):
     g = GRAPHS[name]()
-    dg = segmented(pr, ctx, g, seg_len)
+    check_layout(g, segmented(pr, ctx, g, seg_len), seg_len)
+
+
+def check_layout(g, dg, seg_len):
+    """The prep buffer's segmented layout against its definition; returns the tiles' bases."""
     P, poff, sidx, moff, mpos = expected_layout(g, seg_len)
     h, Pd, poff_d, sidx_d, moff_d, mpos_d = read_layout(dg)
     assert h.seg_len == seg_len and Pd == P == dg.seg_pairs
     np.testing.assert_array_equal(poff_d, poff)
-    np.testing.assert_array_equal(sidx_d, sidx)
     np.testing.assert_array_equal(moff_d, moff)
     np.testing.assert_array_equal(mpos_d, mpos)
     assert h.sl.pair_part.nhubs == 0 and int(np.diff(poff).max()) <= PAIR_MAX
+    # a tile whose sources span fewer than 2^21 ids lists them in source order (ties in pair order),
+    # each word packing the source less the tile's smallest one (descriptor w) and the entry's
+    # pair-order position; any other tile holds the definition's entries as they are
+    starts, base, words = read_tiles(dg)
+    assert starts[0] == 0 and starts[-1] == g.E and np.all(np.diff(starts) > 0)
+    assert np.all(np.diff(starts) < 1 << POS_BITS)           # a tile's positions fit the word
+    tile, src, pos = unpack_tiles(starts, base, words)
+    np.testing.assert_array_equal(src, sidx[starts[tile] + pos])
+    np.testing.assert_array_equal(np.sort(starts[tile] + pos), np.arange(g.E))   # positions: a permutation
+    first = starts[:-1]
+    span = np.maximum.reduceat(sidx, first) - np.minimum.reduceat(sidx, first)
+    np.testing.assert_array_equal(base >= 0, span < 1 << (32 - POS_BITS))
+    np.testing.assert_array_equal(base[base >= 0], np.minimum.reduceat(sidx, first)[base >= 0])
+    sorted_tiles = (base >= 0)[tile]
+    order = np.lexsort((pos, src, tile))                     # tile, then source, then position
+    np.testing.assert_array_equal(order[sorted_tiles[order]], np.flatnonzero(sorted_tiles))
+    return base
+
+
+def test_wide_tiles_stay_in_pair_order(pr, ctx):
+    # 3M vertices, 2^21-id segments: tiles within a segment are packed in source order, tiles
+    # that straddle the boundary may span 2^21 ids or more and keep their pair order; both kinds
+    # are summed exactly as the oracle's rows
+    g = gg.er(3_000_000, 2.0, seed=13)
+    dg = segmented(pr, ctx, g, 1 << 21)
+    base = check_layout(g, dg, 1 << 21)
+    print("tiles %d, in pair order %d" % (base.size, int((base < 0).sum())), flush=True)
+    assert (base >= 0).any() and (base < 0).any()
+    res = pr.pull(ctx, dg, alpha=0.85, tau=1e-10, norm=1, max_iter=500, trace=True)
+    check_fp64_result(g, res["ranks"].cpu().numpy(), res["iterations"], res["converged"], 0.85, 1e-10, 1, 500,
+                      gpu_trace=res["trace"].cpu().numpy())
 
 
 @pytest.mark.parametrize("name,seg_len", [("rmat13", 256), ("rmat13", 2048), ("rmat13", 1500), ("er_c1", 1024),
