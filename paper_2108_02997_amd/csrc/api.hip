@@ -140,7 +140,7 @@ bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl)
   size_t sort_b = 0, scan_e = 0, scan_p = 0, tile_b = 0;
   if (seg_sort_temp_bytes(P, seg_key_bits(N, seg_len), &sort_b) != hipSuccess ||
       seg_scan_temp_bytes(E + 1, &scan_e) != hipSuccess || seg_scan_temp_bytes(P + 1, &scan_p) != hipSuccess ||
-      seg_tile_sort_temp_bytes(E, max_desc(P, E, kTile, kRows), seg_key_bits(N, 1), &tile_b) != hipSuccess)
+      seg_tile_sort_temp_bytes(E, max_desc(P, E, kPairTile, kRows), seg_key_bits(N, 1), &tile_b) != hipSuccess)
     return false;
   SegLayout L{};
   L.pairs = P;
@@ -155,9 +155,9 @@ bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl)
   L.mpos_off = take(4 * (size_t)P);
   L.sidx_off = take(4 * (size_t)(E + 1));
   L.part_off = take(8 * (size_t)P);
-  L.pair_part.tile = kTile;
+  L.pair_part.tile = kPairTile;
   L.pair_part.rows = kRows;
-  L.pair_part.desc_off = take((size_t)(max_desc(P, E, kTile, kRows) + 1) * sizeof(int4));
+  L.pair_part.desc_off = take((size_t)(max_desc(P, E, kPairTile, kRows) + 1) * sizeof(int4));
   L.pair_part.hub_off = take((size_t)max_hubs(P, E) * sizeof(int4));
   L.merge_part.tile = kTile;
   L.merge_part.rows = kRows;
@@ -172,7 +172,7 @@ bool seg_layout(int64_t N, int64_t E, int32_t seg_len, int64_t P, SegLayout *sl)
   // hipCUB's storage; first the pair count's block sums
   L.cub_off = take(std::max({sort_b, scan_e, scan_p, (size_t)(seg_count_blocks() + 1) * sizeof(unsigned long long)}));
   // the tiles' sort runs after the build and reuses the scratch behind temp
-  const size_t tiles = (size_t)max_desc(P, E, kTile, kRows);
+  const size_t tiles = (size_t)max_desc(P, E, kPairTile, kRows);
   const size_t tsort = seg_tile_sort_scratch(E, (int64_t)tiles, tile_b);
   L.tsort_off = (int64_t)tail;
   o = std::max(o, tail + tsort);
@@ -794,12 +794,12 @@ int pr_prepare_segmented(pr_ctx *ctx, void *stream, const int32_t *in_offsets, c
                 {&sl.merge_part, (const int32_t *)(base + sl.moff_off), N, pairs}};
   for (auto &q : parts) {
     PrepPart &pp = *q.pp;
-    PR_HIP(launch_prepare(s, kTile, kRows, q.off, q.rows, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
+    PR_HIP(launch_prepare(s, pp.tile, pp.rows, q.off, q.rows, (int4 *)(base + pp.desc_off), (int4 *)(base + pp.hub_off),
                           base + sl.scan_off, ctx->hscratch));
     pp.ndesc = (int32_t)ctx->hscratch[0];
     pp.nslots = (int32_t)(ctx->hscratch[1] >> 32);
     pp.nhubs = (int32_t)(ctx->hscratch[1] & 0xffffffffull);
-    if (pp.ndesc < 1 || pp.ndesc > max_desc(q.rows, q.entries, kTile, kRows) ||
+    if (pp.ndesc < 1 || pp.ndesc > max_desc(q.rows, q.entries, pp.tile, pp.rows) ||
         pp.nslots > max_slots(q.rows, q.entries) || pp.nhubs > max_hubs(q.rows, q.entries)) {
       set_error("internal: segmented tile partition out of bounds (ndesc %d, slots %d, hubs %d)", pp.ndesc, pp.nslots,
                 pp.nhubs);

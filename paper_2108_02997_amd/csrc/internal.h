@@ -101,6 +101,11 @@ struct SegLayout {
 // per-segment step then gathers in source order (neighbouring lanes share cache lines) and stages
 // each value at its pair-order position, so every pair is still summed in its own order.
 constexpr int32_t kPairMax = kTile;
+// Tile window of the pair partition (entries).  Pairs are never long rows (kPairMax <= kPairTile),
+// and a tile ends with a pair that starts inside its window, so it holds fewer than
+// kPairTile + kPairMax entries: at most kSpan, the per-segment step's staging.
+constexpr int kPairTile = kTile;
+static_assert(kPairMax <= kPairTile && kPairTile + kPairMax <= kSpan, "pair tiles fit the staging");
 constexpr int kPosBits = 11;
 constexpr int kRelBits = 32 - kPosBits;
 constexpr int32_t kMinSegLen = 256;

@@ -202,6 +202,8 @@ hipError_t launch_prepare(hipStream_t s, int tile, int rows, const int32_t *off,
     e = prepare_part<256, 128>(s, off, N, desc, hubs, bsum);
   else if (tile == 128 && rows == 64)
     e = prepare_part<128, 64>(s, off, N, desc, hubs, bsum);
+  else if (tile == kPairTile && rows == kRows)  // the pair partition of the segmented layout
+    e = prepare_part<kPairTile, kRows>(s, off, N, desc, hubs, bsum);
   else
     return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
