@@ -178,7 +178,9 @@ int pr_prepare(pr_ctx *ctx, void *stream, const int32_t *in_offsets, int64_t N, 
  * the row.  pr_pull, given a prep buffer written by pr_prepare_segmented (and option "segmented"
  * at its default 1), runs each update as a per-segment step over the pairs listed segment by
  * segment, writing one partial sum per pair, then a merge step that sums every row's partials
- * in segment order and applies the update's epilogue.  Needs E <= 2^31 - 2.
+ * in segment order and applies the update's epilogue.  Within a work tile of pairs the entries
+ * are gathered in source order; every pair is still summed in its own entry order.  Needs
+ * E <= 2^31 - 2.
  *
  * pr_segment_count: the number of pairs of the graph at seg_len, into *pairs (host).  Reads
  * in_offsets and in_indices (device); workspace: device, >= 8200 bytes.  Synchronises the stream.

@@ -143,16 +143,27 @@ def hub_graph(N=6000, seed=4):
     return gg.from_edges(N, src, dst)
 
 
+def multi_graph(N=4000, seed=6):
+    # every row draws 20 sources, with replacement, from a pool of 600: duplicate edges, so equal
+    # sources within rows and within tiles (their order in a source-ordered tile is pair order);
+    # vertices outside the pool are dangling
+    rng = np.random.default_rng(seed)
+    dst = np.repeat(np.arange(N), 20)
+    src = rng.integers(0, 600, dst.size)
+    return gg.from_edges(N, src, dst, dedupe=False, drop_self_loops=False)
+
+
 GRAPHS = {
     "rmat13": lambda: gg.rmat(13, seed=31),
     "er_c1": gg.workload_c1,
     "hubs": hub_graph,
+    "multi": multi_graph,
 }
 
 
 @pytest.mark.parametrize("name,seg_len", [("rmat13", 256), ("rmat13", 1024), ("rmat13", 3 * 1024 + 7),
                                           ("rmat13", 8192), ("er_c1", 512), ("er_c1", 3000), ("hubs", 256),
-                                          ("hubs", 4096)])
+                                          ("hubs", 4096), ("multi", 256), ("multi", 300)])
 def test_layout_matches_definition(pr, ctx, name, seg_len):
     g = GRAPHS[name]()
     check_layout(g, segmented(pr, ctx, g, seg_len), seg_len)
@@ -201,7 +212,7 @@ def test_wide_tiles_stay_in_pair_order(pr, ctx):
 
 
 @pytest.mark.parametrize("name,seg_len", [("rmat13", 256), ("rmat13", 2048), ("rmat13", 1500), ("er_c1", 1024),
-                                          ("hubs", 512)])
+                                          ("hubs", 512), ("multi", 256)])
 def test_fp64_parity_every_norm(pr, ctx, name, seg_len):
     g = GRAPHS[name]()
     dg = segmented(pr, ctx, g, seg_len)
