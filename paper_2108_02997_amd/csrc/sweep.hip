@@ -60,15 +60,17 @@ __global__ __launch_bounds__(kFoldBlock) void k_sweep_coef(const SweepCols *__re
   }
 }
 
-// ranks_k[x] += sum_i c_k(j0 + i) r_i[x] over the slots i < n (ascending i), r_i[x] = y_i[x] d_x
-// (y_i[x] for a dangling x), for every column k still collecting at these steps; the first fold
-// (j0 = 0, every column collecting) writes ranks_k[x] = that sum instead.
-// (register budget capped for 5 waves per SIMD: the 33 slot values per lane otherwise take 110
-// VGPRs, 4 waves)
-__global__ __launch_bounds__(kFoldBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_sweep_fold(
-    const double *__restrict__ slots, int64_t stride, int32_t first, int32_t n, int32_t j0,
-    const int32_t *__restrict__ outdeg, int32_t N, const FoldTable *__restrict__ ft) {
-#pragma clang fp contract(off)
+// ranks_k[x] += d_x * sum_i c_k(j0 + i) y_i[x] over the slots i < n (fused multiply-adds in
+// ascending i; r_i[x] = y_i[x] d_x, d_x = 1 for a dangling x), for every column k still
+// collecting at these steps; the first fold (j0 = 0, every column collecting) writes ranks_k[x] =
+// that sum instead.  Eleven columns of 26 iterates are 286 multiply-adds per vertex: with
+// separate multiplies and adds (and the degree applied to every iterate) the fold was bound by
+// its arithmetic at 2.7 TB/s; as written it streams at about the copy rate.  The column stores
+// are nontemporal (nothing reads them in this pass).
+__global__ __launch_bounds__(kFoldBlock) void k_sweep_fold(const double *__restrict__ slots, int64_t stride,
+                                                           int32_t first, int32_t n, int32_t j0,
+                                                           const int32_t *__restrict__ outdeg, int32_t N,
+                                                           const FoldTable *__restrict__ ft) {
   __shared__ double coef[kMaxSweepCols][kMaxFoldSlots];
   __shared__ double *outs[kMaxSweepCols];
   const int t = threadIdx.x;
@@ -82,17 +84,18 @@ __global__ __launch_bounds__(kFoldBlock) __attribute__((amdgpu_waves_per_eu(5, 8
   for (int64_t x = (int64_t)blockIdx.x * kFoldBlock + t; x < N; x += (int64_t)gridDim.x * kFoldBlock) {
     const int32_t dx = outdeg[x];
     const double scale = dx > 0 ? (double)dx : 1.0;
-    double r[kMaxFoldSlots];
+    double y[kMaxFoldSlots];
 #pragma unroll
     for (int i = 0; i < kMaxFoldSlots; ++i)
-      r[i] = i < n ? __builtin_nontemporal_load(slots + (int64_t)(first + i) * stride + x) * scale : 0.0;
+      y[i] = i < n ? __builtin_nontemporal_load(slots + (int64_t)(first + i) * stride + x) : 0.0;
     for (int q = 0; q < m; ++q) {
       double *__restrict__ out = outs[q];
-      double acc = j0 == 0 ? 0.0 : out[x];
+      double sum = 0.0;
 #pragma unroll
       for (int i = 0; i < kMaxFoldSlots; ++i)
-        if (i < n) acc += coef[q][i] * r[i];
-      out[x] = acc;
+        if (i < n) sum = __builtin_fma(coef[q][i], y[i], sum);
+      const double acc = j0 == 0 ? sum * scale : out[x] + sum * scale;
+      __builtin_nontemporal_store(acc, &out[x]);
     }
   }
 }
