@@ -19,6 +19,8 @@
 //   3. a stable radix sort of the pairs by segment (hipCUB) gives perm[p] = q, the row-order
 //      pair at segment-major position p; mpos[q] = p; pair lengths in segment-major order;
 //   4. poff = exclusive scan of the lengths; every entry is copied to its place in sidx.
+// After the pair CSR's tile partition is built (api.hip), every pair tile's entries are sorted by
+// source and packed with their pair-order positions (launch_seg_tile_sort, below).
 #include <algorithm>
 
 #include <hipcub/hipcub.hpp>
