@@ -630,6 +630,23 @@ def run_tau(args, pr, gg, np, torch):
                          "mixed_ms": round(res[pr.PR_MIXED][0] * 1e3, 3),
                          "mixed_vs_fp64_l1": pr.l1_distance(ctx, m["ranks"], f["ranks"]),
                          "mixed_vs_fp64_linf": float((m["ranks"] - f["ranks"]).abs().max())})
+    # the same float64 readout from one solve: rank snapshots at every (tau, norm) pair as the
+    # solve to the last of them (1e-10 in L1) runs; each is the ranks of the separate solve
+    pairs = [(tau, norm) for norm in (pr.PR_L1, pr.PR_L2, pr.PR_LINF) for tau in gg.TAU_DECADES]
+
+    def snap_solve():
+        return pr.pull_snapshots(ctx, dg, pairs, alpha=0.85, tau=1e-10, norm=pr.PR_L1)
+    snap_solve()
+    ts, snap = timed(snap_solve, args.steps, "snapshots of %d (tau, norm) pairs" % len(pairs))
+    by_pair = {(r["tau"], r["norm"]): r["fp64_iterations"] for r in rows}
+    snapshots = {"pairs": len(pairs), "ms": round(float(np.mean(ts)) * 1e3, 3),
+                 "separate_fp64_solves_ms": round(total[pr.PR_FP64] * 1e3, 3),
+                 "speedup": round(total[pr.PR_FP64] / float(np.mean(ts)), 2), "solve_iterations": snap["iterations"],
+                 "iterations_as_separate_solves": all(snap["snap_iter"][i] == by_pair[q] for i, q in enumerate(pairs))}
+    one = pr.pull(ctx, dg, alpha=0.85, tau=1e-6, norm=pr.PR_L2)
+    snapshots["ranks_as_separate_solve_1e-6_L2"] = bool(torch.equal(snap["snapshots"][pairs.index((1e-6, pr.PR_L2))],
+                                                                    one["ranks"]))
+    del snap, one
     # sections 4-5 checks per arithmetic and norm, tolerances in decreasing order: the onset of the
     # sensitivity issue (an abrupt jump to max_iter) and the single-iteration stops.  The
     # float32-only ablation continues to tau = 1e-11 and 1e-12.
@@ -677,6 +694,7 @@ def run_tau(args, pr, gg, np, torch):
     line["readout"] = rows
     line["fp32_only_below_1e-10"] = extra
     line["iteration_checks"] = checks
+    line["snapshots"] = snapshots
     # locality of the plain update (no segmented layout): the same graph as generated, under a
     # seeded random relabelling (the stress case) and in out-degree order (hot sources
     # contiguous); update times of one float64 (L1) and one mixed (Linf) solve each, and the

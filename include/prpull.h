@@ -246,6 +246,27 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
             int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
             double *norm_trace, void *workspace, size_t workspace_bytes, pr_result *out);
 
+/* pr_pull with rank snapshots: the tolerance study of sections 3 and 4 (the ranks at each of a
+ * set of (tau, norm) stopping points) from one solve.  For each of the S pairs (snap_tau[i],
+ * snap_norm[i]) the ranks at the first update whose change meets snap_tau[i] in snap_norm[i]
+ * (the same test as the solve's own stop, so exactly the ranks pr_pull returns when given that
+ * tau and norm and the other arguments unchanged) are written to snaps[i * N .. i * N + N) as
+ * the solve runs, and that update's number to snap_iter[i].  The solve itself still stops at its
+ * own (tau, norm) or max_iter: a snapshot it stops before meeting gets snap_iter[i] = 0 and its
+ * row is left as it was, so give the solve the pair that is met last.
+ *   S         : 1 .. 64
+ *   snap_tau  : host, S values >= 0;   snap_norm: host, S values PR_L1, PR_L2 or PR_LINF
+ *   snaps     : device, S x N values, out
+ *   snap_iter : host, S values, out (filled when the call returns; it synchronises the stream)
+ *   precision : PR_FP64 or PR_FP32 (PR_MIXED changes precision along the way: PR_EINVAL)
+ * Other arguments, the workspace (pr_workspace_bytes), results and statuses as pr_pull.  An update
+ * that takes snapshots adds one pass over the iterate and one N-value store per snapshot taken. */
+int pr_pull_snapshots(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                      const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double alpha, double tau,
+                      int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
+                      double *norm_trace, int32_t S, const double *snap_tau, const int32_t *snap_norm,
+                      double *snaps, int32_t *snap_iter, void *workspace, size_t workspace_bytes, pr_result *out);
+
 /* For callers that cannot allocate device memory (serving loops, code that must not call
  * hipMalloc, harnesses that forbid allocation): pr_pull with prep = NULL whose workspace is a
  * fixed device array of the library (pr_noalloc_max_bytes() = 64 MiB per GPU, resolved at

@@ -192,6 +192,38 @@ def pr_pull(ctx: Context, g: DeviceGraph, alpha: float, tau: float, norm: int, m
     return st, res.as_dict()
 
 
+def pull_snapshots(ctx: Context, g: DeviceGraph, snaps, alpha: float = 0.85, tau: float = 1e-10,
+                   norm: int = PR_L1, max_iter: int = 500, precision: int = PR_FP64,
+                   init: torch.Tensor | None = None, trace: bool = False) -> dict:
+    """pr_pull_snapshots: one solve that also keeps the ranks at the first update meeting each
+    (tau_i, norm_i) of `snaps`; returns pull's dict plus snapshots (S x N float64; rows of
+    snapshots not taken are NaN) and snap_iter (0 where the solve stopped first)."""
+    if g.prep is None:
+        g.prepare(ctx)
+    dev = g.off.device
+    S = len(snaps)
+    if init is not None and (init.dtype != torch.float64 or init.numel() != g.N or not init.is_contiguous()):
+        raise ValueError("init must be a contiguous float64 tensor of N elements")
+    ranks = torch.empty(g.N, dtype=torch.float64, device=dev)
+    out = torch.full((max(S, 1), g.N), float("nan"), dtype=torch.float64, device=dev)
+    tr = torch.full((max_iter, 3), float("nan"), dtype=torch.float64, device=dev) if trace else None
+    stau = (ctypes.c_double * max(S, 1))(*[float(t) for t, _ in snaps])
+    snorm = (ctypes.c_int32 * max(S, 1))(*[int(n) for _, n in snaps])
+    siter = (ctypes.c_int32 * max(S, 1))()
+    ws = g.workspace(ctx, precision, False)
+    res = pr_result()
+    st = ctx.lib.pr_pull_snapshots(ctx.handle, ctx.stream, g.off.data_ptr(), _lib.ptr(g.idx) if g.E else None,
+                                   g.outdeg.data_ptr(), g.N, g.E, _lib.ptr(g.prep), float(alpha), float(tau),
+                                   int(norm), int(max_iter), int(precision), _lib.ptr(init), ranks.data_ptr(),
+                                   _lib.ptr(tr), S, stau, snorm, out.data_ptr(), siter, ws.data_ptr(), ws.numel(),
+                                   ctypes.byref(res))
+    _lib.check("pr_pull_snapshots", st)
+    d = res.as_dict()
+    d.update(status=st, ranks=ranks, trace=tr[:d["iterations"]] if trace else None, snapshots=out[:S],
+             snap_iter=[int(siter[i]) for i in range(S)])
+    return d
+
+
 def unpermute(ctx: Context, perm: torch.Tensor, ranks: torch.Tensor) -> torch.Tensor:
     """pr_unpermute: out[v] = ranks[perm[v]], ranks of a relabelled graph back in the original ids."""
     out = torch.empty_like(ranks)

@@ -93,6 +93,8 @@ SIGNATURES = {
     "pr_workspace_bytes": ([_i64, _i64, _i32, _i32], _sz),
     "pr_pull": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz,
                  ctypes.POINTER(pr_result)], ctypes.c_int),
+    "pr_pull_snapshots": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp,
+                           _i32, _vp, _vp, _vp, _vp, _vp, _sz, ctypes.POINTER(pr_result)], ctypes.c_int),
     "pr_noalloc_max_bytes": ([], _sz),
     "pr_pull_noalloc": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp,
                          ctypes.POINTER(pr_result)], ctypes.c_int),

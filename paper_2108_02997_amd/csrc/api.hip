@@ -49,6 +49,7 @@ Layout carve(void *ws, int64_t N, int64_t E, int32_t precision, bool with_prep) 
   L.bpart = (double *)c.take(4 * sizeof(double) * (size_t)kMaxGrid);
   const int64_t slots = max_slots(N, E);
   L.hpart = (double *)c.take(sizeof(double) * (size_t)slots);
+  L.snap = (SnapTable *)c.take(sizeof(SnapTable));
   L.y64[0] = (double *)c.take(sizeof(double) * (size_t)N);
   L.y64[1] = (double *)c.take(sizeof(double) * (size_t)N);
   if (precision == PR_MIXED || precision == PR_FP32) {
@@ -326,7 +327,10 @@ ChunkSpec update_chunk(pr_ctx *ctx, bool fp32, unsigned grid, const IterParams &
     IterParams r = p;
     r.y_in = (k & 1) ? b1 : b0;
     r.y_out = (k & 1) ? b0 : b1;
-    return launch_update(s, fp32, grid, r);
+    r.node = k;
+    const hipError_t e = launch_update(s, fp32, grid, r);
+    if (e != hipSuccess || !r.snap) return e;
+    return launch_snap(s, fp32, r);
   };
   return c;
 }

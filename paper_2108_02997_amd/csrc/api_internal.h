@@ -41,6 +41,7 @@ hipError_t launch_adam(hipStream_t s, float *W, const float *g, float *m, float 
                        float beta2, float eps, int32_t step);
 hipError_t launch_start_vector(hipStream_t s, const float *feat, const float *y, int64_t N, double *r0, double *part);
 hipError_t launch_output(hipStream_t s, bool fp32, const int32_t *outdeg, const void *y, int32_t N, double *ranks);
+hipError_t launch_snap(hipStream_t s, bool fp32, const IterParams &p);
 hipError_t launch_validate(hipStream_t s, const int32_t *off, const int32_t *idx, const int32_t *outdeg, int32_t N,
                            int32_t E, uint32_t *cnt, int32_t *flags, int32_t *host_flags);
 
@@ -158,6 +159,7 @@ struct Layout {
   SolveState *st;
   double *bpart;
   double *hpart;
+  SnapTable *snap;
   double *y64[2];
   float *y32[2];
   void *prep;
@@ -203,10 +205,18 @@ void load_tune_file(pr_ctx *ctx);
 void save_tune_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, int32_t mid, int32_t grid, int32_t mid_b,
                      int32_t grid_b);
 void save_tune_seg_entry(pr_ctx *ctx, const std::vector<int64_t> &sig, const SegTune &t);
+// The rank snapshots a pr_pull_snapshots call asks for (tau, norm and iter: host; out: device).
+struct SnapRequest {
+  int32_t S;
+  const double *tau;
+  const int32_t *norm;
+  double *out;
+  int32_t *iter;
+};
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
-               size_t workspace_bytes, pr_result *out);
+               size_t workspace_bytes, pr_result *out, const SnapRequest *snaps = nullptr);
 // The library's fixed device scratch (api_noalloc.hip): its address on `device`, resolved once
 // per device; PR_OK or PR_EDEVICE.
 int scratch_setup(int device);

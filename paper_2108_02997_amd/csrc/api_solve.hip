@@ -1,6 +1,7 @@
 // api_solve.hip -- the C ABI of the single and K-column solves: pr_pull (float64, mixed, float32
-// phases) and pr_pull_batch (column compaction between chunks, float32 -> float64 hand-over),
-// and the L1 distance of two rank vectors.
+// phases), pr_pull_snapshots (pr_pull with rank snapshots at given (tau, norm) pairs) and
+// pr_pull_batch (column compaction between chunks, float32 -> float64 hand-over), and the L1
+// distance of two rank vectors.
 #include <string.h>
 
 #include <algorithm>
@@ -25,6 +26,21 @@ int pr_pull(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t 
   }
   return pull_solve(ctx, stream, in_offsets, in_indices, outdeg, N, E, prep, alpha, tau, norm, max_iter, precision,
                     init, ranks, norm_trace, workspace, workspace_bytes, out);
+}
+
+int pr_pull_snapshots(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices,
+                      const int32_t *outdeg, int64_t N, int64_t E, const void *prep, double alpha, double tau,
+                      int32_t norm, int32_t max_iter, int32_t precision, const double *init, double *ranks,
+                      double *norm_trace, int32_t S, const double *snap_tau, const int32_t *snap_norm,
+                      double *snaps, int32_t *snap_iter, void *workspace, size_t workspace_bytes, pr_result *out) {
+  if (!ctx || !in_offsets || !outdeg || !ranks || !workspace || !out || (E > 0 && !in_indices) || !snap_tau ||
+      !snap_norm || !snaps || !snap_iter) {
+    set_error("pr_pull_snapshots: NULL argument");
+    return PR_EINVAL;
+  }
+  const SnapRequest r{S, snap_tau, snap_norm, snaps, snap_iter};
+  return pull_solve(ctx, stream, in_offsets, in_indices, outdeg, N, E, prep, alpha, tau, norm, max_iter, precision,
+                    init, ranks, norm_trace, workspace, workspace_bytes, out, &r);
 }
 
 }  // extern "C"
@@ -66,7 +82,7 @@ static void set_segmented(const pr_ctx *ctx, const PrepHeader &h, const void *pp
 int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32_t *in_indices, const int32_t *outdeg,
                int64_t N, int64_t E, const void *prep, double alpha, double tau, int32_t norm, int32_t max_iter,
                int32_t precision, const double *init, double *ranks, double *norm_trace, void *workspace,
-               size_t workspace_bytes, pr_result *out) {
+               size_t workspace_bytes, pr_result *out, const SnapRequest *snaps) {
   if (bad_graph_sizes(N, E)) return PR_EINVAL;
   if (!(alpha >= 0.0 && alpha <= 1.0)) {
     set_error("alpha must be in [0, 1], got %g", alpha);
@@ -87,6 +103,21 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   if (precision != PR_FP64 && precision != PR_MIXED && precision != PR_FP32) {
     set_error("precision must be PR_FP64, PR_MIXED or PR_FP32, got %d", precision);
     return PR_EINVAL;
+  }
+  if (snaps) {
+    if (precision == PR_MIXED) {
+      set_error("pr_pull_snapshots: precision must be PR_FP64 or PR_FP32 (a mixed solve changes phase)");
+      return PR_EINVAL;
+    }
+    if (snaps->S < 1 || snaps->S > kMaxSnaps) {
+      set_error("pr_pull_snapshots: S must be in [1, %d], got %d", kMaxSnaps, snaps->S);
+      return PR_EINVAL;
+    }
+    for (int i = 0; i < snaps->S; ++i)
+      if (!(snaps->tau[i] >= 0.0) || snaps->norm[i] < PR_L1 || snaps->norm[i] > PR_LINF) {
+        set_error("pr_pull_snapshots: snapshot %d needs tau >= 0 and norm PR_L1, PR_L2 or PR_LINF", i);
+        return PR_EINVAL;
+      }
   }
   const Layout L = carve(workspace, N, E, precision, prep == nullptr);
   if (workspace_bytes < L.total) {
@@ -135,6 +166,19 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   p.grid = (int32_t)grid;
   p.trace = norm_trace;
   p.mid_deg = ts.first;
+  if (snaps) {
+    SnapTable t{};
+    for (int i = 0; i < snaps->S; ++i) {
+      t.tau[i] = snaps->tau[i];
+      t.norm[i] = snaps->norm[i];
+    }
+    t.S = snaps->S;
+    t.out = snaps->out;
+    t.node = -1;
+    PR_HIP(hipMemcpyAsync(L.snap, &t, sizeof t, hipMemcpyHostToDevice, s));
+    PR_HIP(hipStreamSynchronize(s));  // t is this frame's
+    p.snap = L.snap;
+  }
 
   int fp32_iters = 0, fbuf = 0;
   const void *final_y = nullptr;
@@ -174,6 +218,7 @@ int pull_solve(pr_ctx *ctx, void *stream, const int32_t *in_offsets, const int32
   }
   PR_HIP(launch_output(s, final_fp32, outdeg, final_y, (int32_t)N, ranks));
   PR_HIP(hipMemcpyAsync(ctx->hstate, L.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+  if (snaps) PR_HIP(hipMemcpyAsync(snaps->iter, L.snap->iter, sizeof(int32_t) * snaps->S, hipMemcpyDeviceToHost, s));
   PR_HIP(hipStreamSynchronize(s));
   const SolveState &hs = *ctx->hstate;
   out->iterations = hs.head.iter;

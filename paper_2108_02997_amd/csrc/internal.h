@@ -169,6 +169,23 @@ struct SweepCols {
   int32_t remaining;
 };
 
+// Rank snapshots of a single-vector solve (the outputs row of section 3's tolerance study): the
+// ranks at the first update whose change meets tau[i] in norm[i] -- the iterate a solve with that
+// (tau, norm) would return -- are copied to out[i * N ..] as the solve runs, so one solve serves
+// every (tau, norm) pair.  finalize marks the snapshots an update takes (pending, that update's
+// output and its position in the chunk); k_snap, launched after it, copies them.
+constexpr int kMaxSnaps = 64;
+struct SnapTable {
+  double tau[kMaxSnaps];
+  int32_t norm[kMaxSnaps];
+  int32_t iter[kMaxSnaps];     // the update snapshot i was taken at (0: not met yet)
+  unsigned long long pending;  // snapshots taken at the last finalized update (bit i)
+  const void *src;             // that update's output (y form, the solve's value type)
+  double *out;                 // S x N ranks
+  int32_t S;
+  int32_t node;                // that update's position in its chunk
+};
+
 // Kernel parameters of one update (passed by value).
 struct IterParams {
   const int32_t *off;
@@ -208,6 +225,11 @@ struct IterParams {
   // Non-null: this is the a = 1 iteration of a power-series sweep; finalize decides every
   // column's stop instead of testing tau.
   SweepCols *sweep;
+  // Non-null: rank snapshots are taken (finalize, k_snap); node is this update's position in its
+  // chunk.
+  SnapTable *snap;
+  int32_t node;
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------- host helpers

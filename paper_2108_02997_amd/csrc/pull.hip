@@ -76,6 +76,22 @@ __device__ __forceinline__ void finalize(const IterParams &p, double l1, double 
     }
     return;
   }
+  if (p.snap) {
+    // rank snapshots (single-phase solves): the same test as the solve's own stop below
+    SnapTable *sn = p.snap;
+    unsigned long long m = 0;
+    for (int i = 0; i < sn->S; ++i) {
+      if (sn->iter[i]) continue;
+      const int ni = sn->norm[i];
+      if ((ni == 1 ? e[0] : ni == 2 ? e[1] : e[2]) < sn->tau[i]) {
+        sn->iter[i] = it;
+        m |= 1ull << i;
+      }
+    }
+    sn->pending = m;
+    sn->src = p.y_out;
+    sn->node = p.node;
+  }
   const bool met = (p.norm == 1 ? e[0] : p.norm == 2 ? e[1] : e[2]) < p.tau;
   if (p.phase == 1) {
     // float32 phase: hand over to float64 once tau is met, the L1 change stops shrinking (in
@@ -279,6 +295,25 @@ __global__ __launch_bounds__(kBlock) void k_output(const int32_t *__restrict__ o
   }
 }
 
+// The rank snapshots the update at chunk position p.node took (finalize): ranks_v as k_output
+// writes them, into every such snapshot.  Runs after every update of a solve with snapshots and
+// copies only after the update that took some (a chunk's updates after the stop do not run
+// finalize, so a later position never matches).
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_snap(IterParams p) {
+  const SnapTable *sn = p.snap;
+  const unsigned long long m = sn->pending;
+  if (m == 0 || sn->node != p.node) return;
+  const VT *__restrict__ y = (const VT *)sn->src;
+  double *__restrict__ out = sn->out;
+  const int64_t N = p.N;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < N; v += (int64_t)gridDim.x * kBlock) {
+    const int32_t dv = p.outdeg[v];
+    const double r = dv > 0 ? (double)y[v] * (double)dv : (double)y[v];
+    for (unsigned long long b = m; b; b &= b - 1) out[(int64_t)(__ffsll((long long)b) - 1) * N + v] = r;
+  }
+}
+
 // Sum of |x_v - y_v|: per-block partials, then one block in block order.
 __global__ __launch_bounds__(kBlock) void k_l1_partial(const double *__restrict__ x, const double *__restrict__ y,
                                                        int64_t N, double *__restrict__ part) {
@@ -354,6 +389,14 @@ hipError_t launch_update(hipStream_t s, bool fp32, unsigned grid, const IterPara
 hipError_t launch_convert(hipStream_t s, const float *y32, double *y64, int32_t N, SolveState *st) {
   hipLaunchKernelGGL(k_convert, dim3(grid_for(N, 2048)), dim3(kBlock), 0, s, y32, y64, N);
   hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_snap(hipStream_t s, bool fp32, const IterParams &p) {
+  if (fp32)
+    hipLaunchKernelGGL(k_snap<float>, dim3(grid_for(p.N, 2048)), dim3(kBlock), 0, s, p);
+  else
+    hipLaunchKernelGGL(k_snap<double>, dim3(grid_for(p.N, 2048)), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
