@@ -123,3 +123,20 @@ def test_argument_errors(pr, ctx):
     b = pr.pull(ctx, dg, alpha=0.85, tau=1e-9, norm=1)
     assert torch.equal(a["ranks"], b["ranks"]) and a["iterations"] == b["iterations"]
     assert np.isfinite(b["ranks"].cpu().numpy()).all()
+
+
+def test_sweep_columns_agree_with_snapshots(pr, ctx):
+    # two independent routes to the same readout: the power-series sweep with one column per
+    # (tau, norm) pair at one alpha (ranks formed from the alpha = 1 iterates) and the snapshots
+    # of one alpha = 0.85 solve (the iterates themselves); equal stops, ranks within 1e-12 in L1
+    g = gg.rmat(13, seed=75)
+    dg = pr.DeviceGraph.from_host(g)
+    pairs = [(t, n) for t in (1e-4, 1e-6, 1e-8) for n in (1, 2, 3)]
+    snap = pr.pull_snapshots(ctx, dg, pairs, alpha=0.85, tau=1e-10, norm=1, max_iter=500)
+    cols = pr.pull_sweep(ctx, dg, [dict(alpha=0.85, tau=t, norm=n, max_iter=500) for t, n in pairs])
+    for i, c in enumerate(cols):
+        # the two decide a stop from the same change computed along different routes: a tie may
+        # move it by one update
+        assert abs(c["iterations"] - snap["snap_iter"][i]) <= 1, (pairs[i], c["iterations"], snap["snap_iter"][i])
+        if c["iterations"] == snap["snap_iter"][i]:
+            assert pr.l1_distance(ctx, c["ranks"], snap["snapshots"][i].contiguous()) <= 1e-12, pairs[i]
