@@ -140,3 +140,23 @@ def test_sweep_columns_agree_with_snapshots(pr, ctx):
         assert abs(c["iterations"] - snap["snap_iter"][i]) <= 1, (pairs[i], c["iterations"], snap["snap_iter"][i])
         if c["iterations"] == snap["snap_iter"][i]:
             assert pr.l1_distance(ctx, c["ranks"], snap["snapshots"][i].contiguous()) <= 1e-12, pairs[i]
+
+
+def test_given_start_and_edgeless(pr, ctx):
+    # from a given start vector the snapshots are the separate solves from that start
+    g = gg.rmat(12, seed=76)
+    dg = pr.DeviceGraph.from_host(g)
+    init = torch.rand(g.N, dtype=torch.float64, device="cuda")
+    init /= init.sum()
+    pairs = [(1e-5, 1), (1e-7, 3)]
+    res = pr.pull_snapshots(ctx, dg, pairs, alpha=0.9, tau=1e-10, norm=1, init=init)
+    for i, (t, n) in enumerate(pairs):
+        one = pr.pull(ctx, dg, alpha=0.9, tau=t, norm=n, init=init)
+        assert res["snap_iter"][i] == one["iterations"] and torch.equal(res["snapshots"][i], one["ranks"])
+    # no edges: every vertex dangling, the uniform start is the fixed point, the first update
+    # changes nothing and takes every snapshot
+    e = gg.edgeless(7)
+    de = pr.DeviceGraph.from_host(e)
+    res = pr.pull_snapshots(ctx, de, [(1e-3, 1), (0.5, 3)], alpha=0.85, tau=1e-12, norm=1)
+    assert res["iterations"] == 1 and res["snap_iter"] == [1, 1]
+    np.testing.assert_allclose(res["snapshots"].cpu().numpy(), np.full((2, 7), 1 / 7), rtol=1e-15)
